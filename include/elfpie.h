@@ -1,0 +1,195 @@
+/*
+ * elfpie.h - C ABI of the MI355X (gfx950) Elfpie reconstruction library.
+ *
+ * Elfpie (Zhang, Berendschot, Zhou, arXiv 2209.14671) reconstructs the
+ * high-resolution spectrum Psi of a sample, and the pupil P of the objective,
+ * from a Fourier-ptychographic stack of K low-resolution intensity images
+ * (Sec. 3, Algorithm 1).  One iteration, for all K LEDs at once:
+ *   - crops each LED's window of Psi and applies the pupil, inverse-transforms
+ *     it to a low-resolution field (Sec. 3.1, Eq. 1, M = 1 LED per image);
+ *   - evaluates the L1 data fidelity on image gradients (Eq. 4 or Eq. 5 with
+ *     the normaliser of Eq. 12) and the Hessian penalties on the amplitude and
+ *     phase of O = F_A Psi (Eq. 6, 7, combined by Eq. 8);
+ *   - forms the closed-form Wirtinger gradients wrt conj(Psi) (Eq. 9-15) and
+ *     conj(P) (Eq. 18);
+ *   - applies the modified AdaBelief update (Eq. 19) to Psi and, optionally,
+ *     to P after a 3x3 Gaussian pre-filter (note under Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays are dense, row-major (row = y, column = x), complex values stored
+ * interleaved (re, im), in the precision of the plan: ELFPIE_F32 -> float /
+ * complex64, ELFPIE_F64 -> double / complex128.  The AdaBelief second moments
+ * v are always double.  Every array pointer is a DEVICE pointer allocated by
+ * the caller, aligned to 16 bytes, unless stated "host".  The library never
+ * allocates device memory: its workspace is handed in at plan creation and is
+ * owned by the caller, who must keep it alive until elfpie_plan_destroy.
+ *
+ * Transforms are centred and unitary: Psi = fftshift(fft2(O)) / n_hi, so the
+ * DC term sits at [n_hi/2, n_hi/2]; the low-resolution field of LED k is
+ * o_k = (n_lo / r) * ifft2(ifftshift(P * crop_k(Psi))), r = n_hi / n_lo.
+ * LED k's window is centred at n_hi/2 + round(k * FOV) (round half away from
+ * zero; k = (kx, ky) in cycles per micrometre, FOV = n_lo * dx_lo).  The pupil
+ * support is the disc |u - n_lo/2|^2 <= R^2 (1 + 1e-12), R = NA * FOV / lambda.
+ *
+ * Streams and errors: every call enqueues its work on `stream` (a hipStream_t;
+ * NULL = the default stream) and returns without waiting, except where noted.
+ * Argument errors are detected before anything is enqueued and are returned
+ * synchronously; the reason is available from elfpie_last_error.  HIP runtime
+ * failures return ELFPIE_E_DEVICE.  A plan is not thread-safe; distinct plans
+ * are independent.  Results are bitwise reproducible for a given plan and
+ * device: no floating-point atomics are used.
+ */
+#ifndef ELFPIE_H
+#define ELFPIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ELFPIE_OK = 0,
+  ELFPIE_E_INVALID = 1,      /* NULL or misaligned pointer, bad value              */
+  ELFPIE_E_RANGE = 2,        /* an LED window falls outside the spectrum           */
+  ELFPIE_E_UNSUPPORTED = 3,  /* size / precision combination not implemented      */
+  ELFPIE_E_WORKSPACE = 4,    /* workspace smaller than elfpie_workspace_bytes      */
+  ELFPIE_E_DEVICE = 5,       /* HIP runtime error                                  */
+  ELFPIE_E_NONFINITE = 6     /* a checked run produced a NaN / Inf loss            */
+} elfpie_status;
+
+enum { ELFPIE_FID_AMPLITUDE = 0, ELFPIE_FID_INTENSITY = 1 }; /* Eq. 4 / Eq. 5 */
+enum { ELFPIE_NORM_ANISO = 0, ELFPIE_NORM_ISO = 1 };          /* Eq. 12        */
+enum { ELFPIE_F64 = 0, ELFPIE_F32 = 1 };                      /* arithmetic    */
+enum {
+  ELFPIE_LEARN_PUPIL = 1u,    /* update P with Eq. 19 after each Psi update          */
+  ELFPIE_PUPIL_SUPPORT = 2u,  /* P is confined to the NA disc (forward uses P * 1_S) */
+  ELFPIE_PUPIL_FILTER = 4u    /* 3x3 Gaussian (sigma 1 px) pre-filter before P update */
+};
+
+/* Problem statement: Algorithm 1's inputs and the optics of Sec. 4.1. */
+typedef struct {
+  int32_t n_lo;            /* low-res image side; power of two, 32..128 (F32), 32..64 (F64) */
+  int32_t upsample;        /* r = n_hi / n_lo; n_hi must be a power of two, 128..1024       */
+  int32_t K;               /* number of LEDs (images), >= 1                                 */
+  double wavelength_um;    /* illumination wavelength, > 0                                  */
+  double na;               /* objective numerical aperture, > 0                             */
+  double dx_lo_um;         /* sample-plane pixel = camera pixel / magnification, > 0         */
+  const double *led_k;     /* HOST, K x 2, (kx, ky) = sin(theta) / lambda in 1/um; copied   */
+  double alpha, beta;      /* Eq. 8 penalty weights, >= 0                                   */
+  double lr;               /* Eq. 19 initial step: delta^0 = lr^2, > 0                      */
+  double gamma1, gamma2;   /* Eq. 19 decay rates, in [0, 1)                                 */
+  double eta_opt;          /* Eq. 19 stabiliser, >= 0                                       */
+  double eta_h;            /* Eq. 14 stabiliser, >= 0                                       */
+  double l1_eps;           /* L1 smoothing: rho(x) = sqrt(x^2 + eps^2) - eps; 0 = exact |x| */
+  int32_t fidelity;        /* ELFPIE_FID_*                                                  */
+  int32_t norm;            /* ELFPIE_NORM_* (fidelity and Hessian terms)                    */
+  int32_t precision;       /* ELFPIE_F32 or ELFPIE_F64                                      */
+  uint32_t flags;          /* ELFPIE_LEARN_PUPIL | ELFPIE_PUPIL_SUPPORT | ELFPIE_PUPIL_FILTER */
+} elfpie_problem;
+
+/* Optimiser state (Eq. 19), all DEVICE pointers owned by the caller.
+ * psi, mu_psi: n_hi x n_hi complex; v_psi: n_hi x n_hi double; delta_psi:
+ * n_hi x n_hi real.  P, mu_P: n_lo x n_lo complex; v_P: double; delta_P: real.
+ * t: one int64, the number of updates done (t = 0 before the first update;
+ * the bias corrections of Eq. 19 use t + 1).  A fresh state has mu = v = 0,
+ * delta = lr^2, t = 0.  The state is the whole checkpoint: saving these
+ * arrays and restoring them continues a run bit-for-bit. */
+typedef struct {
+  void *psi, *P;
+  void *mu_psi;
+  double *v_psi;
+  void *delta_psi;
+  void *mu_P;
+  double *v_P;
+  void *delta_P;
+  int64_t *t;
+} elfpie_state;
+
+typedef struct elfpie_plan elfpie_plan;
+
+/* Fill `p` with the defaults of Eq. 19 and Sec. 4.1: alpha = beta = 1e-3,
+ * lr = 1e-2, gamma1 = 0.9, gamma2 = 0.999, eta_opt = 1e-8, eta_h = 1e-6,
+ * l1_eps = 0, intensity fidelity, anisotropic norm, F32, PUPIL_SUPPORT.
+ * Geometry fields are zeroed. */
+elfpie_status elfpie_problem_defaults(elfpie_problem *p);
+
+/* Bytes of device workspace a plan for `p` needs (host query, no device work).
+ * Fails with the same status elfpie_plan_create would return for `p`. */
+elfpie_status elfpie_workspace_bytes(const elfpie_problem *p, size_t *bytes);
+
+/* Validate `p`, compute the LED windows and pupil support (Sec. 3.1, M_k and P),
+ * and copy the plan tables into the caller's workspace `d_ws` (device, at least
+ * elfpie_workspace_bytes bytes, 256-byte aligned).  Synchronous.  The plan keeps
+ * `d_ws` until destroyed.  Errors: E_INVALID (bad pointer or value), E_RANGE
+ * (window outside the spectrum), E_UNSUPPORTED (size or precision), E_WORKSPACE. */
+elfpie_status elfpie_plan_create(const elfpie_problem *p, void *d_ws, size_t ws_bytes,
+                                 elfpie_plan **out);
+elfpie_status elfpie_plan_destroy(elfpie_plan *plan);
+
+/* Plan facts for callers sizing their buffers: out[0] = n_hi, out[1] = support
+ * pixel count S, out[2] = K, out[3] = n_lo, out[4] = index of the LED nearest
+ * the optical axis. `out` is HOST, 5 int32. */
+elfpie_status elfpie_plan_info(const elfpie_plan *plan, int32_t *out);
+
+/* Forward model, Eq. (1) with M = 1: for every LED, o_k = F_B P M_k Psi.
+ * psi: n_hi^2 complex; P: n_lo^2 complex.  Optional outputs (NULL to skip):
+ * fields: K x n_lo x n_lo complex o_k; intens: K x n_lo x n_lo real |o_k|^2.
+ * If meas (K x n_lo x n_lo real) and d_loss4 (4 doubles) are both given, writes
+ * [L_fid, L_A, L_Phi, L_fid + alpha L_A + beta L_Phi] (Eq. 4/5, 6, 7, 8). */
+elfpie_status elfpie_forward(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
+                             void *fields, void *intens, double *d_loss4, void *stream);
+
+/* Loss (Eq. 8) and its gradients at (psi, P): g_psi = dL/d(conj Psi) (Eq. 15,
+ * n_hi^2 complex), g_P = dL_fid/d(conj P) (Eq. 18, n_lo^2 complex, zero off the
+ * support with ELFPIE_PUPIL_SUPPORT).  g_P or d_loss4 may be NULL.  The per-LED
+ * low-resolution fields are recomputed, not stored. */
+elfpie_status elfpie_grad(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
+                          void *g_psi, void *g_P, double *d_loss4, void *stream);
+
+/* One iteration of Algorithm 1 on `state`: gradients at (psi, P), Eq. 19 update
+ * of psi, then (ELFPIE_LEARN_PUPIL) pre-filter and Eq. 19 update of P, then t += 1.
+ * d_loss4 (optional, device) receives the loss terms at the pre-update state. */
+elfpie_status elfpie_step(elfpie_plan *plan, const elfpie_state *state, const void *meas,
+                          double *d_loss4, void *stream);
+
+/* n_iter iterations (elfpie_step repeated), replayed from a HIP graph captured
+ * on first use for these pointers.  d_loss_hist (optional, device, n_iter x 4
+ * doubles) receives each iteration's loss terms.  checked = 1 waits for the
+ * stream at the end and returns ELFPIE_E_NONFINITE if any loss was NaN / Inf;
+ * checked = 0 returns at once. */
+elfpie_status elfpie_run(elfpie_plan *plan, const elfpie_state *state, const void *meas,
+                         int32_t n_iter, double *d_loss_hist, int32_t checked, void *stream);
+
+/* O = F_A Psi (Algorithm 1's output; centred unitary inverse transform), and its
+ * inverse Psi = F_A^{-1} O.  n_hi^2 complex each; in-place is not allowed. */
+elfpie_status elfpie_object_from_spectrum(elfpie_plan *plan, const void *psi, void *obj, void *stream);
+elfpie_status elfpie_spectrum_from_object(elfpie_plan *plan, const void *obj, void *psi, void *stream);
+
+/* Initial state: psi = the on-axis LED's window filled, on the pupil support,
+ * with (r / n_lo) fftshift(fft2(sqrt(I_c))); zero elsewhere; P = 1 on the
+ * support (everywhere without ELFPIE_PUPIL_SUPPORT); mu = v = 0; delta = lr^2;
+ * t = 0.  meas: K x n_lo x n_lo real. */
+elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpie_state *state,
+                                void *stream);
+
+/* Timing of the iteration's kernels in isolation: each stage is launched
+ * n_rep times back to back on `stream` between two HIP events, on the state's
+ * current arrays (the state is left unchanged), and ms_out (HOST, 8 floats)
+ * receives the mean milliseconds per launch: [0] per-LED kernel, [1] object
+ * inverse FFT, [2] Hessian kernel, [3] object forward FFT, [4] spectrum gather
+ * + update kernel (gradient mode), [5] pupil kernels, [6] loss kernel,
+ * [7] unused.  Synchronous. */
+elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, const void *meas,
+                                  int32_t n_rep, float *ms_out, void *stream);
+
+/* Text of the last error on `plan` (or of the last plan-less call when plan is NULL). */
+const char *elfpie_last_error(const elfpie_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELFPIE_H */

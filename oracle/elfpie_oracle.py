@@ -463,11 +463,12 @@ def new_state(psi0: np.ndarray, P0: np.ndarray, prob: Problem) -> State:
 
 def init_state(meas: np.ndarray, prob: Problem) -> State:
     """Initial guess: the on-axis-most LED's window holds the unitary-scaled spectrum of
-    sqrt(I) on the pupil support, zeros elsewhere; P0 = 1 on the support."""
+    sqrt(I) on the pupil support (the whole window without the support flag), zeros
+    elsewhere; P0 = 1 there."""
     org = window_origins(prob)
     kc = int(np.argmin(np.sum(prob.led_k ** 2, axis=1)))
     n = prob.n_lo
-    S = pupil_support(prob)
+    S = pupil_support(prob) if prob.flags & PUPIL_SUPPORT else np.ones((n, n), dtype=bool)
     spec = (prob.upsample / n) * np.fft.fftshift(np.fft.fft2(np.sqrt(np.clip(meas[kc], 0, None))))
     psi0 = np.zeros((prob.n_hi, prob.n_hi), dtype=np.complex128)
     psi0[org[kc][0]:org[kc][0] + n, org[kc][1]:org[kc][1] + n] = spec * S

@@ -1,0 +1,915 @@
+// Host side of the Elfpie library: plan construction (LED windows, pupil support,
+// coverage lists), workspace carving, the launch sequence of one iteration
+// (Algorithm 1 of arXiv 2209.14671) with its two independent branches on two
+// streams, HIP-graph replay for multi-iteration runs, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "elfpie.h"
+#include "kernels.hpp"
+
+using namespace elfpie;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Everything the host derives from the problem statement before touching the device.
+struct Tables {
+  int n_lo = 0, n_hi = 0, K = 0, S = 0, prec = 0;
+  int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
+  int kc = 0;                      // LED nearest the optical axis
+  int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
+  int nch = 0, chunk = 16;         // pupil reduction chunks
+  std::vector<int> win;            // K x 2 (y0, x0)
+  std::vector<int> xlo, xhi, rowoff;
+  std::vector<int> tile_ptr, tile_led;
+  size_t elem = 0;                 // bytes of one real in the plan precision
+  // workspace offsets
+  size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
+  size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
+  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0;
+  size_t total = 0;
+};
+
+double round_half_away(double v) { return v < 0 ? -std::floor(-v + 0.5) : std::floor(v + 0.5); }
+
+elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err) {
+  auto fail = [&](elfpie_status s, const std::string& m) {
+    *err = m;
+    return s;
+  };
+  if (!p) return fail(ELFPIE_E_INVALID, "problem is NULL");
+  if (p->precision != ELFPIE_F32 && p->precision != ELFPIE_F64)
+    return fail(ELFPIE_E_UNSUPPORTED, "precision must be ELFPIE_F32 or ELFPIE_F64");
+  if (p->K < 1) return fail(ELFPIE_E_INVALID, "K must be >= 1");
+  if (!p->led_k) return fail(ELFPIE_E_INVALID, "led_k is NULL");
+  if (p->n_lo < 2 || p->upsample < 1) return fail(ELFPIE_E_INVALID, "n_lo must be >= 2 and upsample >= 1");
+  const bool f32 = p->precision == ELFPIE_F32;
+  if (!is_pow2(p->n_lo) || p->n_lo < 32 || p->n_lo > (f32 ? 128 : 64))
+    return fail(ELFPIE_E_UNSUPPORTED, f32 ? "n_lo must be 32, 64 or 128 in F32" : "n_lo must be 32 or 64 in F64");
+  const long long nh = (long long)p->n_lo * p->upsample;
+  if (!is_pow2((int)std::min<long long>(nh, 1 << 30)) || nh < 128 || nh > 1024)
+    return fail(ELFPIE_E_UNSUPPORTED, "n_hi = n_lo * upsample must be 128, 256, 512 or 1024");
+  auto finite_pos = [](double v) { return std::isfinite(v) && v > 0; };
+  if (!finite_pos(p->wavelength_um) || !finite_pos(p->na) || !finite_pos(p->dx_lo_um))
+    return fail(ELFPIE_E_INVALID, "wavelength, NA and pixel size must be finite and > 0");
+  if (!(p->alpha >= 0) || !(p->beta >= 0) || !std::isfinite(p->alpha) || !std::isfinite(p->beta))
+    return fail(ELFPIE_E_INVALID, "alpha and beta must be finite and >= 0");
+  if (!finite_pos(p->lr)) return fail(ELFPIE_E_INVALID, "lr must be finite and > 0");
+  if (!(p->gamma1 >= 0 && p->gamma1 < 1) || !(p->gamma2 >= 0 && p->gamma2 < 1))
+    return fail(ELFPIE_E_INVALID, "gamma1 and gamma2 must lie in [0, 1)");
+  if (!(p->eta_opt >= 0) || !(p->eta_h >= 0) || !(p->l1_eps >= 0) || !std::isfinite(p->eta_opt) ||
+      !std::isfinite(p->eta_h) || !std::isfinite(p->l1_eps))
+    return fail(ELFPIE_E_INVALID, "eta_opt, eta_h and l1_eps must be finite and >= 0");
+  if (p->fidelity != ELFPIE_FID_AMPLITUDE && p->fidelity != ELFPIE_FID_INTENSITY)
+    return fail(ELFPIE_E_INVALID, "fidelity must be ELFPIE_FID_AMPLITUDE or ELFPIE_FID_INTENSITY");
+  if (p->norm != ELFPIE_NORM_ANISO && p->norm != ELFPIE_NORM_ISO)
+    return fail(ELFPIE_E_INVALID, "norm must be ELFPIE_NORM_ANISO or ELFPIE_NORM_ISO");
+  if (p->flags & ~7u) return fail(ELFPIE_E_INVALID, "unknown flag bits");
+
+  tb->n_lo = p->n_lo;
+  tb->n_hi = (int)nh;
+  tb->K = p->K;
+  tb->prec = p->precision;
+  tb->elem = f32 ? 4 : 8;
+  const int n = tb->n_lo;
+  const double fov = n * p->dx_lo_um;
+  const double R = p->na * fov / p->wavelength_um;
+
+  // pupil support: row runs of the disc (or full rows without the support flag)
+  tb->xlo.assign(n, 0);
+  tb->xhi.assign(n, -1);
+  tb->rowoff.assign(n, 0);
+  int S = 0;
+  for (int y = 0; y < n; ++y) {
+    int lo = n, hi = -1;
+    for (int x = 0; x < n; ++x) {
+      const double dy = y - n / 2, dx = x - n / 2;
+      const bool in = (p->flags & ELFPIE_PUPIL_SUPPORT) ? (dx * dx + dy * dy <= R * R * (1.0 + 1e-12)) : true;
+      if (in) {
+        lo = std::min(lo, x);
+        hi = std::max(hi, x);
+      }
+    }
+    if (hi < lo) lo = 0, hi = -1;
+    tb->xlo[y] = lo;
+    tb->xhi[y] = hi;
+    tb->rowoff[y] = S;
+    S += hi - lo + 1;
+    if (hi >= lo) {
+      if (tb->y_max < 0) tb->y_min = y;
+      tb->y_max = y;
+      if (tb->x_max < 0 || lo < tb->x_min) tb->x_min = lo;
+      tb->x_max = std::max(tb->x_max, hi);
+    }
+  }
+  if (S == 0) return fail(ELFPIE_E_INVALID, "the pupil support is empty (NA * FOV / lambda too small)");
+  tb->S = S;
+
+  // LED windows
+  tb->win.resize(2 * (size_t)tb->K);
+  double best = 1e300;
+  for (int k = 0; k < tb->K; ++k) {
+    const double kx = p->led_k[2 * k], ky = p->led_k[2 * k + 1];
+    if (!std::isfinite(kx) || !std::isfinite(ky)) return fail(ELFPIE_E_INVALID, "led_k holds a non-finite value");
+    const double ox = round_half_away(kx * fov), oy = round_half_away(ky * fov);
+    const double y0 = tb->n_hi / 2 - n / 2 + oy, x0 = tb->n_hi / 2 - n / 2 + ox;
+    if (y0 < 0 || x0 < 0 || y0 + n > tb->n_hi || x0 + n > tb->n_hi) {
+      char m[160];
+      std::snprintf(m, sizeof m, "LED %d window (%.0f, %.0f) falls outside the %d x %d spectrum", k, y0, x0,
+                    tb->n_hi, tb->n_hi);
+      return fail(ELFPIE_E_RANGE, m);
+    }
+    tb->win[2 * k] = (int)y0;
+    tb->win[2 * k + 1] = (int)x0;
+    const double d2 = kx * kx + ky * ky;
+    if (d2 < best) {
+      best = d2;
+      tb->kc = k;
+    }
+  }
+
+  // coverage lists: 16 x 16 tiles of the spectrum -> LEDs whose support box meets them
+  tb->ntiles_x = tb->n_hi / 16;
+  const int ntiles = tb->ntiles_x * tb->ntiles_x;
+  std::vector<std::vector<int>> lists(ntiles);
+  for (int k = 0; k < tb->K; ++k) {
+    const int ya = tb->win[2 * k] + tb->y_min, yb = tb->win[2 * k] + tb->y_max;
+    const int xa = tb->win[2 * k + 1] + tb->x_min, xb = tb->win[2 * k + 1] + tb->x_max;
+    for (int ty = ya / 16; ty <= yb / 16; ++ty)
+      for (int tx = xa / 16; tx <= xb / 16; ++tx) lists[ty * tb->ntiles_x + tx].push_back(k);
+  }
+  tb->tile_ptr.assign(ntiles + 1, 0);
+  tb->tile_led.clear();
+  for (int t = 0; t < ntiles; ++t) {
+    tb->tile_ptr[t] = (int)tb->tile_led.size();
+    tb->tile_led.insert(tb->tile_led.end(), lists[t].begin(), lists[t].end());
+  }
+  tb->tile_ptr[ntiles] = (int)tb->tile_led.size();
+  if (tb->tile_led.empty()) tb->tile_led.push_back(0);
+  tb->nch = (tb->K + tb->chunk - 1) / tb->chunk;
+
+  // workspace layout
+  const size_t cxb = 2 * tb->elem;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  tb->o_win = take(tb->win.size() * sizeof(int));
+  tb->o_xlo = take(n * sizeof(int));
+  tb->o_xhi = take(n * sizeof(int));
+  tb->o_roff = take(n * sizeof(int));
+  tb->o_tptr = take(tb->tile_ptr.size() * sizeof(int));
+  tb->o_tled = take(tb->tile_led.size() * sizeof(int));
+  tb->o_twlo = take(n * cxb);
+  tb->o_twhi = take(tb->n_hi * cxb);
+  const size_t A = (size_t)tb->n_hi * tb->n_hi;
+  tb->o_C = take((size_t)tb->K * S * cxb);
+  tb->o_D = take((size_t)tb->K * S * cxb);
+  tb->o_T1 = take(A * cxb);
+  tb->o_T2 = take(A * cxb);
+  tb->o_G = take(A * cxb);
+  tb->o_gP = take((size_t)n * n * cxb);
+  tb->o_part = take((size_t)tb->nch * S * cxb);
+  tb->o_Pf = take((size_t)n * n * cxb);
+  tb->o_fid = take(tb->K * sizeof(double));
+  tb->o_hess = take((size_t)2 * ntiles * sizeof(double));
+  tb->o_loss = take(4 * sizeof(double));
+  tb->o_ctr = take(sizeof(int));
+  tb->o_flag = take(sizeof(int));
+  tb->total = off;
+  return ELFPIE_OK;
+}
+
+}  // namespace
+
+struct elfpie_plan {
+  elfpie_problem prob{};
+  Tables tb;
+  char* ws = nullptr;
+  int device = 0;
+  hipStream_t cap = nullptr, side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  elfpie_state gkey{};
+  const void* gkey_meas = nullptr;
+  const double* gkey_hist = nullptr;
+  std::string err;
+
+  template <class X> X* at(size_t o) const { return reinterpret_cast<X*>(ws + o); }
+};
+
+namespace {
+
+elfpie_status set_err(elfpie_plan* pl, elfpie_status s, const std::string& m) {
+  if (pl) pl->err = m;
+  g_last_error = m;
+  return s;
+}
+
+elfpie_status hip_check(elfpie_plan* pl, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ELFPIE_OK;
+  return set_err(pl, ELFPIE_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(pl, expr)                                          \
+  do {                                                             \
+    elfpie_status s_ = hip_check((pl), (expr), #expr);            \
+    if (s_ != ELFPIE_OK) return s_;                                \
+  } while (0)
+
+#define LAUNCH_CHECK(pl, name)                                     \
+  do {                                                             \
+    elfpie_status s_ = hip_check((pl), hipGetLastError(), name);  \
+    if (s_ != ELFPIE_OK) return s_;                                \
+  } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Launch sequence for one precision.
+template <class T>
+struct Ops {
+  using C = cx<T>;
+
+  static elfpie_status led(elfpie_plan* pl, int mode, const void* psi, const void* P, const void* meas,
+                           void* fields, void* intens, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    LedArgs a{};
+    a.psi = psi;
+    a.P = P;
+    a.meas = meas;
+    a.C = pl->at<void>(tb.o_C);
+    a.D = pl->at<void>(tb.o_D);
+    a.fields = fields;
+    a.intens = intens;
+    a.fid_partial = pl->at<double>(tb.o_fid);
+    a.win = pl->at<int>(tb.o_win);
+    a.xlo = pl->at<int>(tb.o_xlo);
+    a.xhi = pl->at<int>(tb.o_xhi);
+    a.rowoff = pl->at<int>(tb.o_roff);
+    a.tw = pl->at<void>(tb.o_twlo);
+    a.n_hi = tb.n_hi;
+    a.S = tb.S;
+    a.y_min = tb.y_min;
+    a.y_max = tb.y_max;
+    a.x_min = tb.x_min;
+    a.x_max = tb.x_max;
+    a.inv_scale = 1.0 / ((double)pl->prob.upsample * tb.n_lo);
+    a.eps = pl->prob.l1_eps;
+    a.mode = mode;
+    a.fidelity = pl->prob.fidelity;
+    a.norm = pl->prob.norm;
+    switch (tb.n_lo) {
+      case 32: k_led<T, 32><<<tb.K, LedShape<32>::NT, 0, s>>>(a); break;
+      case 64: k_led<T, 64><<<tb.K, LedShape<64>::NT, 0, s>>>(a); break;
+      case 128:
+        if constexpr (sizeof(T) == 4) {
+          k_led<T, 128><<<tb.K, LedShape<128>::NT, 0, s>>>(a);
+          break;
+        }
+        [[fallthrough]];
+      default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_lo not supported in this precision");
+    }
+    LAUNCH_CHECK(pl, "k_led");
+    return ELFPIE_OK;
+  }
+
+  template <bool INV, bool COLS>
+  static elfpie_status lines(elfpie_plan* pl, const void* in, void* out, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    const C* tw = pl->at<C>(tb.o_twhi);
+    const C* i = static_cast<const C*>(in);
+    C* o = static_cast<C*>(out);
+    switch (tb.n_hi) {
+      case 128: k_fft_lines<T, 128, INV, COLS><<<128 / BigShape<128>::RPB, BigShape<128>::NT, 0, s>>>(i, o, tw); break;
+      case 256: k_fft_lines<T, 256, INV, COLS><<<256 / BigShape<256>::RPB, BigShape<256>::NT, 0, s>>>(i, o, tw); break;
+      case 512: k_fft_lines<T, 512, INV, COLS><<<512 / BigShape<512>::RPB, BigShape<512>::NT, 0, s>>>(i, o, tw); break;
+      case 1024:
+        k_fft_lines<T, 1024, INV, COLS><<<1024 / BigShape<1024>::RPB, BigShape<1024>::NT, 0, s>>>(i, o, tw);
+        break;
+      default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
+    }
+    LAUNCH_CHECK(pl, "k_fft_lines");
+    return ELFPIE_OK;
+  }
+
+  // out = unnormalised inverse DFT of psi (rows into out, then columns in place)
+  static elfpie_status obj_inverse(elfpie_plan* pl, const void* psi, void* out, hipStream_t s) {
+    elfpie_status st = lines<true, false>(pl, psi, out, s);
+    if (st != ELFPIE_OK) return st;
+    return lines<true, true>(pl, out, out, s);
+  }
+
+  // out = unnormalised forward DFT of in (columns into out, then rows in place)
+  static elfpie_status obj_forward(elfpie_plan* pl, const void* in, void* out, hipStream_t s) {
+    elfpie_status st = lines<false, true>(pl, in, out, s);
+    if (st != ELFPIE_OK) return st;
+    return lines<false, false>(pl, out, out, s);
+  }
+
+  static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    HessArgs a{};
+    a.Ot = Ot;
+    a.Gt = Gt;
+    a.partial = pl->at<double>(tb.o_hess);
+    a.n = tb.n_hi;
+    a.inv_n = 1.0 / tb.n_hi;
+    a.alpha = pl->prob.alpha;
+    a.beta = pl->prob.beta;
+    a.eta_h = pl->prob.eta_h;
+    a.eps = pl->prob.l1_eps;
+    a.norm = pl->prob.norm;
+    a.want_grad = grad ? 1 : 0;
+    dim3 grid(tb.n_hi / 16, tb.n_hi / 16);
+    k_hessian<T><<<grid, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_hessian");
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status psi_update(elfpie_plan* pl, const elfpie_state* st, void* g_out, const void* gH,
+                                  hipStream_t s) {
+    const Tables& tb = pl->tb;
+    UpdArgs a{};
+    if (st) {
+      a.x = st->psi;
+      a.mu = st->mu_psi;
+      a.v = st->v_psi;
+      a.delta = st->delta_psi;
+      a.t = reinterpret_cast<const long long*>(st->t);
+    }
+    a.g_out = g_out;
+    a.gH = gH;
+    a.C = pl->at<void>(tb.o_C);
+    a.win = pl->at<int>(tb.o_win);
+    a.xlo = pl->at<int>(tb.o_xlo);
+    a.xhi = pl->at<int>(tb.o_xhi);
+    a.rowoff = pl->at<int>(tb.o_roff);
+    a.tile_ptr = pl->at<int>(tb.o_tptr);
+    a.tile_led = pl->at<int>(tb.o_tled);
+    a.n_hi = tb.n_hi;
+    a.n_lo = tb.n_lo;
+    a.S = tb.S;
+    a.ntiles_x = tb.ntiles_x;
+    a.g1 = pl->prob.gamma1;
+    a.g2 = pl->prob.gamma2;
+    a.eta = pl->prob.eta_opt;
+    a.step = st ? 1 : 0;
+    k_psi_update<T><<<tb.ntiles_x * tb.ntiles_x, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_psi_update");
+    return ELFPIE_OK;
+  }
+
+  static PupilArgs pupil_args(elfpie_plan* pl, const void* P) {
+    const Tables& tb = pl->tb;
+    PupilArgs a{};
+    a.P = P;
+    a.Pf = pl->at<void>(tb.o_Pf);
+    a.Pf_out = pl->at<void>(tb.o_Pf);
+    a.D = pl->at<void>(tb.o_D);
+    a.part = pl->at<void>(tb.o_part);
+    a.xlo = pl->at<int>(tb.o_xlo);
+    a.xhi = pl->at<int>(tb.o_xhi);
+    a.rowoff = pl->at<int>(tb.o_roff);
+    a.n_lo = tb.n_lo;
+    a.S = tb.S;
+    a.K = tb.K;
+    a.chunk = tb.chunk;
+    a.nch = tb.nch;
+    const double e1 = std::exp(-0.5), e2 = std::exp(-1.0), z = 1.0 + 4.0 * e1 + 4.0 * e2;
+    a.w_c = 1.0 / z;
+    a.w_e = e1 / z;
+    a.w_k = e2 / z;
+    a.g1 = pl->prob.gamma1;
+    a.g2 = pl->prob.gamma2;
+    a.eta = pl->prob.eta_opt;
+    a.filter = (pl->prob.flags & ELFPIE_PUPIL_FILTER) ? 1 : 0;
+    a.support = (pl->prob.flags & ELFPIE_PUPIL_SUPPORT) ? 1 : 0;
+    return a;
+  }
+
+  // partial sums of the pupil contributions (and the pre-filter when stepping)
+  static elfpie_status pupil_reduce(elfpie_plan* pl, const void* P, bool prefilter, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    PupilArgs a = pupil_args(pl, P);
+    dim3 g1((tb.S + 255) / 256, tb.nch);
+    k_pupil_partial<T><<<g1, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_pupil_partial");
+    if (prefilter) {
+      k_pupil_gauss<T><<<(tb.n_lo * tb.n_lo + 255) / 256, 256, 0, s>>>(a);
+      LAUNCH_CHECK(pl, "k_pupil_gauss");
+    }
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status pupil_finish(elfpie_plan* pl, const void* P, const elfpie_state* st, void* g_out,
+                                    hipStream_t s) {
+    const Tables& tb = pl->tb;
+    PupilArgs a = pupil_args(pl, P);
+    a.g_out = g_out;
+    if (st) {
+      a.P_out = st->P;
+      a.mu = st->mu_P;
+      a.v = st->v_P;
+      a.delta = st->delta_P;
+      a.t = reinterpret_cast<const long long*>(st->t);
+      a.step = 1;
+    }
+    k_pupil_update<T><<<(tb.n_lo * tb.n_lo + 255) / 256, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_pupil_update");
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status finalize(elfpie_plan* pl, double* loss4, double* hist, int64_t* t, bool bump,
+                                hipStream_t s) {
+    const Tables& tb = pl->tb;
+    FinArgs a{};
+    a.fid_partial = pl->at<double>(tb.o_fid);
+    a.K = tb.K;
+    a.hess_partial = pl->at<double>(tb.o_hess);
+    a.ntiles = tb.ntiles_x * tb.ntiles_x;
+    a.alpha = pl->prob.alpha;
+    a.beta = pl->prob.beta;
+    a.loss4 = loss4;
+    a.hist = hist;
+    a.ctr = pl->at<int>(tb.o_ctr);
+    a.t = reinterpret_cast<long long*>(t);
+    a.flag = pl->at<int>(tb.o_flag);
+    a.bump_t = bump ? 1 : 0;
+    k_finalize<<<1, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_finalize");
+    return ELFPIE_OK;
+  }
+
+  // One gradient evaluation (st == NULL) or one update step (st != NULL).
+  // The LED branch runs on `s`; the object branch (inverse transform, Hessian,
+  // forward transform) runs concurrently on the plan's side stream.
+  static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
+                                 const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
+                                 hipStream_t s) {
+    const Tables& tb = pl->tb;
+    void* T1 = pl->at<void>(tb.o_T1);
+    void* T2 = pl->at<void>(tb.o_T2);
+    HIP_TRY(pl, hipEventRecord(pl->ev_fork, s));
+    HIP_TRY(pl, hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
+    elfpie_status r;
+    if ((r = obj_inverse(pl, psi, T1, pl->side)) != ELFPIE_OK) return r;
+    if ((r = hessian(pl, true, T1, T2, pl->side)) != ELFPIE_OK) return r;
+    if ((r = obj_forward(pl, T2, T2, pl->side)) != ELFPIE_OK) return r;
+    HIP_TRY(pl, hipEventRecord(pl->ev_join, pl->side));
+    if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s)) != ELFPIE_OK) return r;
+    const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
+    if (learn_p) {
+      const bool pre = st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
+      if ((r = pupil_reduce(pl, P, pre, s)) != ELFPIE_OK) return r;
+    }
+    HIP_TRY(pl, hipStreamWaitEvent(s, pl->ev_join, 0));
+    if ((r = psi_update(pl, st, g_psi, T2, s)) != ELFPIE_OK) return r;
+    if (learn_p) {
+      if ((r = pupil_finish(pl, P, st, g_P, s)) != ELFPIE_OK) return r;
+    }
+    return finalize(pl, loss4, hist, st ? st->t : nullptr, st != nullptr, s);
+  }
+
+  static elfpie_status forward(elfpie_plan* pl, const void* psi, const void* P, const void* meas, void* fields,
+                               void* intens, double* loss4, hipStream_t s) {
+    const bool want_loss = meas && loss4;
+    int mode = 0;
+    if (fields) mode |= LED_FIELDS;
+    if (intens) mode |= LED_INTENS;
+    if (want_loss) mode |= LED_LOSS;
+    elfpie_status r;
+    if (mode && (r = led(pl, mode, psi, P, meas, fields, intens, s)) != ELFPIE_OK) return r;
+    if (!want_loss) return ELFPIE_OK;
+    void* T1 = pl->at<void>(pl->tb.o_T1);
+    if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
+    if ((r = hessian(pl, false, T1, nullptr, s)) != ELFPIE_OK) return r;
+    return finalize(pl, loss4, nullptr, nullptr, false, s);
+  }
+
+  static elfpie_status to_object(elfpie_plan* pl, const void* psi, void* obj, hipStream_t s) {
+    const int n = pl->tb.n_hi;
+    elfpie_status r = obj_inverse(pl, psi, obj, s);
+    if (r != ELFPIE_OK) return r;
+    const size_t A = (size_t)n * n;
+    k_sign_scale<T><<<(A + 255) / 256, 256, 0, s>>>(static_cast<C*>(obj), static_cast<C*>(obj), n, T(1.0 / n));
+    LAUNCH_CHECK(pl, "k_sign_scale");
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status to_spectrum(elfpie_plan* pl, const void* obj, void* psi, hipStream_t s) {
+    const int n = pl->tb.n_hi;
+    const size_t A = (size_t)n * n;
+    k_sign_scale<T><<<(A + 255) / 256, 256, 0, s>>>(static_cast<const C*>(obj), static_cast<C*>(psi), n,
+                                                    T(1.0 / n));
+    LAUNCH_CHECK(pl, "k_sign_scale");
+    return obj_forward(pl, psi, psi, s);
+  }
+
+  template <class E>
+  static elfpie_status fill(elfpie_plan* pl, void* p, E v, size_t n, hipStream_t s) {
+    k_fill<E><<<(n + 255) / 256, 256, 0, s>>>(static_cast<E*>(p), v, n);
+    LAUNCH_CHECK(pl, "k_fill");
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status init_state(elfpie_plan* pl, const void* meas, const elfpie_state* st, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    const size_t A = (size_t)tb.n_hi * tb.n_hi, B = (size_t)tb.n_lo * tb.n_lo;
+    const T d0 = T(pl->prob.lr * pl->prob.lr);
+    elfpie_status r;
+    if ((r = fill<C>(pl, st->psi, C{T(0), T(0)}, A, s)) != ELFPIE_OK) return r;
+    if ((r = fill<C>(pl, st->mu_psi, C{T(0), T(0)}, A, s)) != ELFPIE_OK) return r;
+    if ((r = fill<double>(pl, st->v_psi, 0.0, A, s)) != ELFPIE_OK) return r;
+    if ((r = fill<T>(pl, st->delta_psi, d0, A, s)) != ELFPIE_OK) return r;
+    if ((r = fill<C>(pl, st->mu_P, C{T(0), T(0)}, B, s)) != ELFPIE_OK) return r;
+    if ((r = fill<double>(pl, st->v_P, 0.0, B, s)) != ELFPIE_OK) return r;
+    if ((r = fill<T>(pl, st->delta_P, d0, B, s)) != ELFPIE_OK) return r;
+    if ((r = fill<long long>(pl, st->t, 0LL, 1, s)) != ELFPIE_OK) return r;
+    k_init_pupil<T><<<(B + 255) / 256, 256, 0, s>>>(static_cast<C*>(st->P), pl->at<int>(tb.o_xlo),
+                                                   pl->at<int>(tb.o_xhi), tb.n_lo);
+    LAUNCH_CHECK(pl, "k_init_pupil");
+    const T* mc = static_cast<const T*>(meas) + (size_t)tb.kc * B;
+    const int y0 = tb.win[2 * tb.kc], x0 = tb.win[2 * tb.kc + 1];
+    const T sc = T((double)pl->prob.upsample / tb.n_lo);
+    C* psi = static_cast<C*>(st->psi);
+    const int* xlo = pl->at<int>(tb.o_xlo);
+    const int* xhi = pl->at<int>(tb.o_xhi);
+    const C* tw = pl->at<C>(tb.o_twlo);
+    switch (tb.n_lo) {
+      case 32: k_init_window<T, 32><<<1, LedShape<32>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;
+      case 64: k_init_window<T, 64><<<1, LedShape<64>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;
+      case 128:
+        if constexpr (sizeof(T) == 4) {
+          k_init_window<T, 128><<<1, LedShape<128>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw);
+          break;
+        }
+        [[fallthrough]];
+      default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_lo not supported in this precision");
+    }
+    LAUNCH_CHECK(pl, "k_init_window");
+    return ELFPIE_OK;
+  }
+
+  static elfpie_status stage_timing(elfpie_plan* pl, const elfpie_state* st, const void* meas, int n_rep,
+                                    float* ms, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    void* T1 = pl->at<void>(tb.o_T1);
+    void* T2 = pl->at<void>(tb.o_T2);
+    void* G = pl->at<void>(tb.o_G);
+    void* gP = pl->at<void>(tb.o_gP);
+    double* l4 = pl->at<double>(tb.o_loss);
+    hipEvent_t e0, e1;
+    HIP_TRY(pl, hipEventCreate(&e0));
+    HIP_TRY(pl, hipEventCreate(&e1));
+    elfpie_status r = ELFPIE_OK;
+    for (int stage = 0; stage < 7 && r == ELFPIE_OK; ++stage) {
+      // warm the stage once, then time n_rep launches
+      for (int rep = -1; rep < n_rep && r == ELFPIE_OK; ++rep) {
+        if (rep == 0) {
+          if (hipEventRecord(e0, s) != hipSuccess) r = set_err(pl, ELFPIE_E_DEVICE, "hipEventRecord");
+        }
+        switch (stage) {
+          case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s); break;
+          case 1: r = obj_inverse(pl, st->psi, T1, s); break;
+          case 2: r = hessian(pl, true, T1, T2, s); break;
+          case 3: r = obj_forward(pl, T2, G, s); break;
+          case 4: r = psi_update(pl, nullptr, G, T2, s); break;
+          case 5:
+            r = pupil_reduce(pl, st->P, true, s);
+            if (r == ELFPIE_OK) r = pupil_finish(pl, st->P, nullptr, gP, s);
+            break;
+          case 6: r = finalize(pl, l4, nullptr, nullptr, false, s); break;
+        }
+      }
+      if (r != ELFPIE_OK) break;
+      HIP_TRY(pl, hipEventRecord(e1, s));
+      HIP_TRY(pl, hipEventSynchronize(e1));
+      float t = 0.f;
+      HIP_TRY(pl, hipEventElapsedTime(&t, e0, e1));
+      ms[stage] = t / (float)n_rep;
+    }
+    ms[7] = 0.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r;
+  }
+};
+
+template <class F>
+elfpie_status dispatch(elfpie_plan* pl, F&& f) {
+  if (pl->tb.prec == ELFPIE_F32) return f(Ops<float>{});
+  return f(Ops<double>{});
+}
+
+elfpie_status check_state(elfpie_plan* pl, const elfpie_state* st) {
+  if (!st) return set_err(pl, ELFPIE_E_INVALID, "state is NULL");
+  const void* ptrs[] = {st->psi, st->P, st->mu_psi, st->v_psi, st->delta_psi, st->mu_P, st->v_P, st->delta_P, st->t};
+  for (const void* q : ptrs)
+    if (!q || !aligned16(q)) return set_err(pl, ELFPIE_E_INVALID, "a state pointer is NULL or not 16-byte aligned");
+  return ELFPIE_OK;
+}
+
+elfpie_status check_ptr(elfpie_plan* pl, const void* q, const char* name, bool optional) {
+  if (!q) return optional ? ELFPIE_OK : set_err(pl, ELFPIE_E_INVALID, std::string(name) + " is NULL");
+  if (!aligned16(q)) return set_err(pl, ELFPIE_E_INVALID, std::string(name) + " is not 16-byte aligned");
+  return ELFPIE_OK;
+}
+
+#define CHECK(expr)                   \
+  do {                                \
+    elfpie_status s_ = (expr);        \
+    if (s_ != ELFPIE_OK) return s_;   \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+elfpie_status elfpie_problem_defaults(elfpie_problem* p) {
+  if (!p) return ELFPIE_E_INVALID;
+  std::memset(p, 0, sizeof *p);
+  p->upsample = 4;
+  p->alpha = 1e-3;
+  p->beta = 1e-3;
+  p->lr = 1e-2;
+  p->gamma1 = 0.9;
+  p->gamma2 = 0.999;
+  p->eta_opt = 1e-8;
+  p->eta_h = 1e-6;
+  p->l1_eps = 0.0;
+  p->fidelity = ELFPIE_FID_INTENSITY;
+  p->norm = ELFPIE_NORM_ANISO;
+  p->precision = ELFPIE_F32;
+  p->flags = ELFPIE_PUPIL_SUPPORT;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_workspace_bytes(const elfpie_problem* p, size_t* bytes) {
+  if (!bytes) {
+    g_last_error = "bytes is NULL";
+    return ELFPIE_E_INVALID;
+  }
+  Tables tb;
+  std::string err;
+  const elfpie_status s = build_tables(p, &tb, &err);
+  if (s != ELFPIE_OK) {
+    g_last_error = err;
+    return s;
+  }
+  *bytes = tb.total;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_bytes, elfpie_plan** out) {
+  if (!out) {
+    g_last_error = "out is NULL";
+    return ELFPIE_E_INVALID;
+  }
+  *out = nullptr;
+  Tables tb;
+  std::string err;
+  elfpie_status s = build_tables(p, &tb, &err);
+  if (s != ELFPIE_OK) {
+    g_last_error = err;
+    return s;
+  }
+  if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) % kAlign) != 0) {
+    g_last_error = "workspace is NULL or not 256-byte aligned";
+    return ELFPIE_E_INVALID;
+  }
+  if (ws_bytes < tb.total) {
+    g_last_error = "workspace too small: need " + std::to_string(tb.total) + " bytes";
+    return ELFPIE_E_WORKSPACE;
+  }
+  elfpie_plan* pl = new elfpie_plan();
+  pl->prob = *p;
+  pl->prob.led_k = nullptr;  // host array is not kept
+  pl->tb = std::move(tb);
+  pl->ws = static_cast<char*>(d_ws);
+  const Tables& t = pl->tb;
+  auto cleanup = [&](elfpie_status st) {
+    g_last_error = pl->err;
+    elfpie_plan_destroy(pl);
+    return st;
+  };
+  if (hipGetDevice(&pl->device) != hipSuccess) return cleanup(set_err(pl, ELFPIE_E_DEVICE, "hipGetDevice failed"));
+  // twiddle tables exp(-2 pi i k / n), computed in double
+  auto twiddles = [&](int n) {
+    std::vector<double> tw(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+      const double a = -2.0 * M_PI * k / n;
+      tw[2 * k] = std::cos(a);
+      tw[2 * k + 1] = std::sin(a);
+    }
+    return tw;
+  };
+  auto put = [&](size_t off, const void* src, size_t bytes) -> elfpie_status {
+    if (!bytes) return ELFPIE_OK;
+    return hip_check(pl, hipMemcpy(pl->ws + off, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(plan tables)");
+  };
+  auto put_tw = [&](size_t off, int n) -> elfpie_status {
+    std::vector<double> tw = twiddles(n);
+    if (t.prec == ELFPIE_F32) {
+      std::vector<float> f(tw.begin(), tw.end());
+      return put(off, f.data(), f.size() * sizeof(float));
+    }
+    return put(off, tw.data(), tw.size() * sizeof(double));
+  };
+  elfpie_status st;
+  if ((st = put(t.o_win, t.win.data(), t.win.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_xlo, t.xlo.data(), t.xlo.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_xhi, t.xhi.data(), t.xhi.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_roff, t.rowoff.data(), t.rowoff.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_tptr, t.tile_ptr.data(), t.tile_ptr.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_tled, t.tile_led.data(), t.tile_led.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
+    return cleanup(st);
+  const int zero = 0;
+  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
+    return cleanup(st);
+  if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
+    return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream / event creation failed"));
+  *out = pl;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_plan_destroy(elfpie_plan* pl) {
+  if (!pl) return ELFPIE_E_INVALID;
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
+  if (pl->side) (void)hipStreamDestroy(pl->side);
+  delete pl;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_plan_info(const elfpie_plan* pl, int32_t* out) {
+  if (!pl || !out) return ELFPIE_E_INVALID;
+  out[0] = pl->tb.n_hi;
+  out[1] = pl->tb.S;
+  out[2] = pl->tb.K;
+  out[3] = pl->tb.n_lo;
+  out[4] = pl->tb.kc;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_forward(elfpie_plan* pl, const void* psi, const void* P, const void* meas, void* fields,
+                             void* intens, double* d_loss4, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, psi, "psi", false));
+  CHECK(check_ptr(pl, P, "P", false));
+  CHECK(check_ptr(pl, meas, "meas", true));
+  CHECK(check_ptr(pl, fields, "fields", true));
+  CHECK(check_ptr(pl, intens, "intens", true));
+  CHECK(check_ptr(pl, d_loss4, "d_loss4", true));
+  if (d_loss4 && !meas) return set_err(pl, ELFPIE_E_INVALID, "d_loss4 needs meas");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::forward(pl, psi, P, meas, fields, intens, d_loss4, s); });
+}
+
+elfpie_status elfpie_grad(elfpie_plan* pl, const void* psi, const void* P, const void* meas, void* g_psi,
+                          void* g_P, double* d_loss4, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, psi, "psi", false));
+  CHECK(check_ptr(pl, P, "P", false));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  CHECK(check_ptr(pl, g_psi, "g_psi", false));
+  CHECK(check_ptr(pl, g_P, "g_P", true));
+  CHECK(check_ptr(pl, d_loss4, "d_loss4", true));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) {
+    return decltype(ops)::iteration(pl, psi, P, meas, nullptr, g_psi, g_P, d_loss4, nullptr, s);
+  });
+}
+
+elfpie_status elfpie_step(elfpie_plan* pl, const elfpie_state* st, const void* meas, double* d_loss4,
+                          void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_state(pl, st));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  CHECK(check_ptr(pl, d_loss4, "d_loss4", true));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) {
+    return decltype(ops)::iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, d_loss4, nullptr, s);
+  });
+}
+
+elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* meas, int32_t n_iter,
+                         double* d_loss_hist, int32_t checked, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_state(pl, st));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  CHECK(check_ptr(pl, d_loss_hist, "d_loss_hist", true));
+  if (n_iter < 0) return set_err(pl, ELFPIE_E_INVALID, "n_iter must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Tables& tb = pl->tb;
+  int* ctr = pl->at<int>(tb.o_ctr);
+  int* flag = pl->at<int>(tb.o_flag);
+  // reset the history slot counter and the non-finite flag (kernels, not memsets)
+  k_fill<int><<<1, 64, 0, s>>>(ctr, 0, 1);
+  k_fill<int><<<1, 64, 0, s>>>(flag, 0, 1);
+  LAUNCH_CHECK(pl, "k_fill");
+  if (n_iter == 0) return ELFPIE_OK;
+  // the graph bakes in every pointer of the iteration: reuse it only for the same ones
+  const bool same = pl->gexec && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
+                    pl->gkey_hist == d_loss_hist;
+  if (!same) {
+    // (re)capture one iteration on the plan's capture stream
+    if (pl->gexec) {
+      (void)hipGraphExecDestroy(pl->gexec);
+      pl->gexec = nullptr;
+    }
+    if (pl->graph) {
+      (void)hipGraphDestroy(pl->graph);
+      pl->graph = nullptr;
+    }
+    HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    const elfpie_status r = dispatch(pl, [&](auto ops) {
+      return decltype(ops)::iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, d_loss_hist, pl->cap);
+    });
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(pl->cap, &g);
+    if (r != ELFPIE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    HIP_TRY(pl, ec);
+    pl->graph = g;
+    HIP_TRY(pl, hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0));
+    pl->gkey = *st;
+    pl->gkey_meas = meas;
+    pl->gkey_hist = d_loss_hist;
+  }
+  for (int i = 0; i < n_iter; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexec, s));
+  if (checked) {
+    HIP_TRY(pl, hipStreamSynchronize(s));
+    int h = 0;
+    HIP_TRY(pl, hipMemcpy(&h, flag, sizeof h, hipMemcpyDeviceToHost));
+    if (h) return set_err(pl, ELFPIE_E_NONFINITE, "a loss value was NaN or Inf");
+  }
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_object_from_spectrum(elfpie_plan* pl, const void* psi, void* obj, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, psi, "psi", false));
+  CHECK(check_ptr(pl, obj, "obj", false));
+  if (psi == obj) return set_err(pl, ELFPIE_E_INVALID, "in-place transform is not allowed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::to_object(pl, psi, obj, s); });
+}
+
+elfpie_status elfpie_spectrum_from_object(elfpie_plan* pl, const void* obj, void* psi, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, psi, "psi", false));
+  CHECK(check_ptr(pl, obj, "obj", false));
+  if (psi == obj) return set_err(pl, ELFPIE_E_INVALID, "in-place transform is not allowed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::to_spectrum(pl, obj, psi, s); });
+}
+
+elfpie_status elfpie_init_state(elfpie_plan* pl, const void* meas, const elfpie_state* st, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_state(pl, st));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::init_state(pl, meas, st, s); });
+}
+
+elfpie_status elfpie_stage_timing(elfpie_plan* pl, const elfpie_state* st, const void* meas, int32_t n_rep,
+                                  float* ms_out, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_state(pl, st));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  if (!ms_out || n_rep < 1) return set_err(pl, ELFPIE_E_INVALID, "ms_out is NULL or n_rep < 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::stage_timing(pl, st, meas, n_rep, ms_out, s); });
+}
+
+const char* elfpie_last_error(const elfpie_plan* pl) {
+  if (pl) return pl->err.c_str();
+  return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,680 @@
+// gfx950 kernels of one Elfpie iteration (Zhang et al., arXiv 2209.14671, Sec. 3,
+// Algorithm 1).  All transforms are unnormalised DFTs; the unitary scalings and
+// the centring of the spectra are folded into the neighbouring elementwise work:
+// for even n, ifftshift before / fftshift after a DFT equals a (-1)^(x+y) factor on
+// the spatial side, and for the per-LED path that factor cancels between the
+// inverse transform (o) and the forward transform of W, because W is o times a
+// real field.  So the per-LED path needs no sign at all.
+#pragma once
+
+#include <cfloat>
+#include <cmath>
+
+#include "cx.hpp"
+#include "fft.hpp"
+#include "params.hpp"
+
+namespace elfpie {
+
+// ---------------------------------------------------------------------------
+// Deterministic block reduction of a double (fixed shuffle and slot order).
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* scratch /* NT/64 */) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s += scratch[i];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// L1 term rho(d) = sqrt(d^2 + eps^2) - eps (eps > 0) or |d| and its derivative.
+template <class T>
+__device__ __forceinline__ T rho(T d, T eps) {
+  return eps > T(0) ? sqrt(d * d + eps * eps) - eps : fabs(d);
+}
+template <class T>
+__device__ __forceinline__ T omega(T d, T eps) {
+  if (eps > T(0)) return d / sqrt(d * d + eps * eps);
+  return T((d > T(0)) - (d < T(0)));
+}
+// 1 / ||c|| for the isotropic normaliser (0 at the origin when eps = 0).
+template <class T>
+__device__ __forceinline__ T inv_norm(T s2, T eps) {
+  if (eps > T(0)) return T(1) / sqrt(s2 + eps * eps);
+  return s2 > T(0) ? T(1) / sqrt(s2) : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Per-LED fused kernel: one workgroup per LED, the n_lo x n_lo tile in LDS.
+// ---------------------------------------------------------------------------
+template <int N> struct LedShape;
+template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 4, R2 = 8; };
+template <> struct LedShape<64> { static constexpr int NT = 256, R1 = 8, R2 = 8; };
+template <> struct LedShape<128> { static constexpr int NT = 1024, R1 = 16, R2 = 8; };
+
+// Steps of the per-LED branch (one LED per workgroup):
+//   gather   X = P * M_k Psi on the pupil support                  (Eq. 1)
+//   inverse  o = F_B X / (r n_lo): rows holding support, then columns
+//   residual e = |o|^2 - I  or  |o| - sqrt(I)                        (Eq. 5 / Eq. 4)
+//   features forward differences of e, L1 loss, omega               (Eq. 12)
+//   adjoint  q = grad^T omega, dL/d(conj o) = q o  or  q o / (2|o|)  (Eq. 11 / Eq. 10)
+//   forward  Y = F_B^H dL/d(conj o): all rows, then support columns
+//   outputs  C = conj(P) Y and D = conj(M_k Psi) Y on the support    (Eq. 9, Eq. 18)
+template <class T, int N>
+__global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
+  using Sh = LedShape<N>;
+  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
+  static_assert(R1 * R2 == N, "two-pass decomposition");
+  constexpr int MB1 = ceil_div(N * (N / R1), NT);
+  constexpr int MB2 = ceil_div(N * (N / R2), NT);
+  using P1i = StockhamPass<T, N, R1, 1, true, NT, MB1>;
+  using P2i = StockhamPass<T, N, R2, R1, true, NT, MB2>;
+  using P1f = StockhamPass<T, N, R1, 1, false, NT, MB1>;
+  using P2f = StockhamPass<T, N, R2, R1, false, NT, MB2>;
+
+  __shared__ cx<T> img[N * PITCH];
+  __shared__ cx<T> twl[N];
+  __shared__ int sxlo[N], sxhi[N], sroff[N];
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x;
+  const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
+  const cx<T>* P = static_cast<const cx<T>*>(a.P);
+  for (int i = tid; i < N; i += NT) {
+    twl[i] = static_cast<const cx<T>*>(a.tw)[i];
+    sxlo[i] = a.xlo[i];
+    sxhi[i] = a.xhi[i];
+    sroff[i] = a.rowoff[i];
+  }
+  const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
+  const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
+  __syncthreads();
+
+  // gather (zeros off the support)
+  for (int p = tid; p < N * N; p += NT) {
+    const int y = p / N, x = p % N;
+    cx<T> v = czero<T>();
+    if (x >= sxlo[y] && x <= sxhi[y]) v = P[p] * win[(size_t)y * a.n_hi + x];
+    img[y * PITCH + x] = v;
+  }
+  __syncthreads();
+
+  // inverse DFT: rows that hold support pixels, then every column
+  const int nband = a.y_max - a.y_min + 1;
+  P1i::run(img, a.y_min, nband, PITCH, 1, twl, tid);
+  P2i::run(img, a.y_min, nband, PITCH, 1, twl, tid);
+  P1i::run(img, 0, N, 1, PITCH, twl, tid);
+  cx<T> o[MB2][R2];
+  P2i::load(img, 0, N, 1, PITCH, twl, tid, o);
+  __syncthreads();
+
+  // register (i, r) holds pixel y = j + r R1, x = m, where b = tid + i NT = j N + m
+  const T sc = T(a.inv_scale);
+  const T eps = T(a.eps);
+  const int mode = a.mode;
+  const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
+  const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
+  T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
+  T ev[MB2][R2];
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int b = tid + i * NT;
+    if (b < N * R1) {
+      const int j = b / N, x = b - j * N;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = j + r * R1;
+        const cx<T> ov = scale(o[i][r], sc);
+        o[i][r] = ov;
+        const size_t pix = (size_t)k * N * N + (size_t)y * N + x;
+        if (mode & LED_FIELDS) {
+          const cx<T> f = ((x + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
+          static_cast<cx<T>*>(a.fields)[pix] = f;
+        }
+        const T i2 = norm2(ov);
+        if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
+        if (need_e) {
+          const T mv = meas[(size_t)y * N + x];
+          const T e = (a.fidelity == 0) ? sqrt(i2) - sqrt(mv > T(0) ? mv : T(0)) : i2 - mv;
+          ev[i][r] = e;
+          eb[y * PITCH + x] = e;
+        }
+      }
+    }
+  }
+  if (!need_e) return;
+  __syncthreads();
+
+  auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
+  double lsum = 0.0;
+  cx<T> w[MB2][R2];
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int b = tid + i * NT;
+    if (b < N * R1) {
+      const int j = b / N, x = b - j * N;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = j + r * R1;
+        const T e = ev[i][r];
+        const T dx0 = (x < N - 1) ? E(y, x + 1) - e : T(0);
+        const T dy0 = (y < N - 1) ? E(y + 1, x) - e : T(0);
+        T q;
+        if (a.norm == 0) {
+          const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
+          const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
+          q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
+          lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+        } else {
+          const T s0 = dx0 * dx0 + dy0 * dy0;
+          const T inv0 = inv_norm(s0, eps);
+          q = -(dx0 + dy0) * inv0;
+          if (x > 0) {  // normaliser at (y, x-1)
+            const T el = E(y, x - 1);
+            const T gx = e - el;
+            const T gy = (y < N - 1) ? E(y + 1, x - 1) - el : T(0);
+            q += gx * inv_norm(gx * gx + gy * gy, eps);
+          }
+          if (y > 0) {  // normaliser at (y-1, x)
+            const T eu = E(y - 1, x);
+            const T gy = e - eu;
+            const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
+            q += gy * inv_norm(gx * gx + gy * gy, eps);
+          }
+          lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+        }
+        const cx<T> ov = o[i][r];
+        if (a.fidelity == 0) {
+          const T am = sqrt(norm2(ov));
+          w[i][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
+        } else {
+          w[i][r] = scale(ov, q);
+        }
+      }
+    }
+  }
+  __syncthreads();  // every residual read is done; the tile can be overwritten
+
+  const bool grad = (mode & LED_GRAD) != 0;
+  if (grad) {
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+      const int b = tid + i * NT;
+      if (b < N * R1) {
+        const int j = b / N, x = b - j * N;
+#pragma unroll
+        for (int r = 0; r < R2; ++r) img[(j + r * R1) * PITCH + x] = w[i][r];
+      }
+    }
+  }
+  const double tot = block_sum<NT>(lsum, red);  // contains barriers
+  if (tid == 0) a.fid_partial[k] = tot;
+  if (!grad) return;
+
+  // forward DFT of dL/d(conj o): all rows, then only columns that hold support
+  P1f::run(img, 0, N, PITCH, 1, twl, tid);
+  P2f::run(img, 0, N, PITCH, 1, twl, tid);
+  const int ncol = a.x_max - a.x_min + 1;
+  P1f::run(img, a.x_min, ncol, 1, PITCH, twl, tid);
+  cx<T> Y[MB2][R2];
+  P2f::load(img, a.x_min, ncol, 1, PITCH, twl, tid, Y);
+
+  cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
+  cx<T>* D = static_cast<cx<T>*>(a.D) + (size_t)k * a.S;
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int b = tid + i * NT;
+    if (b < ncol * R1) {
+      const int j = b / ncol, m = b - j * ncol;
+      const int x = a.x_min + m;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = j + r * R1;
+        const int lo = sxlo[y];
+        if (x >= lo && x <= sxhi[y]) {
+          const int s = sroff[y] + x - lo;
+          const cx<T> yv = scale(Y[i][r], sc);
+          C[s] = cmulc(P[y * N + x], yv);
+          D[s] = cmulc(win[(size_t)y * a.n_hi + x], yv);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Object-branch FFTs on the n_hi x n_hi spectrum: RPB rows (or columns) per block.
+// ---------------------------------------------------------------------------
+template <int N> struct BigShape;
+template <> struct BigShape<128> { static constexpr int NT = 128, RPB = 16, R1 = 16, R2 = 8, R3 = 1; };
+template <> struct BigShape<256> { static constexpr int NT = 128, RPB = 8, R1 = 16, R2 = 16, R3 = 1; };
+template <> struct BigShape<512> { static constexpr int NT = 128, RPB = 2, R1 = 8, R2 = 8, R3 = 8; };
+template <> struct BigShape<1024> { static constexpr int NT = 128, RPB = 2, R1 = 16, R2 = 8, R3 = 8; };
+
+// Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
+// (COLS = true) of an N x N complex array; in may equal out.
+template <class T, int N, bool INV, bool COLS>
+__global__ __launch_bounds__(BigShape<N>::NT) void k_fft_lines(const cx<T>* in, cx<T>* out, const cx<T>* tw) {
+  using Sh = BigShape<N>;
+  constexpr int NT = Sh::NT, RPB = Sh::RPB, R1 = Sh::R1, R2 = Sh::R2, R3 = Sh::R3, PITCH = N + 1;
+  constexpr int MB1 = ceil_div(RPB * (N / R1), NT);
+  constexpr int MB2 = ceil_div(RPB * (N / R2), NT);
+  constexpr int MB3 = ceil_div(RPB * (N / R3), NT);
+  __shared__ cx<T> buf[RPB * PITCH];
+  __shared__ cx<T> twl[N];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * RPB;
+  for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+  for (int p = tid; p < RPB * N; p += NT) {
+    if (COLS) {
+      const int c = p % RPB, y = p / RPB;
+      buf[c * PITCH + y] = in[(size_t)y * N + l0 + c];
+    } else {
+      const int r = p / N, x = p % N;
+      buf[r * PITCH + x] = in[(size_t)(l0 + r) * N + x];
+    }
+  }
+  __syncthreads();
+  auto emit = [&](int m, int e, cx<T> v) {
+    if (COLS) out[(size_t)e * N + l0 + m] = v;
+    else out[(size_t)(l0 + m) * N + e] = v;
+  };
+  using PA = StockhamPass<T, N, R1, 1, INV, NT, MB1>;
+  using PB = StockhamPass<T, N, R2, R1, INV, NT, MB2>;
+  PA::run(buf, 0, RPB, PITCH, 1, twl, tid);
+  if constexpr (R3 == 1) {
+    cx<T> v[MB2][R2];
+    PB::load(buf, 0, RPB, PITCH, 1, twl, tid, v);
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+      const int b = tid + i * NT;
+      if (b < RPB * (N / R2)) {
+        const int j = b / RPB, m = b - j * RPB;
+#pragma unroll
+        for (int r = 0; r < R2; ++r) emit(m, PB::out_index(j, r), v[i][r]);
+      }
+    }
+  } else {
+    using PC = StockhamPass<T, N, R3, R1 * R2, INV, NT, MB3>;
+    PB::run(buf, 0, RPB, PITCH, 1, twl, tid);
+    cx<T> v[MB3][R3];
+    PC::load(buf, 0, RPB, PITCH, 1, twl, tid, v);
+#pragma unroll
+    for (int i = 0; i < MB3; ++i) {
+      const int b = tid + i * NT;
+      if (b < RPB * (N / R3)) {
+        const int j = b / RPB, m = b - j * RPB;
+#pragma unroll
+        for (int r = 0; r < R3; ++r) emit(m, PC::out_index(j, r), v[i][r]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hessian penalties (Eq. 6, 7) and their gradient (Eq. 13, 14) on 16 x 16 tiles.
+// ---------------------------------------------------------------------------
+// Input: Ot = unnormalised inverse DFT of Psi, so O = (-1)^(x+y) Ot / n.
+// H components at p: xx = f(x-1) - 2 f(x) + f(x+1) (1 <= x <= n-2), yy likewise,
+// xy = f(p) - f(p+ex) - f(p+ey) + f(p+ex+ey) (x, y <= n-2); each zero elsewhere.
+// The gradient at p needs omega within 1 pixel, which needs |O| and angle(O)
+// within 2 pixels: the block loads a 20 x 20 patch.
+template <class T>
+__global__ __launch_bounds__(256) void k_hessian(HessArgs a) {
+  constexpr int TS = 16, HP = TS + 4, HO = TS + 2;
+  __shared__ T sa[HP][HP + 1], sp[HP][HP + 1];
+  __shared__ T om[6][HO][HO + 1];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
+  const int n = a.n;
+  const T inv_n = T(a.inv_n);
+  const T eps = T(a.eps);
+  const cx<T>* Ot = static_cast<const cx<T>*>(a.Ot);
+  for (int p = tid; p < HP * HP; p += 256) {
+    const int ly = p / HP, lx = p % HP;
+    const int gy = ty0 + ly - 2, gx = tx0 + lx - 2;
+    T am = T(0), ph = T(0);
+    if (gy >= 0 && gy < n && gx >= 0 && gx < n) {
+      cx<T> O = scale(Ot[(size_t)gy * n + gx], ((gx + gy) & 1) ? -inv_n : inv_n);
+      am = sqrt(norm2(O));
+      ph = atan2(O.y, O.x);
+    }
+    sa[ly][lx] = am;
+    sp[ly][lx] = ph;
+  }
+  __syncthreads();
+  double la = 0.0, lp = 0.0;
+  for (int p = tid; p < HO * HO; p += 256) {
+    const int ly = p / HO, lx = p % HO;          // patch index (ly + 1, lx + 1)
+    const int gy = ty0 + ly - 1, gx = tx0 + lx - 1;
+    const bool in = gy >= 0 && gy < n && gx >= 0 && gx < n;
+    const bool vxx = in && gx >= 1 && gx <= n - 2;
+    const bool vyy = in && gy >= 1 && gy <= n - 2;
+    const bool vxy = in && gx <= n - 2 && gy <= n - 2;
+    const bool own = ly >= 1 && ly <= TS && lx >= 1 && lx <= TS && in;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      T (*src)[HP + 1] = f == 0 ? sa : sp;
+      const int cy = ly + 1, cx_ = lx + 1;
+      const T c = src[cy][cx_];
+      const T hxx = vxx ? src[cy][cx_ - 1] - T(2) * c + src[cy][cx_ + 1] : T(0);
+      const T hyy = vyy ? src[cy - 1][cx_] - T(2) * c + src[cy + 1][cx_] : T(0);
+      const T hxy = vxy ? c - src[cy][cx_ + 1] - src[cy + 1][cx_] + src[cy + 1][cx_ + 1] : T(0);
+      T wxx, wyy, wxy;
+      double l;
+      if (a.norm == 0) {
+        wxx = omega(hxx, eps);
+        wyy = omega(hyy, eps);
+        wxy = omega(hxy, eps);
+        l = double(rho(hxx, eps)) + double(rho(hyy, eps)) + double(rho(hxy, eps));
+      } else {
+        const T s2 = hxx * hxx + hyy * hyy + hxy * hxy;
+        const T inv = inv_norm(s2, eps);
+        wxx = hxx * inv;
+        wyy = hyy * inv;
+        wxy = hxy * inv;
+        l = eps > T(0) ? double(sqrt(s2 + eps * eps) - eps) : double(sqrt(s2));
+      }
+      om[3 * f + 0][ly][lx] = wxx;
+      om[3 * f + 1][ly][lx] = wyy;
+      om[3 * f + 2][ly][lx] = wxy;
+      if (own) {
+        if (f == 0) la += l;
+        else lp += l;
+      }
+    }
+  }
+  __syncthreads();
+  const int ty = tid / TS, tx = tid % TS;
+  const int gy = ty0 + ty, gx = tx0 + tx;
+  if (a.want_grad && gy < n && gx < n) {
+    const int ly = ty + 1, lx = tx + 1;  // omega index of the own pixel
+    T q[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const T (*wx)[HO + 1] = om[3 * f + 0];
+      const T (*wy)[HO + 1] = om[3 * f + 1];
+      const T (*wz)[HO + 1] = om[3 * f + 2];
+      q[f] = wx[ly][lx - 1] - T(2) * wx[ly][lx] + wx[ly][lx + 1] + wy[ly - 1][lx] - T(2) * wy[ly][lx] +
+             wy[ly + 1][lx] + wz[ly][lx] - wz[ly][lx - 1] - wz[ly - 1][lx] + wz[ly - 1][lx - 1];
+    }
+    const T sgn = ((gx + gy) & 1) ? -inv_n : inv_n;
+    const cx<T> O = scale(Ot[(size_t)gy * n + gx], sgn);
+    const T a2 = norm2(O);
+    const T am = sqrt(a2);
+    cx<T> G = czero<T>();
+    if (am > T(0)) G = scale(O, T(a.alpha) * q[0] / (T(2) * am));
+    const T den = a2 + T(a.eta_h);
+    if (den > T(0)) G = G + scale(mul_i(O), T(a.beta) * q[1] / (T(2) * den));
+    static_cast<cx<T>*>(a.Gt)[(size_t)gy * n + gx] = scale(G, sgn);
+  }
+  // deterministic block sums of the two penalty partials
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    la += __shfl_down(la, off, 64);
+    lp += __shfl_down(lp, off, 64);
+  }
+  __shared__ double red2[4][2];
+  if ((tid & 63) == 0) {
+    red2[tid >> 6][0] = la;
+    red2[tid >> 6][1] = lp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    a.partial[2 * tile + 0] = red2[0][0] + red2[1][0] + red2[2][0] + red2[3][0];
+    a.partial[2 * tile + 1] = red2[0][1] + red2[1][1] + red2[2][1] + red2[3][1];
+  }
+  (void)red;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (19) for one element, FP64 second moment and normaliser.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, double& v, T& delta, double g1,
+                                               double g2, double eta, double bc1, double bc2) {
+  const T tg1 = T(g1);
+  const cx<T> m = {tg1 * mu.x + (T(1) - tg1) * g.x, tg1 * mu.y + (T(1) - tg1) * g.y};
+  const double dxr = double(m.x) - double(g.x), dxi = double(m.y) - double(g.y);
+  const double vn = g2 * v + (1.0 - g2) * (dxr * dxr + dxi * dxi);
+  const double ratio = (sqrt(double(delta)) + eta) / (sqrt(vn / bc2) + eta);
+  // gamma1 * mu_hat + (1 - gamma1) g
+  const double sx = g1 * double(m.x) / bc1 + (1.0 - g1) * double(g.x);
+  const double sy = g1 * double(m.y) / bc1 + (1.0 - g1) * double(g.y);
+  const cx<T> step = {T(ratio * sx), T(ratio * sy)};
+  x = x - step;
+  delta = tg1 * delta + (T(1) - tg1) * norm2(step);
+  mu = m;
+  v = vn;
+}
+
+// Spectrum gradient gather (segmented sum of the LED contributions that cover each
+// pixel, ascending LED order: Eq. 9's sum of M^T) plus the Hessian gradient, then
+// either the gradient is written or Eq. 19 updates Psi.  One 16 x 16 tile per block.
+template <class T>
+__global__ __launch_bounds__(256) void k_psi_update(UpdArgs a) {
+  const int tile = blockIdx.x;
+  const int ty0 = (tile / a.ntiles_x) * 16, tx0 = (tile % a.ntiles_x) * 16;
+  const int uy = ty0 + threadIdx.x / 16, ux = tx0 + threadIdx.x % 16;
+  const size_t u = (size_t)uy * a.n_hi + ux;
+  cx<T> g = static_cast<const cx<T>*>(a.gH)[u];
+  const cx<T>* C = static_cast<const cx<T>*>(a.C);
+  const int b0 = a.tile_ptr[tile], b1 = a.tile_ptr[tile + 1];
+  for (int idx = b0; idx < b1; ++idx) {
+    const int k = a.tile_led[idx];
+    const int dy = uy - a.win[2 * k], dx = ux - a.win[2 * k + 1];
+    if (dy >= 0 && dy < a.n_lo) {
+      const int lo = a.xlo[dy];
+      if (dx >= lo && dx <= a.xhi[dy]) g = g + C[(size_t)k * a.S + a.rowoff[dy] + dx - lo];
+    }
+  }
+  if (!a.step) {
+    static_cast<cx<T>*>(a.g_out)[u] = g;
+    return;
+  }
+  const double t1 = double(*a.t + 1);
+  const double bc1 = 1.0 - pow(a.g1, t1), bc2 = 1.0 - pow(a.g2, t1);
+  cx<T> x = static_cast<cx<T>*>(a.x)[u];
+  cx<T> mu = static_cast<cx<T>*>(a.mu)[u];
+  double v = a.v[u];
+  T d = static_cast<T*>(a.delta)[u];
+  adabelief_elem(x, g, mu, v, d, a.g1, a.g2, a.eta, bc1, bc2);
+  static_cast<cx<T>*>(a.x)[u] = x;
+  static_cast<cx<T>*>(a.mu)[u] = mu;
+  a.v[u] = v;
+  static_cast<T*>(a.delta)[u] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Pupil: partial sums over LED chunks (Eq. 18), Gaussian pre-filter, update.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_pupil_partial(PupilArgs a) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (s >= a.S) return;
+  const cx<T>* D = static_cast<const cx<T>*>(a.D);
+  const int k0 = ch * a.chunk;
+  const int k1 = min(a.K, k0 + a.chunk);
+  cx<T> acc = czero<T>();
+  for (int k = k0; k < k1; ++k) acc = acc + D[(size_t)k * a.S + s];
+  static_cast<cx<T>*>(a.part)[(size_t)ch * a.S + s] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pupil_gauss(PupilArgs a) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int n = a.n_lo;
+  if (p >= n * n) return;
+  const int y = p / n, x = p % n;
+  const cx<T>* P = static_cast<const cx<T>*>(a.P);
+  cx<T> acc = czero<T>();
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int yy = y + dy, xx = x + dx;
+      if (yy < 0 || yy >= n || xx < 0 || xx >= n) continue;
+      const int ring = (dy != 0) + (dx != 0);
+      const T w = T(ring == 0 ? a.w_c : (ring == 1 ? a.w_e : a.w_k));
+      acc = acc + scale(P[yy * n + xx], w);
+    }
+  static_cast<cx<T>*>(a.Pf_out)[p] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int n = a.n_lo;
+  if (p >= n * n) return;
+  const int y = p / n, x = p % n;
+  const int lo = a.xlo[y];
+  const bool in = x >= lo && x <= a.xhi[y];
+  cx<T> g = czero<T>();
+  if (in) {
+    const int s = a.rowoff[y] + x - lo;
+    const cx<T>* part = static_cast<const cx<T>*>(a.part);
+    for (int c = 0; c < a.nch; ++c) g = g + part[(size_t)c * a.S + s];
+  }
+  if (!a.step) {
+    static_cast<cx<T>*>(a.g_out)[p] = g;
+    return;
+  }
+  const double t1 = double(*a.t + 1);
+  const double bc1 = 1.0 - pow(a.g1, t1), bc2 = 1.0 - pow(a.g2, t1);
+  cx<T> xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
+  cx<T> mu = static_cast<cx<T>*>(a.mu)[p];
+  double v = a.v[p];
+  T d = static_cast<T*>(a.delta)[p];
+  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, bc1, bc2);
+  if (a.support && !in) xv = czero<T>();
+  static_cast<cx<T>*>(a.P_out)[p] = xv;
+  static_cast<cx<T>*>(a.mu)[p] = mu;
+  a.v[p] = v;
+  static_cast<T*>(a.delta)[p] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Loss terms of Eq. (8), deterministic FP64 reduction; step counter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x;
+  double f = 0.0, la = 0.0, lp = 0.0;
+  for (int i = tid; i < a.K; i += 256) f += a.fid_partial[i];
+  for (int i = tid; i < a.ntiles; i += 256) {
+    la += a.hess_partial[2 * i];
+    lp += a.hess_partial[2 * i + 1];
+  }
+  red[0][tid] = f;
+  red[1][tid] = la;
+  red[2][tid] = lp;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+      red[2][tid] += red[2][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double F = red[0][0], A = red[1][0], Ph = red[2][0];
+    const double L = F + a.alpha * A + a.beta * Ph;
+    if (a.loss4) {
+      a.loss4[0] = F;
+      a.loss4[1] = A;
+      a.loss4[2] = Ph;
+      a.loss4[3] = L;
+    }
+    if (a.hist) {
+      const int c = *a.ctr;
+      a.hist[4 * c + 0] = F;
+      a.hist[4 * c + 1] = A;
+      a.hist[4 * c + 2] = Ph;
+      a.hist[4 * c + 3] = L;
+      *a.ctr = c + 1;
+    }
+    if (!isfinite(L)) *a.flag = 1;
+    if (a.bump_t) *a.t = *a.t + 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small utilities.
+// ---------------------------------------------------------------------------
+template <class E>
+__global__ void k_fill(E* p, E val, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+// out[y][x] = (-1)^(x+y) * s * in[y][x]
+template <class T>
+__global__ void k_sign_scale(const cx<T>* in, cx<T>* out, int n, T s) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n * n) return;
+  const int y = int(i / n), x = int(i % n);
+  out[i] = scale(in[i], ((x + y) & 1) ? -s : s);
+}
+
+// Pupil of the initial state: 1 on the support, 0 elsewhere.
+template <class T>
+__global__ void k_init_pupil(cx<T>* P, const int* xlo, const int* xhi, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n * n) return;
+  const int y = p / n, x = p % n;
+  P[p] = (x >= xlo[y] && x <= xhi[y]) ? cx<T>{T(1), T(0)} : czero<T>();
+}
+
+// Initial spectrum window: (r / n) * fftshift(fft2(sqrt(I_c))) on the support of
+// the on-axis LED's window; fftshift after a DFT = (-1)^(x+y) before it.
+template <class T, int N>
+__global__ __launch_bounds__(LedShape<N>::NT) void k_init_window(const T* meas_c, cx<T>* psi, int y0, int x0,
+                                                                 int n_hi, T sc, const int* xlo, const int* xhi,
+                                                                 const cx<T>* tw) {
+  using Sh = LedShape<N>;
+  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
+  constexpr int MB1 = ceil_div(N * (N / R1), NT);
+  constexpr int MB2 = ceil_div(N * (N / R2), NT);
+  using P1f = StockhamPass<T, N, R1, 1, false, NT, MB1>;
+  using P2f = StockhamPass<T, N, R2, R1, false, NT, MB2>;
+  __shared__ cx<T> img[N * PITCH];
+  __shared__ cx<T> twl[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+  for (int p = tid; p < N * N; p += NT) {
+    const int y = p / N, x = p % N;
+    const T m = meas_c[p];
+    const T s = sqrt(m > T(0) ? m : T(0));
+    img[y * PITCH + x] = cx<T>{((x + y) & 1) ? -s : s, T(0)};
+  }
+  __syncthreads();
+  P1f::run(img, 0, N, PITCH, 1, twl, tid);
+  P2f::run(img, 0, N, PITCH, 1, twl, tid);
+  P1f::run(img, 0, N, 1, PITCH, twl, tid);
+  cx<T> Y[MB2][R2];
+  P2f::load(img, 0, N, 1, PITCH, twl, tid, Y);
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int b = tid + i * NT;
+    if (b < N * R1) {
+      const int j = b / N, x = b - j * N;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = j + r * R1;
+        if (x >= xlo[y] && x <= xhi[y]) psi[(size_t)(y0 + y) * n_hi + x0 + x] = scale(Y[i][r], sc);
+      }
+    }
+  }
+}
+
+}  // namespace elfpie

@@ -1,0 +1,108 @@
+// Kernel argument blocks shared by the host launcher and the device kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace elfpie {
+
+enum LedMode : int {
+  LED_GRAD = 1,     // residual, W and the back-projected contributions C, D
+  LED_FIELDS = 2,   // write the complex low-resolution fields
+  LED_INTENS = 4,   // write |o|^2
+  LED_LOSS = 8      // fidelity loss partial per LED
+};
+
+struct LedArgs {
+  const void* psi;      // n_hi x n_hi complex
+  const void* P;        // n_lo x n_lo complex
+  const void* meas;     // K x n_lo x n_lo real
+  void* C;              // K x S complex: conj(P) Y_k on the support (spectrum gradient part)
+  void* D;              // K x S complex: conj(M_k Psi) Y_k on the support (pupil gradient part)
+  void* fields;         // K x n_lo x n_lo complex (optional)
+  void* intens;         // K x n_lo x n_lo real (optional)
+  double* fid_partial;  // K doubles
+  const int* win;       // K x 2: (row y0, column x0) of each window
+  const int* xlo;       // n_lo: first support column of each row
+  const int* xhi;       // n_lo: last support column (xlo - 1 for an empty row)
+  const int* rowoff;    // n_lo: support index of (y, xlo[y])
+  const void* tw;       // n_lo complex forward twiddles exp(-2 pi i k / n_lo)
+  int n_hi;
+  int S;
+  int y_min, y_max;     // rows holding support pixels
+  int x_min, x_max;     // columns holding support pixels
+  double inv_scale;     // 1 / (r n_lo)
+  double eps;           // L1 smoothing
+  int mode;
+  int fidelity;
+  int norm;
+};
+
+struct HessArgs {
+  const void* Ot;       // unnormalised inverse DFT of Psi (n x n complex), no centring sign
+  void* Gt;             // out: (-1)^(x+y) G / n, ready for an unnormalised forward DFT
+  double* partial;      // 2 doubles per 16 x 16 tile: sum rho(H|O|), sum rho(H angle O)
+  int n;
+  double inv_n;
+  double alpha, beta, eta_h, eps;
+  int norm;
+  int want_grad;
+};
+
+struct UpdArgs {
+  void* x;              // parameter (psi), updated in place in step mode
+  void* mu;
+  double* v;
+  void* delta;
+  void* g_out;          // gradient output in gradient mode
+  const void* gH;       // n_hi^2 complex gradient of the Hessian terms
+  const void* C;        // K x S
+  const int* win;
+  const int* xlo;
+  const int* xhi;
+  const int* rowoff;
+  const int* tile_ptr;  // CSR over 16 x 16 tiles of the spectrum
+  const int* tile_led;
+  const long long* t;
+  int n_hi, n_lo, S, ntiles_x;
+  double g1, g2, eta;
+  int step;             // 0: write g_out; 1: Eq. 19 update
+};
+
+struct PupilArgs {
+  const void* P;        // current pupil (n_lo^2 complex)
+  void* P_out;          // updated pupil (state) in step mode
+  const void* Pf;       // pre-filtered pupil (workspace)
+  void* Pf_out;
+  const void* D;        // K x S
+  void* part;           // nch x S complex partial sums
+  void* g_out;          // gradient output (gradient mode)
+  void* mu;
+  double* v;
+  void* delta;
+  const int* xlo;
+  const int* xhi;
+  const int* rowoff;
+  const long long* t;
+  int n_lo, S, K, chunk, nch;
+  double w_c, w_e, w_k;  // Gaussian weights: centre, edge, corner
+  double g1, g2, eta;
+  int step;
+  int filter;
+  int support;
+};
+
+struct FinArgs {
+  const double* fid_partial;
+  int K;
+  const double* hess_partial;
+  int ntiles;
+  double alpha, beta;
+  double* loss4;        // optional
+  double* hist;         // optional, indexed by *ctr
+  int* ctr;
+  long long* t;         // incremented when bump_t
+  int* flag;            // set to 1 when the total loss is not finite
+  int bump_t;
+};
+
+}  // namespace elfpie

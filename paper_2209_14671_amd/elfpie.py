@@ -1,0 +1,309 @@
+"""Python binding of the gfx950 Elfpie library on torch device memory and streams.
+
+Every computation runs in the HIP library (``lib/libelfpie.so``); this module only
+allocates torch tensors, checks their shapes and dtypes, and passes pointers and
+the current stream through the C ABI of ``include/elfpie.h``.  There is no CPU or
+torch fallback: if the library is missing, importing ``Plan`` works but creating
+one raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (F32, F64, FID_AMPLITUDE, FID_INTENSITY, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
+                   PUPIL_FILTER, PUPIL_SUPPORT, ElfpieError)
+
+
+@dataclasses.dataclass
+class Problem:
+    """Problem statement (mirrors ``elfpie_problem``)."""
+    n_lo: int
+    upsample: int
+    led_k: np.ndarray               # (K, 2) (kx, ky) in 1/um
+    wavelength_um: float
+    na: float
+    dx_lo_um: float
+    alpha: float = 1e-3
+    beta: float = 1e-3
+    lr: float = 1e-2
+    gamma1: float = 0.9
+    gamma2: float = 0.999
+    eta_opt: float = 1e-8
+    eta_h: float = 1e-6
+    l1_eps: float = 0.0
+    fidelity: int = FID_INTENSITY
+    norm: int = NORM_ANISO
+    precision: int = F32
+    flags: int = PUPIL_SUPPORT
+
+    def to_c(self):
+        k = np.ascontiguousarray(np.asarray(self.led_k, dtype=np.float64).reshape(-1, 2))
+        p = _lib.ProblemC()
+        p.n_lo, p.upsample, p.K = int(self.n_lo), int(self.upsample), int(k.shape[0])
+        p.wavelength_um, p.na, p.dx_lo_um = float(self.wavelength_um), float(self.na), float(self.dx_lo_um)
+        p.led_k = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.alpha, p.beta, p.lr = float(self.alpha), float(self.beta), float(self.lr)
+        p.gamma1, p.gamma2, p.eta_opt = float(self.gamma1), float(self.gamma2), float(self.eta_opt)
+        p.eta_h, p.l1_eps = float(self.eta_h), float(self.l1_eps)
+        p.fidelity, p.norm, p.precision, p.flags = int(self.fidelity), int(self.norm), int(self.precision), int(self.flags)
+        return p, k  # keep k alive while p is used
+
+
+def problem_from_optics(optics, led_k, **kw) -> Problem:
+    """Problem from a ``synth.Optics`` description and LED wave-vectors."""
+    return Problem(n_lo=optics.n_lo, upsample=optics.upsample, led_k=np.asarray(led_k, float),
+                   wavelength_um=optics.wavelength_um, na=optics.na, dx_lo_um=optics.dx_lo_um, **kw)
+
+
+def workspace_bytes(problem: Problem) -> int:
+    lib = _lib.load()
+    p, _keep = problem.to_c()
+    n = ctypes.c_size_t(0)
+    _lib.check(lib.elfpie_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclasses.dataclass
+class State:
+    """Optimiser state of Eq. (19) on the device; saving these tensors is a checkpoint."""
+    psi: torch.Tensor
+    P: torch.Tensor
+    mu_psi: torch.Tensor
+    v_psi: torch.Tensor
+    delta_psi: torch.Tensor
+    mu_P: torch.Tensor
+    v_P: torch.Tensor
+    delta_P: torch.Tensor
+    t: torch.Tensor
+
+    def to_c(self):
+        s = _lib.StateC()
+        for f in dataclasses.fields(self):
+            setattr(s, f.name, getattr(self, f.name).data_ptr())
+        return s
+
+    def clone(self) -> "State":
+        return State(*(getattr(self, f.name).clone() for f in dataclasses.fields(self)))
+
+    def state_dict(self):
+        return {f.name: getattr(self, f.name) for f in dataclasses.fields(self)}
+
+
+class Plan:
+    """A validated problem with its device workspace (owned here, as a torch tensor)."""
+
+    def __init__(self, problem: Problem, device=None):
+        self.lib = _lib.load()
+        self.problem = problem
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        p, _keep = problem.to_c()
+        n = ctypes.c_size_t(0)
+        _lib.check(self.lib.elfpie_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(n.value) + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            handle = ctypes.c_void_p(0)
+            _lib.check(self.lib.elfpie_plan_create(ctypes.byref(p), ctypes.c_void_p(base + off),
+                                                   ctypes.c_size_t(int(n.value)), ctypes.byref(handle)))
+        self.handle = handle
+        info = (ctypes.c_int32 * 5)()
+        _lib.check(self.lib.elfpie_plan_info(self.handle, info), self.handle)
+        self.n_hi, self.S, self.K, self.n_lo, self.kc = (int(v) for v in info)
+        self.rdtype = torch.float32 if problem.precision == F32 else torch.float64
+        self.cdtype = torch.complex64 if problem.precision == F32 else torch.complex128
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.elfpie_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument checks ------------------------------------------------------------
+    def _need(self, t, shape, dtype, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, plan is on {self.device}")
+        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+        return t
+
+    def _check(self, status):
+        _lib.check(status, self.handle)
+
+    @property
+    def spec_shape(self):
+        return (self.n_hi, self.n_hi)
+
+    @property
+    def pupil_shape(self):
+        return (self.n_lo, self.n_lo)
+
+    @property
+    def stack_shape(self):
+        return (self.K, self.n_lo, self.n_lo)
+
+    # -- state ----------------------------------------------------------------------
+    def new_state(self, psi0: torch.Tensor, P0: torch.Tensor) -> State:
+        """Fresh Eq. (19) state (mu = v = 0, delta = lr^2, t = 0) around copies of psi0, P0."""
+        A, B = self.spec_shape, self.pupil_shape
+        kw = dict(device=self.device)
+        d0 = self.problem.lr ** 2
+        return State(
+            psi=self._need(psi0, A, self.cdtype, "psi0").clone(), P=self._need(P0, B, self.cdtype, "P0").clone(),
+            mu_psi=torch.zeros(A, dtype=self.cdtype, **kw), v_psi=torch.zeros(A, dtype=torch.float64, **kw),
+            delta_psi=torch.full(A, d0, dtype=self.rdtype, **kw),
+            mu_P=torch.zeros(B, dtype=self.cdtype, **kw), v_P=torch.zeros(B, dtype=torch.float64, **kw),
+            delta_P=torch.full(B, d0, dtype=self.rdtype, **kw),
+            t=torch.zeros(1, dtype=torch.int64, **kw))
+
+    def init_state(self, meas: torch.Tensor) -> State:
+        """Initial guess from the on-axis image (library kernel), all moments reset."""
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        A, B = self.spec_shape, self.pupil_shape
+        kw = dict(device=self.device)
+        st = State(psi=torch.empty(A, dtype=self.cdtype, **kw), P=torch.empty(B, dtype=self.cdtype, **kw),
+                   mu_psi=torch.empty(A, dtype=self.cdtype, **kw), v_psi=torch.empty(A, dtype=torch.float64, **kw),
+                   delta_psi=torch.empty(A, dtype=self.rdtype, **kw),
+                   mu_P=torch.empty(B, dtype=self.cdtype, **kw), v_P=torch.empty(B, dtype=torch.float64, **kw),
+                   delta_P=torch.empty(B, dtype=self.rdtype, **kw), t=torch.empty(1, dtype=torch.int64, **kw))
+        sc = st.to_c()
+        self._check(self.lib.elfpie_init_state(self.handle, _ptr(meas), ctypes.byref(sc), _stream()))
+        return st
+
+    def _state_c(self, st: State):
+        A, B = self.spec_shape, self.pupil_shape
+        self._need(st.psi, A, self.cdtype, "psi")
+        self._need(st.P, B, self.cdtype, "P")
+        self._need(st.mu_psi, A, self.cdtype, "mu_psi")
+        self._need(st.v_psi, A, torch.float64, "v_psi")
+        self._need(st.delta_psi, A, self.rdtype, "delta_psi")
+        self._need(st.mu_P, B, self.cdtype, "mu_P")
+        self._need(st.v_P, B, torch.float64, "v_P")
+        self._need(st.delta_P, B, self.rdtype, "delta_P")
+        self._need(st.t, (1,), torch.int64, "t")
+        return st.to_c()
+
+    # -- entry points ---------------------------------------------------------------
+    def forward(self, psi, P, meas=None, fields=False, intens=False, loss=False):
+        """Returns dict with optional 'fields', 'intens', 'loss4' (Eq. 1, Eq. 8)."""
+        self._need(psi, self.spec_shape, self.cdtype, "psi")
+        self._need(P, self.pupil_shape, self.cdtype, "P")
+        if meas is not None:
+            self._need(meas, self.stack_shape, self.rdtype, "meas")
+        out = {}
+        kw = dict(device=self.device)
+        f = torch.empty(self.stack_shape, dtype=self.cdtype, **kw) if fields else None
+        i = torch.empty(self.stack_shape, dtype=self.rdtype, **kw) if intens else None
+        l4 = torch.empty(4, dtype=torch.float64, **kw) if loss else None
+        if loss and meas is None:
+            raise ValueError("loss needs meas")
+        self._check(self.lib.elfpie_forward(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(f), _ptr(i),
+                                            _ptr(l4), _stream()))
+        if fields:
+            out["fields"] = f
+        if intens:
+            out["intens"] = i
+        if loss:
+            out["loss4"] = l4
+        return out
+
+    def grad(self, psi, P, meas, want_gP=True):
+        """(loss4, dL/d conj(psi), dL_fid/d conj(P) or None) at (psi, P) (Eq. 8, 15, 18)."""
+        self._need(psi, self.spec_shape, self.cdtype, "psi")
+        self._need(P, self.pupil_shape, self.cdtype, "P")
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        kw = dict(device=self.device)
+        g = torch.empty(self.spec_shape, dtype=self.cdtype, **kw)
+        gP = torch.empty(self.pupil_shape, dtype=self.cdtype, **kw) if want_gP else None
+        l4 = torch.empty(4, dtype=torch.float64, **kw)
+        self._check(self.lib.elfpie_grad(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(g), _ptr(gP),
+                                         _ptr(l4), _stream()))
+        return l4, g, gP
+
+    def step(self, st: State, meas, want_loss=True):
+        sc = self._state_c(st)
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        l4 = torch.empty(4, dtype=torch.float64, device=self.device) if want_loss else None
+        self._check(self.lib.elfpie_step(self.handle, ctypes.byref(sc), _ptr(meas), _ptr(l4), _stream()))
+        return l4
+
+    def run(self, st: State, meas, n_iter: int, history=True, checked=False):
+        sc = self._state_c(st)
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        h = torch.empty((max(n_iter, 1), 4), dtype=torch.float64, device=self.device) if history else None
+        self._check(self.lib.elfpie_run(self.handle, ctypes.byref(sc), _ptr(meas), int(n_iter), _ptr(h),
+                                        1 if checked else 0, _stream()))
+        return h[:n_iter] if history else None
+
+    def object_from_spectrum(self, psi):
+        self._need(psi, self.spec_shape, self.cdtype, "psi")
+        o = torch.empty_like(psi)
+        self._check(self.lib.elfpie_object_from_spectrum(self.handle, _ptr(psi), _ptr(o), _stream()))
+        return o
+
+    def spectrum_from_object(self, obj):
+        self._need(obj, self.spec_shape, self.cdtype, "obj")
+        p = torch.empty_like(obj)
+        self._check(self.lib.elfpie_spectrum_from_object(self.handle, _ptr(obj), _ptr(p), _stream()))
+        return p
+
+    def stage_timing(self, st: State, meas, n_rep: int = 20):
+        """Mean ms per launch of each stage in isolation (see elfpie_stage_timing)."""
+        sc = self._state_c(st)
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        ms = (ctypes.c_float * 8)()
+        self._check(self.lib.elfpie_stage_timing(self.handle, ctypes.byref(sc), _ptr(meas), int(n_rep), ms,
+                                                 _stream()))
+        names = ["led", "obj_inverse", "hessian", "obj_forward", "psi_gather", "pupil", "loss"]
+        return {n: float(ms[i]) for i, n in enumerate(names)}
+
+
+class ElfpieLoss(torch.autograd.Function):
+    """L(psi, P) of Eq. (8) as an autograd function.  backward calls the library's
+    closed-form gradient (Eq. 15, 18), recomputing the per-LED fields.  torch stores
+    2 dL/d(conj z) as the gradient of a real loss wrt a complex z."""
+
+    @staticmethod
+    def forward(ctx, psi, P, plan: Plan, meas):
+        out = plan.forward(psi.detach().contiguous(), P.detach().contiguous(), meas, loss=True)
+        ctx.plan = plan
+        ctx.save_for_backward(psi, P, meas)
+        return out["loss4"][3].clone()
+
+    @staticmethod
+    def backward(ctx, g_out):
+        psi, P, meas = ctx.saved_tensors
+        _, g, gP = ctx.plan.grad(psi.detach().contiguous(), P.detach().contiguous(), meas,
+                                 want_gP=ctx.needs_input_grad[1])
+        s = (2.0 * g_out).to(ctx.plan.rdtype)
+        gpsi = g * s if ctx.needs_input_grad[0] else None
+        gp = gP * s if (gP is not None and ctx.needs_input_grad[1]) else None
+        return gpsi, gp, None, None
+
+
+def elfpie_loss(psi, P, plan: Plan, meas):
+    return ElfpieLoss.apply(psi, P, plan, meas)
