@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the Elfpie iteration on one MI355X.
+
+Workload: the paper-shaped single field of view -- FP32, 512 x 512 high-resolution
+spectrum, 15 x 15 LEDs (K = 225), 128 x 128 low-resolution images, Zernike-aberrated
+pupil, LED position jitter, vignetting, Poisson / Gaussian / salt-and-pepper noise --
+built from seeded synthetic inputs.  One step = one full iteration (all LEDs, object
+branch, spectrum and pupil updates, loss).  The measured stack is simulated on the
+GPU with the library's own forward model from the seeded ground truth; the CPU
+baseline leg re-simulates it with the oracle.
+
+Prints one JSON line (see the keys below).  Only one GPU is used: --gpus above 1 is
+refused.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LED sub-image updates/sec (K×iters/s) at K=225, 128² low-res; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2209_14671_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def byte_model(K, S, B, A):
+    """Algorithmic HBM bytes (FP32): per-LED kernel and whole iteration."""
+    led_kernel = K * (24 * S + 4 * B) + 8 * S          # window of psi + image in, C and D out; P once
+    iteration = K * (40 * S + 4 * B) + 112 * A         # + C, D re-read; object FFTs, Hessian, update
+    return led_kernel, iteration
+
+
+def measured_traffic(src_hash):
+    """HBM traffic of the per-LED kernel from the committed rocprofv3 counter summary,
+    valid only while the kernel sources still hash to the value recorded there."""
+    path = os.path.join(ROOT, "profiles", "k_led_config2_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
+    """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
+    import oracle as orc
+    import synth
+    o = case.optics
+    sim = orc.problem_from_optics(o, case.led_k_true)
+    clean = orc.intensities(orc.spectrum_from_object(case.obj), case.pupil, sim)
+    meas = synth.degrade(clean, case.degradation, case.noise_seed)
+    prob = orc.problem_from_optics(o, case.led_k, flags=flags)
+    st = orc.init_state(meas, prob)
+    n = 0
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    while n < max_iter and (time.perf_counter() - t0) < budget_s:
+        st, _ = orc.step(st, meas, prob)
+        n += 1
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    K = prob.K
+    return {"value": K * n / wall, "unit": "LED-updates/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"{n} oracle iterations of the same workload (NumPy FP64), {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stage-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    case = synth.config_case(2)
+    o = case.optics
+    flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+
+    # simulate the measured stack on the GPU (library forward model, true LED positions)
+    log("simulating the measured stack")
+    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=E.F32), device=dev)
+    obj = torch.from_numpy(case.obj).to(torch.complex64).to(dev)
+    psi_true = sim.spectrum_from_object(obj)
+    p_true = torch.from_numpy(case.pupil).to(torch.complex64).to(dev)
+    clean = sim.forward(psi_true, p_true, intens=True)["intens"].cpu().numpy().astype(np.float64)
+    meas_np = synth.degrade(clean, case.degradation, case.noise_seed)
+    meas = torch.from_numpy(meas_np).to(torch.float32).to(dev)
+    sim.close()
+
+    plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=E.F32, flags=flags), device=dev)
+    K, S, B, A = plan.K, plan.S, plan.n_lo ** 2, plan.n_hi ** 2
+    st = plan.init_state(meas)
+    stream = torch.cuda.current_stream()
+
+    log(f"warmup {args.warmup} iterations")
+    if args.warmup:
+        plan.run(st, meas, args.warmup)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} iterations")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    hist = plan.run(st, meas, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / max(args.steps, 1)
+    value = K * args.steps / (ms / 1e3)
+    h = hist.cpu().numpy()
+    if not np.all(np.isfinite(h)):
+        raise RuntimeError("non-finite loss during the timed run")
+    log(f"{ms_step * 1e3:.1f} us/iteration, loss {h[0, 3]:.4e} -> {h[-1, 3]:.4e} (wall {wall:.3f} s)")
+
+    # per-kernel timing, HIP events around back-to-back launches on this stream
+    log("per-stage timing")
+    stages = plan.stage_timing(st, meas, args.stage_reps)
+    led_bytes, it_bytes = byte_model(K, S, B, A)
+    led_s = stages["led"] * 1e-3
+    src_hash = kernel_source_hash()
+    traffic = measured_traffic(src_hash)
+    roof = {"bound": "hbm", "achieved": round(led_bytes / led_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(led_bytes / led_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_led<float,128>", "algorithmic_bytes": led_bytes, "avg_launch_ms": round(stages["led"], 4)}
+    it_gbs = it_bytes / (ms_step * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "LED-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single FOV, FP32: 512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, "
+                               "Zernike pupil, noise + salt-and-pepper + vignetting + LED jitter",
+                   "K": K, "n_lo": plan.n_lo, "n_hi": plan.n_hi, "support_px": S, "learn_pupil": True},
+        "roofline": roof,
+        "iteration_roofline": {"algorithmic_bytes": it_bytes, "achieved_GBs": round(it_gbs, 1),
+                               "frac": round(it_gbs / HBM_PEAK_GBS, 4)},
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "source_hash": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(case, flags)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

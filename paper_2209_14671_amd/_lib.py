@@ -57,7 +57,8 @@ _LIB = None
 
 
 def library_path() -> str:
-    return _build.LIB
+    """The in-tree build, or the library named by ELFPIE_LIB (an alternative build)."""
+    return os.environ.get("ELFPIE_LIB") or _build.LIB
 
 
 def load() -> ctypes.CDLL:

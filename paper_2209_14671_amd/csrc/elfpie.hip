@@ -1,7 +1,7 @@
 // Host side of the Elfpie library: plan construction (LED windows, pupil support,
 // coverage lists), workspace carving, the launch sequence of one iteration
-// (Algorithm 1 of arXiv 2209.14671) with its two independent branches on two
-// streams, HIP-graph replay for multi-iteration runs, and the C ABI.
+// (Algorithm 1 of arXiv 2209.14671), HIP-graph replay for multi-iteration runs,
+// and the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +21,11 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr size_t kAlign = 256;
+constexpr int kGraphIters = 8;  // iterations per replayed graph
+#ifndef ELFPIE_FUSE_PUPIL
+#define ELFPIE_FUSE_PUPIL 1
+#endif
+constexpr bool kFusePupil = ELFPIE_FUSE_PUPIL != 0;  // pupil partial sums ride in the update launch
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -31,7 +36,7 @@ struct Tables {
   int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
   int kc = 0;                      // LED nearest the optical axis
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
-  int nch = 0, chunk = 16;         // pupil reduction chunks
+  int nch = 0, chunk = kPupilChunk;  // pupil reduction chunks
   std::vector<int> win;            // K x 2 (y0, x0)
   std::vector<int> xlo, xhi, rowoff;
   std::vector<int> tile_ptr, tile_led;
@@ -141,7 +146,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
     }
   }
 
-  // coverage lists: 16 x 16 tiles of the spectrum -> LEDs whose support box meets them
+  // coverage lists: 16 x 16 tiles of the spectrum -> LEDs whose support box meets
+  // them, in ascending LED order
   tb->ntiles_x = tb->n_hi / 16;
   const int ntiles = tb->ntiles_x * tb->ntiles_x;
   std::vector<std::vector<int>> lists(ntiles);
@@ -187,7 +193,7 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_part = take((size_t)tb->nch * S * cxb);
   tb->o_Pf = take((size_t)n * n * cxb);
   tb->o_fid = take(tb->K * sizeof(double));
-  tb->o_hess = take((size_t)2 * ntiles * sizeof(double));
+  tb->o_hess = take((size_t)2 * tb->ntiles_x * tb->ntiles_x * sizeof(double));
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
@@ -202,10 +208,10 @@ struct elfpie_plan {
   Tables tb;
   char* ws = nullptr;
   int device = 0;
-  hipStream_t cap = nullptr, side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;  // graph capture stream (captures cannot use the legacy NULL stream)
+  hipGraphExec_t gexec = nullptr;   // non-null once the graphs below exist
+  hipGraphExec_t gexecs[2] = {nullptr, nullptr};
+  hipGraph_t graphs[2] = {nullptr, nullptr};
   elfpie_state gkey{};
   const void* gkey_meas = nullptr;
   const double* gkey_hist = nullptr;
@@ -289,6 +295,12 @@ struct Ops {
     return ELFPIE_OK;
   }
 
+  template <int N, bool INV, bool COLS>
+  static void launch_lines(const C* in, C* out, const C* tw, hipStream_t s) {
+    using Sh = BigShape<N, COLS>;
+    k_fft_lines<T, N, INV, COLS><<<N / Sh::RPB, Sh::NT, 0, s>>>(in, out, tw);
+  }
+
   template <bool INV, bool COLS>
   static elfpie_status lines(elfpie_plan* pl, const void* in, void* out, hipStream_t s) {
     const Tables& tb = pl->tb;
@@ -296,12 +308,10 @@ struct Ops {
     const C* i = static_cast<const C*>(in);
     C* o = static_cast<C*>(out);
     switch (tb.n_hi) {
-      case 128: k_fft_lines<T, 128, INV, COLS><<<128 / BigShape<128>::RPB, BigShape<128>::NT, 0, s>>>(i, o, tw); break;
-      case 256: k_fft_lines<T, 256, INV, COLS><<<256 / BigShape<256>::RPB, BigShape<256>::NT, 0, s>>>(i, o, tw); break;
-      case 512: k_fft_lines<T, 512, INV, COLS><<<512 / BigShape<512>::RPB, BigShape<512>::NT, 0, s>>>(i, o, tw); break;
-      case 1024:
-        k_fft_lines<T, 1024, INV, COLS><<<1024 / BigShape<1024>::RPB, BigShape<1024>::NT, 0, s>>>(i, o, tw);
-        break;
+      case 128: launch_lines<128, INV, COLS>(i, o, tw, s); break;
+      case 256: launch_lines<256, INV, COLS>(i, o, tw, s); break;
+      case 512: launch_lines<512, INV, COLS>(i, o, tw, s); break;
+      case 1024: launch_lines<1024, INV, COLS>(i, o, tw, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
     LAUNCH_CHECK(pl, "k_fft_lines");
@@ -342,8 +352,10 @@ struct Ops {
     return ELFPIE_OK;
   }
 
-  static elfpie_status psi_update(elfpie_plan* pl, const elfpie_state* st, void* g_out, const void* gH,
-                                  hipStream_t s) {
+  // LED gather + (gradient | Eq. 19 update) on 16 x 16 tiles, with the pupil partial
+  // sums (and pre-filter) as trailing blocks of the launch.
+  static elfpie_status update(elfpie_plan* pl, const elfpie_state* st, void* g_out, const void* gH,
+                              const void* P, bool pupil, bool prefilter, hipStream_t s) {
     const Tables& tb = pl->tb;
     UpdArgs a{};
     if (st) {
@@ -366,12 +378,26 @@ struct Ops {
     a.n_lo = tb.n_lo;
     a.S = tb.S;
     a.ntiles_x = tb.ntiles_x;
+    a.ntiles = tb.ntiles_x * tb.ntiles_x;
     a.g1 = pl->prob.gamma1;
     a.g2 = pl->prob.gamma2;
     a.eta = pl->prob.eta_opt;
     a.step = st ? 1 : 0;
-    k_psi_update<T><<<tb.ntiles_x * tb.ntiles_x, 256, 0, s>>>(a);
-    LAUNCH_CHECK(pl, "k_psi_update");
+    PupilArgs pa = pupil_args(pl, P);
+    pa.filter = prefilter ? 1 : 0;
+    int pblocks = 0;
+    if (pupil) {
+      pblocks = ((tb.S + 255) / 256) * tb.nch;
+      if (prefilter) pblocks += (tb.n_lo * tb.n_lo + 255) / 256;
+    }
+    a.pupil_blocks = pblocks;
+    if (kFusePupil) {
+      k_update<T><<<a.ntiles + pblocks, 256, 0, s>>>(a, pa);
+    } else {
+      if (pblocks) k_pupil_partial<T><<<pblocks, 256, 0, s>>>(pa);
+      k_update<T><<<a.ntiles, 256, 0, s>>>(a, pa);
+    }
+    LAUNCH_CHECK(pl, "k_update");
     return ELFPIE_OK;
   }
 
@@ -401,20 +427,6 @@ struct Ops {
     a.filter = (pl->prob.flags & ELFPIE_PUPIL_FILTER) ? 1 : 0;
     a.support = (pl->prob.flags & ELFPIE_PUPIL_SUPPORT) ? 1 : 0;
     return a;
-  }
-
-  // partial sums of the pupil contributions (and the pre-filter when stepping)
-  static elfpie_status pupil_reduce(elfpie_plan* pl, const void* P, bool prefilter, hipStream_t s) {
-    const Tables& tb = pl->tb;
-    PupilArgs a = pupil_args(pl, P);
-    dim3 g1((tb.S + 255) / 256, tb.nch);
-    k_pupil_partial<T><<<g1, 256, 0, s>>>(a);
-    LAUNCH_CHECK(pl, "k_pupil_partial");
-    if (prefilter) {
-      k_pupil_gauss<T><<<(tb.n_lo * tb.n_lo + 255) / 256, 256, 0, s>>>(a);
-      LAUNCH_CHECK(pl, "k_pupil_gauss");
-    }
-    return ELFPIE_OK;
   }
 
   static elfpie_status pupil_finish(elfpie_plan* pl, const void* P, const elfpie_state* st, void* g_out,
@@ -456,30 +468,26 @@ struct Ops {
     return ELFPIE_OK;
   }
 
-  // One gradient evaluation (st == NULL) or one update step (st != NULL).
-  // The LED branch runs on `s`; the object branch (inverse transform, Hessian,
-  // forward transform) runs concurrently on the plan's side stream.
+  // One gradient evaluation (st == NULL) or one update step (st != NULL), all on
+  // stream `s`: object branch (inverse transform, Hessian, forward transform), the
+  // per-LED kernel, the spectrum update (gather, Eq. 19; pupil partial sums in the
+  // same launch), the pupil update and the loss.
+  // Kernels on one queue dispatch back to back; a join across queues costs more
+  // than the overlap it buys (the per-LED kernel fills every CU).
   static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
                                  const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
                                  hipStream_t s) {
     const Tables& tb = pl->tb;
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
-    HIP_TRY(pl, hipEventRecord(pl->ev_fork, s));
-    HIP_TRY(pl, hipStreamWaitEvent(pl->side, pl->ev_fork, 0));
     elfpie_status r;
-    if ((r = obj_inverse(pl, psi, T1, pl->side)) != ELFPIE_OK) return r;
-    if ((r = hessian(pl, true, T1, T2, pl->side)) != ELFPIE_OK) return r;
-    if ((r = obj_forward(pl, T2, T2, pl->side)) != ELFPIE_OK) return r;
-    HIP_TRY(pl, hipEventRecord(pl->ev_join, pl->side));
+    if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
+    if ((r = hessian(pl, true, T1, T2, s)) != ELFPIE_OK) return r;
+    if ((r = obj_forward(pl, T2, T2, s)) != ELFPIE_OK) return r;
     if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s)) != ELFPIE_OK) return r;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
-    if (learn_p) {
-      const bool pre = st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
-      if ((r = pupil_reduce(pl, P, pre, s)) != ELFPIE_OK) return r;
-    }
-    HIP_TRY(pl, hipStreamWaitEvent(s, pl->ev_join, 0));
-    if ((r = psi_update(pl, st, g_psi, T2, s)) != ELFPIE_OK) return r;
+    const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
+    if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s)) != ELFPIE_OK) return r;
     if (learn_p) {
       if ((r = pupil_finish(pl, P, st, g_P, s)) != ELFPIE_OK) return r;
     }
@@ -589,11 +597,8 @@ struct Ops {
           case 1: r = obj_inverse(pl, st->psi, T1, s); break;
           case 2: r = hessian(pl, true, T1, T2, s); break;
           case 3: r = obj_forward(pl, T2, G, s); break;
-          case 4: r = psi_update(pl, nullptr, G, T2, s); break;
-          case 5:
-            r = pupil_reduce(pl, st->P, true, s);
-            if (r == ELFPIE_OK) r = pupil_finish(pl, st->P, nullptr, gP, s);
-            break;
+          case 4: r = update(pl, nullptr, T1, G, st->P, true, true, s); break;
+          case 5: r = pupil_finish(pl, st->P, nullptr, gP, s); break;
           case 6: r = finalize(pl, l4, nullptr, nullptr, false, s); break;
         }
       }
@@ -743,23 +748,19 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
   const int zero = 0;
   if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
     return cleanup(st);
-  if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)
-    return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream / event creation failed"));
+  if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));
   *out = pl;
   return ELFPIE_OK;
 }
 
 elfpie_status elfpie_plan_destroy(elfpie_plan* pl) {
   if (!pl) return ELFPIE_E_INVALID;
-  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
-  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
-  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  for (int g = 0; g < 2; ++g) {
+    if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
+    if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
+  }
   if (pl->cap) (void)hipStreamDestroy(pl->cap);
-  if (pl->side) (void)hipStreamDestroy(pl->side);
   delete pl;
   return ELFPIE_OK;
 }
@@ -831,37 +832,44 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   k_fill<int><<<1, 64, 0, s>>>(flag, 0, 1);
   LAUNCH_CHECK(pl, "k_fill");
   if (n_iter == 0) return ELFPIE_OK;
-  // the graph bakes in every pointer of the iteration: reuse it only for the same ones
+  // the graphs bake in every pointer of the iteration: reuse them only for the same ones
   const bool same = pl->gexec && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
                     pl->gkey_hist == d_loss_hist;
   if (!same) {
-    // (re)capture one iteration on the plan's capture stream
-    if (pl->gexec) {
-      (void)hipGraphExecDestroy(pl->gexec);
-      pl->gexec = nullptr;
+    // (re)capture: one graph of kGraphIters iterations and one of a single iteration
+    for (int g = 0; g < 2; ++g) {
+      if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
+      if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
+      pl->gexecs[g] = nullptr;
+      pl->graphs[g] = nullptr;
     }
-    if (pl->graph) {
-      (void)hipGraphDestroy(pl->graph);
-      pl->graph = nullptr;
+    pl->gexec = nullptr;
+    for (int g = 0; g < 2; ++g) {
+      const int reps = g == 0 ? kGraphIters : 1;
+      HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+      elfpie_status r = ELFPIE_OK;
+      for (int it = 0; it < reps && r == ELFPIE_OK; ++it)
+        r = dispatch(pl, [&](auto ops) {
+          return decltype(ops)::iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, d_loss_hist,
+                                          pl->cap);
+        });
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(pl->cap, &gr);
+      if (r != ELFPIE_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return r;
+      }
+      HIP_TRY(pl, ec);
+      pl->graphs[g] = gr;
+      HIP_TRY(pl, hipGraphInstantiate(&pl->gexecs[g], gr, nullptr, nullptr, 0));
     }
-    HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    const elfpie_status r = dispatch(pl, [&](auto ops) {
-      return decltype(ops)::iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, d_loss_hist, pl->cap);
-    });
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(pl->cap, &g);
-    if (r != ELFPIE_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return r;
-    }
-    HIP_TRY(pl, ec);
-    pl->graph = g;
-    HIP_TRY(pl, hipGraphInstantiate(&pl->gexec, g, nullptr, nullptr, 0));
+    pl->gexec = pl->gexecs[0];
     pl->gkey = *st;
     pl->gkey_meas = meas;
     pl->gkey_hist = d_loss_hist;
   }
-  for (int i = 0; i < n_iter; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexec, s));
+  for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[0], s));
+  for (int i = 0; i < n_iter % kGraphIters; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[1], s));
   if (checked) {
     HIP_TRY(pl, hipStreamSynchronize(s));
     int h = 0;

@@ -16,6 +16,8 @@
 
 namespace elfpie {
 
+constexpr int kMaxLo = 256;  // largest low-resolution side any kernel stages in LDS
+
 // ---------------------------------------------------------------------------
 // Deterministic block reduction of a double (fixed shuffle and slot order).
 // ---------------------------------------------------------------------------
@@ -54,10 +56,17 @@ __device__ __forceinline__ T inv_norm(T s2, T eps) {
 // ---------------------------------------------------------------------------
 // Per-LED fused kernel: one workgroup per LED, the n_lo x n_lo tile in LDS.
 // ---------------------------------------------------------------------------
+#ifndef ELFPIE_LED_LINES
+#define ELFPIE_LED_LINES 0  // 1: each row / column transform by one wavefront (LineFft)
+#endif
+
 template <int N> struct LedShape;
-template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 4, R2 = 8; };
+template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 8, R2 = 4; };
 template <> struct LedShape<64> { static constexpr int NT = 256, R1 = 8, R2 = 8; };
-template <> struct LedShape<128> { static constexpr int NT = 1024, R1 = 16, R2 = 8; };
+#ifndef ELFPIE_LED128_NT
+#define ELFPIE_LED128_NT 1024
+#endif
+template <> struct LedShape<128> { static constexpr int NT = ELFPIE_LED128_NT, R1 = 16, R2 = 8; };
 
 // Steps of the per-LED branch (one LED per workgroup):
 //   gather   X = P * M_k Psi on the pupil support                  (Eq. 1)
@@ -67,24 +76,30 @@ template <> struct LedShape<128> { static constexpr int NT = 1024, R1 = 16, R2 =
 //   adjoint  q = grad^T omega, dL/d(conj o) = q o  or  q o / (2|o|)  (Eq. 11 / Eq. 10)
 //   forward  Y = F_B^H dL/d(conj o): all rows, then support columns
 //   outputs  C = conj(P) Y and D = conj(M_k Psi) Y on the support    (Eq. 9, Eq. 18)
+#if ELFPIE_LED_LINES
+// Each 1-D transform of a row or column is done by L lanes of one wavefront
+// (LineFft), so the block synchronises only between the row and column phases.
 template <class T, int N>
 __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   using Sh = LedShape<N>;
-  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
-  static_assert(R1 * R2 == N, "two-pass decomposition");
-  constexpr int MB1 = ceil_div(N * (N / R1), NT);
-  constexpr int MB2 = ceil_div(N * (N / R2), NT);
-  using P1i = StockhamPass<T, N, R1, 1, true, NT, MB1>;
-  using P2i = StockhamPass<T, N, R2, R1, true, NT, MB2>;
-  using P1f = StockhamPass<T, N, R1, 1, false, NT, MB1>;
-  using P2f = StockhamPass<T, N, R2, R1, false, NT, MB2>;
+  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2;
+  constexpr int NW = NT / 64;                     // wavefronts per block
+  using LF = LineFft<T, N, R1, R2, N + N / R1>;
+  constexpr int PITCH = N + LF::L, L = LF::L, LPW = LF::LPW, B2 = LF::B2;
+  constexpr int GPW = (N / LPW) / NW;             // dense line groups per wavefront
+  static_assert(GPW * NW * LPW == N, "dense phases split evenly over the wavefronts");
+  constexpr int PPT = N * N / NT;                 // pixels per thread in the gather
+  constexpr int GB = PPT < 8 ? PPT : 8;           // loads kept in flight per batch
+  static_assert(GPW * B2 * R2 == PPT, "pixel ownership after the column phase");
 
   __shared__ cx<T> img[N * PITCH];
   __shared__ cx<T> twl[N];
   __shared__ int sxlo[N], sxhi[N], sroff[N];
-  __shared__ double red[NT / 64];
+  __shared__ double red[NW];
 
   const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int grp = lane / L, jl = lane % L;        // line within the wavefront's group, lane in line
   const int k = blockIdx.x;
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
@@ -98,42 +113,70 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
   __syncthreads();
 
-  // gather (zeros off the support)
-  for (int p = tid; p < N * N; p += NT) {
-    const int y = p / N, x = p % N;
-    cx<T> v = czero<T>();
-    if (x >= sxlo[y] && x <= sxhi[y]) v = P[p] * win[(size_t)y * a.n_hi + x];
-    img[y * PITCH + x] = v;
+  // gather X = P * window, zeros off the support.  Every address of the window is
+  // valid, so the loads are unconditional and a batch of them is in flight at once.
+#pragma unroll
+  for (int i0 = 0; i0 < PPT; i0 += GB) {
+    cx<T> pv[GB], wv[GB];
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int p = tid + (i0 + i) * NT;
+      pv[i] = P[p];
+      wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
+    }
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int p = tid + (i0 + i) * NT;
+      const int y = p / N, x = p % N;
+      const bool in = x >= sxlo[y] && x <= sxhi[y];
+      img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
+    }
   }
   __syncthreads();
 
-  // inverse DFT: rows that hold support pixels, then every column
+  // inverse DFT along the rows that hold support pixels (the others are zero)
   const int nband = a.y_max - a.y_min + 1;
-  P1i::run(img, a.y_min, nband, PITCH, 1, twl, tid);
-  P2i::run(img, a.y_min, nband, PITCH, 1, twl, tid);
-  P1i::run(img, 0, N, 1, PITCH, twl, tid);
-  cx<T> o[MB2][R2];
-  P2i::load(img, 0, N, 1, PITCH, twl, tid, o);
+  for (int g = wave; g * LPW < nband; g += NW) {
+    const int t = a.y_min + g * LPW + grp;
+    const bool ok = t <= a.y_max;
+    cx<T> v[B2][R2];
+    LF::template run<true, true>(img, twl, t, jl, ok, v);
+    LF::template store<true>(img, t, jl, ok, v);
+  }
+  __syncthreads();
+  // ... then along every column; the results stay in registers:
+  // o[gi][b][r] is pixel (row j + b L + r R1, column (wave + gi NW) LPW + grp)
+  cx<T> o[GPW][B2][R2];
+#pragma unroll
+  for (int gi = 0; gi < GPW; ++gi) {
+    const int t = (wave + gi * NW) * LPW + grp;
+    LF::template run<true, false>(img, twl, t, jl, true, o[gi]);
+  }
   __syncthreads();
 
-  // register (i, r) holds pixel y = j + r R1, x = m, where b = tid + i NT = j N + m
   const T sc = T(a.inv_scale);
   const T eps = T(a.eps);
   const int mode = a.mode;
   const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
   const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
   T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
-  T ev[MB2][R2];
 #pragma unroll
-  for (int i = 0; i < MB2; ++i) {
-    const int b = tid + i * NT;
-    if (b < N * R1) {
-      const int j = b / N, x = b - j * N;
+  for (int gi = 0; gi < GPW; ++gi) {
+    const int x = (wave + gi * NW) * LPW + grp;
+    T mv[B2][R2];
+    if (need_e) {
+#pragma unroll
+      for (int b = 0; b < B2; ++b)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) mv[b][r] = meas[(size_t)(jl + b * L + r * R1) * N + x];
+    }
+#pragma unroll
+    for (int b = 0; b < B2; ++b)
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
-        const int y = j + r * R1;
-        const cx<T> ov = scale(o[i][r], sc);
-        o[i][r] = ov;
+        const int y = jl + b * L + r * R1;
+        const cx<T> ov = scale(o[gi][b][r], sc);
+        o[gi][b][r] = ov;
         const size_t pix = (size_t)k * N * N + (size_t)y * N + x;
         if (mode & LED_FIELDS) {
           const cx<T> f = ((x + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
@@ -142,29 +185,26 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         const T i2 = norm2(ov);
         if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
         if (need_e) {
-          const T mv = meas[(size_t)y * N + x];
-          const T e = (a.fidelity == 0) ? sqrt(i2) - sqrt(mv > T(0) ? mv : T(0)) : i2 - mv;
-          ev[i][r] = e;
-          eb[y * PITCH + x] = e;
+          const T m = mv[b][r];
+          eb[y * PITCH + x] = (a.fidelity == 0) ? sqrt(i2) - sqrt(m > T(0) ? m : T(0)) : i2 - m;
         }
       }
-    }
   }
   if (!need_e) return;
   __syncthreads();
 
+  // features, loss and dL/d(conj o), written over the field registers
   auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
   double lsum = 0.0;
-  cx<T> w[MB2][R2];
 #pragma unroll
-  for (int i = 0; i < MB2; ++i) {
-    const int b = tid + i * NT;
-    if (b < N * R1) {
-      const int j = b / N, x = b - j * N;
+  for (int gi = 0; gi < GPW; ++gi) {
+    const int x = (wave + gi * NW) * LPW + grp;
+#pragma unroll
+    for (int b = 0; b < B2; ++b)
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
-        const int y = j + r * R1;
-        const T e = ev[i][r];
+        const int y = jl + b * L + r * R1;
+        const T e = E(y, x);
         const T dx0 = (x < N - 1) ? E(y, x + 1) - e : T(0);
         const T dy0 = (y < N - 1) ? E(y + 1, x) - e : T(0);
         T q;
@@ -191,13 +231,236 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
           }
           lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
         }
-        const cx<T> ov = o[i][r];
+        const cx<T> ov = o[gi][b][r];
         if (a.fidelity == 0) {
           const T am = sqrt(norm2(ov));
-          w[i][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
+          o[gi][b][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
         } else {
-          w[i][r] = scale(ov, q);
+          o[gi][b][r] = scale(ov, q);
         }
+      }
+  }
+  __syncthreads();  // every residual read is done; the tile can be overwritten
+
+  const bool grad = (mode & LED_GRAD) != 0;
+  if (grad) {
+#pragma unroll
+    for (int gi = 0; gi < GPW; ++gi) {
+      const int x = (wave + gi * NW) * LPW + grp;
+#pragma unroll
+      for (int b = 0; b < B2; ++b)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) img[(jl + b * L + r * R1) * PITCH + x] = o[gi][b][r];
+    }
+  }
+  const double tot = block_sum<NT>(lsum, red);  // contains barriers
+  if (tid == 0) a.fid_partial[k] = tot;
+  if (!grad) return;
+
+  // forward DFT of dL/d(conj o): every row, then the columns that hold support
+#pragma unroll
+  for (int gi = 0; gi < GPW; ++gi) {
+    const int t = (wave + gi * NW) * LPW + grp;
+    cx<T> v[B2][R2];
+    LF::template run<false, true>(img, twl, t, jl, true, v);
+    LF::template store<true>(img, t, jl, true, v);
+  }
+  __syncthreads();
+  const int ncol = a.x_max - a.x_min + 1;
+  cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
+  cx<T>* D = static_cast<cx<T>*>(a.D) + (size_t)k * a.S;
+#pragma unroll
+  for (int gi = 0; gi < GPW; ++gi) {
+    const int g = wave + gi * NW;
+    if (g * LPW >= ncol) break;  // uniform per wavefront
+    const int x = a.x_min + g * LPW + grp;
+    const bool ok = x <= a.x_max;
+    cx<T> Y[B2][R2];
+    LF::template run<false, false>(img, twl, x, jl, ok, Y);
+    // contributions on the support; each butterfly's window and pupil loads go out together
+    const int xs = ok ? x : a.x_min;
+#pragma unroll
+    for (int b = 0; b < B2; ++b) {
+      cx<T> pw[R2], ww[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = jl + b * L + r * R1;
+        pw[r] = P[y * N + xs];
+        ww[r] = win[(size_t)y * a.n_hi + xs];
+      }
+      if (ok) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const int y = jl + b * L + r * R1;
+          const int lo = sxlo[y];
+          if (x >= lo && x <= sxhi[y]) {
+            const int s = sroff[y] + x - lo;
+            const cx<T> yv = scale(Y[b][r], sc);
+            C[s] = cmulc(pw[r], yv);
+            D[s] = cmulc(ww[r], yv);
+          }
+        }
+      }
+    }
+  }
+}
+
+#else
+// Every pass of each 2-D transform is spread over the whole block (StockhamPass).
+template <class T, int N>
+__global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
+  using Sh = LedShape<N>;
+  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
+  static_assert(R1 * R2 == N, "two-pass decomposition");
+  constexpr int MB1 = ceil_div(N * (N / R1), NT);
+  constexpr int MB2 = ceil_div(N * (N / R2), NT);
+  static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
+  constexpr int PPT = N * N / NT;        // pixels per thread in the gather
+  constexpr int GB = PPT < 8 ? PPT : 8;  // loads kept in flight per batch
+  // row passes (transform stride PITCH) and column passes (element stride PITCH)
+  using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
+  using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1>;
+  using P1iC = StockhamPass<T, N, R1, 1, true, NT, MB1, 1, PITCH, N>;
+  using P2iC = StockhamPass<T, N, R2, R1, true, NT, MB2, 1, PITCH, N>;
+  using P1fR = StockhamPass<T, N, R1, 1, false, NT, MB1, PITCH, 1, N>;
+  using P2fR = StockhamPass<T, N, R2, R1, false, NT, MB2, PITCH, 1, N>;
+  using P1fC = StockhamPass<T, N, R1, 1, false, NT, MB1, 1, PITCH>;
+  using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH>;
+
+  __shared__ cx<T> img[N * PITCH];
+  __shared__ cx<T> twl[N];
+  __shared__ int sxlo[N], sxhi[N], sroff[N];
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x;
+  const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
+  const cx<T>* P = static_cast<const cx<T>*>(a.P);
+  for (int i = tid; i < N; i += NT) {
+    twl[i] = static_cast<const cx<T>*>(a.tw)[i];
+    sxlo[i] = a.xlo[i];
+    sxhi[i] = a.xhi[i];
+    sroff[i] = a.rowoff[i];
+  }
+  const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
+  const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
+  __syncthreads();
+
+  // gather X = P * window, zeros off the support.  Every address of the window is
+  // valid, so the loads are unconditional and a batch of them is in flight at once.
+#pragma unroll
+  for (int i0 = 0; i0 < PPT; i0 += GB) {
+    cx<T> pv[GB], wv[GB];
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int p = tid + (i0 + i) * NT;
+      pv[i] = P[p];
+      wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
+    }
+#pragma unroll
+    for (int i = 0; i < GB; ++i) {
+      const int p = tid + (i0 + i) * NT;
+      const int y = p / N, x = p % N;
+      const bool in = x >= sxlo[y] && x <= sxhi[y];
+      img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
+    }
+  }
+  __syncthreads();
+
+  // inverse DFT: rows that hold support pixels, then every column
+  const int nband = a.y_max - a.y_min + 1;
+  P1iR::run(img, a.y_min, nband, twl, tid);
+  P2iR::run(img, a.y_min, nband, twl, tid);
+  P1iC::run(img, 0, N, twl, tid);
+  // register (i, r) of the last column pass holds pixel y = jj[i] + r R1, x = mm[i]
+  int mm[MB2], jj[MB2];
+  bool lv[MB2];
+  P2iC::coords(N, tid, mm, jj, lv);
+  cx<T> o[MB2][R2];
+  P2iC::load(img, 0, mm, jj, lv, twl, o);
+  __syncthreads();
+
+  const T sc = T(a.inv_scale);
+  const T eps = T(a.eps);
+  const int mode = a.mode;
+  const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
+  const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
+  T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
+  T mv[MB2][R2];
+  if (need_e) {
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+      const int j = jj[i], x = mm[i];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) mv[i][r] = meas[(size_t)(j + r * R1) * N + x];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int j = jj[i], x = mm[i];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int y = j + r * R1;
+      const cx<T> ov = scale(o[i][r], sc);
+      o[i][r] = ov;
+      const size_t pix = (size_t)k * N * N + (size_t)y * N + x;
+      if (mode & LED_FIELDS) {
+        const cx<T> f = ((x + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
+        static_cast<cx<T>*>(a.fields)[pix] = f;
+      }
+      const T i2 = norm2(ov);
+      if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
+      if (need_e) {
+        const T m = mv[i][r];
+        eb[y * PITCH + x] = (a.fidelity == 0) ? sqrt(i2) - sqrt(m > T(0) ? m : T(0)) : i2 - m;
+      }
+    }
+  }
+  if (!need_e) return;
+  __syncthreads();
+
+  // features, loss and dL/d(conj o), written over the field registers
+  auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int j = jj[i], x = mm[i];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int y = j + r * R1;
+      const T e = E(y, x);
+      const T dx0 = (x < N - 1) ? E(y, x + 1) - e : T(0);
+      const T dy0 = (y < N - 1) ? E(y + 1, x) - e : T(0);
+      T q;
+      if (a.norm == 0) {
+        const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
+        const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
+        q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
+        lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+      } else {
+        const T s0 = dx0 * dx0 + dy0 * dy0;
+        const T inv0 = inv_norm(s0, eps);
+        q = -(dx0 + dy0) * inv0;
+        if (x > 0) {  // normaliser at (y, x-1)
+          const T el = E(y, x - 1);
+          const T gx = e - el;
+          const T gy = (y < N - 1) ? E(y + 1, x - 1) - el : T(0);
+          q += gx * inv_norm(gx * gx + gy * gy, eps);
+        }
+        if (y > 0) {  // normaliser at (y-1, x)
+          const T eu = E(y - 1, x);
+          const T gy = e - eu;
+          const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
+          q += gy * inv_norm(gx * gx + gy * gy, eps);
+        }
+        lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+      }
+      const cx<T> ov = o[i][r];
+      if (a.fidelity == 0) {
+        const T am = sqrt(norm2(ov));
+        o[i][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
+      } else {
+        o[i][r] = scale(ov, q);
       }
     }
   }
@@ -207,12 +470,9 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   if (grad) {
 #pragma unroll
     for (int i = 0; i < MB2; ++i) {
-      const int b = tid + i * NT;
-      if (b < N * R1) {
-        const int j = b / N, x = b - j * N;
+      const int j = jj[i], x = mm[i];
 #pragma unroll
-        for (int r = 0; r < R2; ++r) img[(j + r * R1) * PITCH + x] = w[i][r];
-      }
+      for (int r = 0; r < R2; ++r) img[(j + r * R1) * PITCH + x] = o[i][r];
     }
   }
   const double tot = block_sum<NT>(lsum, red);  // contains barriers
@@ -220,21 +480,30 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   if (!grad) return;
 
   // forward DFT of dL/d(conj o): all rows, then only columns that hold support
-  P1f::run(img, 0, N, PITCH, 1, twl, tid);
-  P2f::run(img, 0, N, PITCH, 1, twl, tid);
+  P1fR::run(img, 0, N, twl, tid);
+  P2fR::run(img, 0, N, twl, tid);
   const int ncol = a.x_max - a.x_min + 1;
-  P1f::run(img, a.x_min, ncol, 1, PITCH, twl, tid);
+  P1fC::run(img, a.x_min, ncol, twl, tid);
+  P2fC::coords(ncol, tid, mm, jj, lv);
   cx<T> Y[MB2][R2];
-  P2f::load(img, a.x_min, ncol, 1, PITCH, twl, tid, Y);
+  P2fC::load(img, a.x_min, mm, jj, lv, twl, Y);
 
+  // contributions on the support; the window and pupil loads are issued together
   cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
   cx<T>* D = static_cast<cx<T>*>(a.D) + (size_t)k * a.S;
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
-    const int b = tid + i * NT;
-    if (b < ncol * R1) {
-      const int j = b / ncol, m = b - j * ncol;
-      const int x = a.x_min + m;
+    const bool live = lv[i];
+    const int j = jj[i];
+    const int x = live ? a.x_min + mm[i] : 0;
+    cx<T> pw[R2], ww[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int y = live ? j + r * R1 : 0;
+      pw[r] = P[y * N + x];
+      ww[r] = win[(size_t)y * a.n_hi + x];
+    }
+    if (live) {
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int y = j + r * R1;
@@ -242,81 +511,107 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         if (x >= lo && x <= sxhi[y]) {
           const int s = sroff[y] + x - lo;
           const cx<T> yv = scale(Y[i][r], sc);
-          C[s] = cmulc(P[y * N + x], yv);
-          D[s] = cmulc(win[(size_t)y * a.n_hi + x], yv);
+          C[s] = cmulc(pw[r], yv);
+          D[s] = cmulc(ww[r], yv);
         }
       }
     }
   }
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Object-branch FFTs on the n_hi x n_hi spectrum: RPB rows (or columns) per block.
 // ---------------------------------------------------------------------------
-template <int N> struct BigShape;
-template <> struct BigShape<128> { static constexpr int NT = 128, RPB = 16, R1 = 16, R2 = 8, R3 = 1; };
-template <> struct BigShape<256> { static constexpr int NT = 128, RPB = 8, R1 = 16, R2 = 16, R3 = 1; };
-template <> struct BigShape<512> { static constexpr int NT = 128, RPB = 2, R1 = 8, R2 = 8, R3 = 8; };
-template <> struct BigShape<1024> { static constexpr int NT = 128, RPB = 2, R1 = 16, R2 = 8, R3 = 8; };
+#ifndef ELFPIE_COLS512
+#define ELFPIE_COLS512 8  // columns per block of the 512-point column transform
+#endif
+// Lines (rows, or columns when COLS) per block and radices of the object-branch transforms.
+template <int N, bool COLS = false> struct BigShape;
+template <bool C> struct BigShape<128, C> { static constexpr int NT = 128, RPB = 16, R1 = 16, R2 = 8, R3 = 1; };
+template <bool C> struct BigShape<256, C> { static constexpr int NT = 128, RPB = 8, R1 = 16, R2 = 16, R3 = 1; };
+template <> struct BigShape<512, false> { static constexpr int NT = 128, RPB = 2, R1 = 8, R2 = 8, R3 = 8; };
+template <> struct BigShape<512, true> {
+  static constexpr int RPB = ELFPIE_COLS512, NT = RPB * 64, R1 = 8, R2 = 8, R3 = 8;
+};
+template <bool C> struct BigShape<1024, C> { static constexpr int NT = 128, RPB = 2, R1 = 16, R2 = 8, R3 = 8; };
+
+// All passes of an unnormalised DFT of the RPB lines held in buf (line m at
+// m * (N + 1)); the outputs of the last pass go to emit(m, e, value).
+template <class T, int N, bool INV, bool COLS, class Emit>
+__device__ __forceinline__ void fft_lines_lds(cx<T>* buf, const cx<T>* twl, int tid, Emit&& emit) {
+  using Sh = BigShape<N, COLS>;
+  constexpr int NT = Sh::NT, RPB = Sh::RPB, R1 = Sh::R1, R2 = Sh::R2, R3 = Sh::R3, PITCH = N + 1;
+  constexpr int MB1 = ceil_div(RPB * (N / R1), NT);
+  constexpr int MB2 = ceil_div(RPB * (N / R2), NT);
+  using PA = StockhamPass<T, N, R1, 1, INV, NT, MB1, PITCH, 1, RPB>;
+  using PB = StockhamPass<T, N, R2, R1, INV, NT, MB2, PITCH, 1, RPB>;
+  PA::run(buf, 0, RPB, twl, tid);
+  if constexpr (R3 == 1) {
+    int m[MB2], j[MB2];
+    bool lv[MB2];
+    PB::coords(RPB, tid, m, j, lv);
+    cx<T> v[MB2][R2];
+    PB::load(buf, 0, m, j, lv, twl, v);
+#pragma unroll
+    for (int i = 0; i < MB2; ++i)
+      if (lv[i]) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) emit(m[i], PB::out_index(j[i], r), v[i][r]);
+      }
+  } else {
+    constexpr int MB3 = ceil_div(RPB * (N / R3), NT);
+    using PC = StockhamPass<T, N, R3, R1 * R2, INV, NT, MB3, PITCH, 1, RPB>;
+    PB::run(buf, 0, RPB, twl, tid);
+    int m[MB3], j[MB3];
+    bool lv[MB3];
+    PC::coords(RPB, tid, m, j, lv);
+    cx<T> v[MB3][R3];
+    PC::load(buf, 0, m, j, lv, twl, v);
+#pragma unroll
+    for (int i = 0; i < MB3; ++i)
+      if (lv[i]) {
+#pragma unroll
+        for (int r = 0; r < R3; ++r) emit(m[i], PC::out_index(j[i], r), v[i][r]);
+      }
+  }
+}
 
 // Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
 // (COLS = true) of an N x N complex array; in may equal out.
 template <class T, int N, bool INV, bool COLS>
-__global__ __launch_bounds__(BigShape<N>::NT) void k_fft_lines(const cx<T>* in, cx<T>* out, const cx<T>* tw) {
-  using Sh = BigShape<N>;
+__global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<T>* in, cx<T>* out,
+                                                                      const cx<T>* tw) {
+  using Sh = BigShape<N, COLS>;
   constexpr int NT = Sh::NT, RPB = Sh::RPB, R1 = Sh::R1, R2 = Sh::R2, R3 = Sh::R3, PITCH = N + 1;
   constexpr int MB1 = ceil_div(RPB * (N / R1), NT);
   constexpr int MB2 = ceil_div(RPB * (N / R2), NT);
   constexpr int MB3 = ceil_div(RPB * (N / R3), NT);
+  constexpr int EPT = RPB * N / NT;
+  static_assert(EPT * NT == RPB * N, "whole elements per thread");
   __shared__ cx<T> buf[RPB * PITCH];
   __shared__ cx<T> twl[N];
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * RPB;
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
-  for (int p = tid; p < RPB * N; p += NT) {
-    if (COLS) {
-      const int c = p % RPB, y = p / RPB;
-      buf[c * PITCH + y] = in[(size_t)y * N + l0 + c];
-    } else {
-      const int r = p / N, x = p % N;
-      buf[r * PITCH + x] = in[(size_t)(l0 + r) * N + x];
-    }
+  cx<T> ld[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int p = tid + i * NT;
+    if (COLS) ld[i] = in[(size_t)(p / RPB) * N + l0 + p % RPB];
+    else ld[i] = in[(size_t)(l0 + p / N) * N + p % N];
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int p = tid + i * NT;
+    if (COLS) buf[(p % RPB) * PITCH + p / RPB] = ld[i];
+    else buf[(p / N) * PITCH + p % N] = ld[i];
   }
   __syncthreads();
-  auto emit = [&](int m, int e, cx<T> v) {
+  fft_lines_lds<T, N, INV, COLS>(buf, twl, tid, [&](int m, int e, cx<T> v) {
     if (COLS) out[(size_t)e * N + l0 + m] = v;
     else out[(size_t)(l0 + m) * N + e] = v;
-  };
-  using PA = StockhamPass<T, N, R1, 1, INV, NT, MB1>;
-  using PB = StockhamPass<T, N, R2, R1, INV, NT, MB2>;
-  PA::run(buf, 0, RPB, PITCH, 1, twl, tid);
-  if constexpr (R3 == 1) {
-    cx<T> v[MB2][R2];
-    PB::load(buf, 0, RPB, PITCH, 1, twl, tid, v);
-#pragma unroll
-    for (int i = 0; i < MB2; ++i) {
-      const int b = tid + i * NT;
-      if (b < RPB * (N / R2)) {
-        const int j = b / RPB, m = b - j * RPB;
-#pragma unroll
-        for (int r = 0; r < R2; ++r) emit(m, PB::out_index(j, r), v[i][r]);
-      }
-    }
-  } else {
-    using PC = StockhamPass<T, N, R3, R1 * R2, INV, NT, MB3>;
-    PB::run(buf, 0, RPB, PITCH, 1, twl, tid);
-    cx<T> v[MB3][R3];
-    PC::load(buf, 0, RPB, PITCH, 1, twl, tid, v);
-#pragma unroll
-    for (int i = 0; i < MB3; ++i) {
-      const int b = tid + i * NT;
-      if (b < RPB * (N / R3)) {
-        const int j = b / RPB, m = b - j * RPB;
-#pragma unroll
-        for (int r = 0; r < R3; ++r) emit(m, PC::out_index(j, r), v[i][r]);
-      }
-    }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -458,103 +753,204 @@ __device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, dou
   v = vn;
 }
 
-// Spectrum gradient gather (segmented sum of the LED contributions that cover each
-// pixel, ascending LED order: Eq. 9's sum of M^T) plus the Hessian gradient, then
-// either the gradient is written or Eq. 19 updates Psi.  One 16 x 16 tile per block.
+// ---------------------------------------------------------------------------
+// Pupil: partial sums over LED chunks (Eq. 18) and the Gaussian pre-filter in one
+// launch (blocks with blockIdx.y == nch filter), then the update.
+// ---------------------------------------------------------------------------
+constexpr int kPupilChunk = 16;
+
+// Virtual block vb of the pupil work carried by the spectrum-update launch:
+// vb < nsb * nch: partial sum of LED chunk vb / nsb for NT support pixels;
+// after that: the 3 x 3 Gaussian of the current pupil (zero padding) for NT pixels.
+template <class T, int NT>
+__device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid) {
+  const int nsb = (a.S + NT - 1) / NT;
+  if (vb >= nsb * a.nch) {
+    const int p = (vb - nsb * a.nch) * NT + tid;
+    const int n = a.n_lo;
+    if (p >= n * n) return;
+    const int y = p / n, x = p % n;
+    const cx<T>* P = static_cast<const cx<T>*>(a.P);
+    cx<T> nb[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = min(max(y + t / 3 - 1, 0), n - 1), xx = min(max(x + t % 3 - 1, 0), n - 1);
+      nb[t] = P[yy * n + xx];
+    }
+    cx<T> acc = czero<T>();
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      const bool in = y + dy >= 0 && y + dy < n && x + dx >= 0 && x + dx < n;
+      const int ring = (dy != 0) + (dx != 0);
+      const T w = in ? T(ring == 0 ? a.w_c : (ring == 1 ? a.w_e : a.w_k)) : T(0);
+      acc = acc + scale(nb[t], w);
+    }
+    static_cast<cx<T>*>(a.Pf_out)[p] = acc;
+    return;
+  }
+  const int ch = vb / nsb;
+  const int s = (vb - ch * nsb) * NT + tid;
+  if (s >= a.S) return;
+  const cx<T>* D = static_cast<const cx<T>*>(a.D);
+  const int k0 = ch * kPupilChunk;
+  cx<T> v[kPupilChunk];
+#pragma unroll
+  for (int j = 0; j < kPupilChunk; ++j) {
+    const int k = k0 + j < a.K ? k0 + j : k0;
+    v[j] = D[(size_t)k * a.S + s];
+  }
+  cx<T> acc = czero<T>();
+#pragma unroll
+  for (int j = 0; j < kPupilChunk; ++j)
+    if (k0 + j < a.K) acc = acc + v[j];
+  static_cast<cx<T>*>(a.part)[(size_t)ch * a.S + s] = acc;
+}
+
+// Spectrum gradient gather (the segmented sum of the LED contributions that cover
+// each pixel, ascending LED order: Eq. 9's sum of M^T C_k, no atomics) plus the
+// Hessian gradient, then either the gradient is written or Eq. 19 updates Psi.
+// One 16 x 16 tile per block: the tile's LED list and the support row table are
+// staged in LDS and up to GB contribution loads per pixel are issued together (an
+// off-support entry reads C[0] and is discarded), so the sum keeps its fixed order.
+// Blocks past the tiles run the pupil partial sums and pre-filter, which depend
+// only on the per-LED kernel, as this launch does.
+#ifndef ELFPIE_UPD_GB
+#define ELFPIE_UPD_GB 8  // contribution loads in flight per pixel
+#endif
 template <class T>
-__global__ __launch_bounds__(256) void k_psi_update(UpdArgs a) {
+__global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
+  constexpr int LCH = 64, GB = ELFPIE_UPD_GB;
+  __shared__ int sxlo[kMaxLo], sxhi[kMaxLo], sroff[kMaxLo];
+  __shared__ int sk[LCH], sy0[LCH], sx0[LCH];
+  __shared__ double sbc[2];
+  const int tid = threadIdx.x;
   const int tile = blockIdx.x;
+  if (tile >= a.ntiles) {
+    pupil_block<T, 256>(pa, tile - a.ntiles, tid);
+    return;
+  }
   const int ty0 = (tile / a.ntiles_x) * 16, tx0 = (tile % a.ntiles_x) * 16;
-  const int uy = ty0 + threadIdx.x / 16, ux = tx0 + threadIdx.x % 16;
+  const int uy = ty0 + tid / 16, ux = tx0 + tid % 16;
   const size_t u = (size_t)uy * a.n_hi + ux;
+  for (int i = tid; i < a.n_lo; i += 256) {
+    sxlo[i] = a.xlo[i];
+    sxhi[i] = a.xhi[i];
+    sroff[i] = a.rowoff[i];
+  }
+  if (a.step && tid == 0) {
+    const double t1 = double(*a.t + 1);
+    sbc[0] = 1.0 - pow(a.g1, t1);
+    sbc[1] = 1.0 - pow(a.g2, t1);
+  }
+  // state loads go out first; they do not depend on the gather
   cx<T> g = static_cast<const cx<T>*>(a.gH)[u];
+  cx<T> x = czero<T>(), mu = czero<T>();
+  double v = 0.0;
+  T d = T(0);
+  if (a.step) {
+    x = static_cast<cx<T>*>(a.x)[u];
+    mu = static_cast<cx<T>*>(a.mu)[u];
+    v = a.v[u];
+    d = static_cast<T*>(a.delta)[u];
+  }
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
   const int b0 = a.tile_ptr[tile], b1 = a.tile_ptr[tile + 1];
-  for (int idx = b0; idx < b1; ++idx) {
-    const int k = a.tile_led[idx];
-    const int dy = uy - a.win[2 * k], dx = ux - a.win[2 * k + 1];
-    if (dy >= 0 && dy < a.n_lo) {
-      const int lo = a.xlo[dy];
-      if (dx >= lo && dx <= a.xhi[dy]) g = g + C[(size_t)k * a.S + a.rowoff[dy] + dx - lo];
+  for (int c0 = b0; c0 < b1; c0 += LCH) {
+    const int nl = min(LCH, b1 - c0);
+    __syncthreads();
+    if (tid < nl) {
+      const int k = a.tile_led[c0 + tid];
+      sk[tid] = k;
+      sy0[tid] = a.win[2 * k];
+      sx0[tid] = a.win[2 * k + 1];
+    }
+    __syncthreads();
+    for (int l0 = 0; l0 < nl; l0 += GB) {
+      cx<T> cv[GB];
+      bool ok[GB];
+#pragma unroll
+      for (int j = 0; j < GB; ++j) {
+        const int l = l0 + j;
+        size_t idx = 0;
+        ok[j] = false;
+        if (l < nl) {
+          const int dy = uy - sy0[l], dx = ux - sx0[l];
+          if (dy >= 0 && dy < a.n_lo) {
+            const int lo = sxlo[dy];
+            if (dx >= lo && dx <= sxhi[dy]) {
+              ok[j] = true;
+              idx = (size_t)sk[l] * a.S + sroff[dy] + dx - lo;
+            }
+          }
+        }
+        cv[j] = C[idx];
+      }
+#pragma unroll
+      for (int j = 0; j < GB; ++j)
+        if (ok[j]) g = g + cv[j];
     }
   }
   if (!a.step) {
     static_cast<cx<T>*>(a.g_out)[u] = g;
     return;
   }
-  const double t1 = double(*a.t + 1);
-  const double bc1 = 1.0 - pow(a.g1, t1), bc2 = 1.0 - pow(a.g2, t1);
-  cx<T> x = static_cast<cx<T>*>(a.x)[u];
-  cx<T> mu = static_cast<cx<T>*>(a.mu)[u];
-  double v = a.v[u];
-  T d = static_cast<T*>(a.delta)[u];
-  adabelief_elem(x, g, mu, v, d, a.g1, a.g2, a.eta, bc1, bc2);
+  __syncthreads();
+  adabelief_elem(x, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
   static_cast<cx<T>*>(a.x)[u] = x;
   static_cast<cx<T>*>(a.mu)[u] = mu;
   a.v[u] = v;
   static_cast<T*>(a.delta)[u] = d;
 }
 
-// ---------------------------------------------------------------------------
-// Pupil: partial sums over LED chunks (Eq. 18), Gaussian pre-filter, update.
-// ---------------------------------------------------------------------------
+// The pupil partial sums and pre-filter as a launch of their own.
 template <class T>
 __global__ __launch_bounds__(256) void k_pupil_partial(PupilArgs a) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  const int ch = blockIdx.y;
-  if (s >= a.S) return;
-  const cx<T>* D = static_cast<const cx<T>*>(a.D);
-  const int k0 = ch * a.chunk;
-  const int k1 = min(a.K, k0 + a.chunk);
-  cx<T> acc = czero<T>();
-  for (int k = k0; k < k1; ++k) acc = acc + D[(size_t)k * a.S + s];
-  static_cast<cx<T>*>(a.part)[(size_t)ch * a.S + s] = acc;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_pupil_gauss(PupilArgs a) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  const int n = a.n_lo;
-  if (p >= n * n) return;
-  const int y = p / n, x = p % n;
-  const cx<T>* P = static_cast<const cx<T>*>(a.P);
-  cx<T> acc = czero<T>();
-  for (int dy = -1; dy <= 1; ++dy)
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int yy = y + dy, xx = x + dx;
-      if (yy < 0 || yy >= n || xx < 0 || xx >= n) continue;
-      const int ring = (dy != 0) + (dx != 0);
-      const T w = T(ring == 0 ? a.w_c : (ring == 1 ? a.w_e : a.w_k));
-      acc = acc + scale(P[yy * n + xx], w);
-    }
-  static_cast<cx<T>*>(a.Pf_out)[p] = acc;
+  pupil_block<T, 256>(a, blockIdx.x, threadIdx.x);
 }
 
 template <class T>
 __global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
+  constexpr int GB = 8;
+  __shared__ double sbc[2];
   const int p = blockIdx.x * 256 + threadIdx.x;
   const int n = a.n_lo;
+  if (a.step && threadIdx.x == 0) {
+    const double t1 = double(*a.t + 1);
+    sbc[0] = 1.0 - pow(a.g1, t1);
+    sbc[1] = 1.0 - pow(a.g2, t1);
+  }
+  __syncthreads();
   if (p >= n * n) return;
   const int y = p / n, x = p % n;
   const int lo = a.xlo[y];
   const bool in = x >= lo && x <= a.xhi[y];
-  cx<T> g = czero<T>();
-  if (in) {
-    const int s = a.rowoff[y] + x - lo;
-    const cx<T>* part = static_cast<const cx<T>*>(a.part);
-    for (int c = 0; c < a.nch; ++c) g = g + part[(size_t)c * a.S + s];
+  const int s = in ? a.rowoff[y] + x - lo : 0;
+  cx<T> xv = czero<T>(), mu = czero<T>();
+  double v = 0.0;
+  T d = T(0);
+  if (a.step) {
+    xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
+    mu = static_cast<cx<T>*>(a.mu)[p];
+    v = a.v[p];
+    d = static_cast<T*>(a.delta)[p];
   }
+  cx<T> g = czero<T>();
+  const cx<T>* part = static_cast<const cx<T>*>(a.part);
+  for (int c0 = 0; c0 < a.nch; c0 += GB) {
+    cx<T> pv[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) pv[j] = part[(size_t)(c0 + j < a.nch ? c0 + j : c0) * a.S + s];
+#pragma unroll
+    for (int j = 0; j < GB; ++j)
+      if (c0 + j < a.nch) g = g + pv[j];
+  }
+  if (!in) g = czero<T>();
   if (!a.step) {
     static_cast<cx<T>*>(a.g_out)[p] = g;
     return;
   }
-  const double t1 = double(*a.t + 1);
-  const double bc1 = 1.0 - pow(a.g1, t1), bc2 = 1.0 - pow(a.g2, t1);
-  cx<T> xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
-  cx<T> mu = static_cast<cx<T>*>(a.mu)[p];
-  double v = a.v[p];
-  T d = static_cast<T*>(a.delta)[p];
-  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, bc1, bc2);
+  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
   if (a.support && !in) xv = czero<T>();
   static_cast<cx<T>*>(a.P_out)[p] = xv;
   static_cast<cx<T>*>(a.mu)[p] = mu;
@@ -566,28 +962,31 @@ __global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
 // Loss terms of Eq. (8), deterministic FP64 reduction; step counter.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
-  __shared__ double red[3][256];
+  __shared__ double red[3][4];
   const int tid = threadIdx.x;
   double f = 0.0, la = 0.0, lp = 0.0;
   for (int i = tid; i < a.K; i += 256) f += a.fid_partial[i];
+#pragma unroll 4
   for (int i = tid; i < a.ntiles; i += 256) {
     la += a.hess_partial[2 * i];
     lp += a.hess_partial[2 * i + 1];
   }
-  red[0][tid] = f;
-  red[1][tid] = la;
-  red[2][tid] = lp;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) {
-      red[0][tid] += red[0][tid + s];
-      red[1][tid] += red[1][tid + s];
-      red[2][tid] += red[2][tid + s];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    f += __shfl_down(f, off, 64);
+    la += __shfl_down(la, off, 64);
+    lp += __shfl_down(lp, off, 64);
   }
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = f;
+    red[1][tid >> 6] = la;
+    red[2][tid >> 6] = lp;
+  }
+  __syncthreads();
   if (tid == 0) {
-    const double F = red[0][0], A = red[1][0], Ph = red[2][0];
+    const double F = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double A = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double Ph = red[2][0] + red[2][1] + red[2][2] + red[2][3];
     const double L = F + a.alpha * A + a.beta * Ph;
     if (a.loss4) {
       a.loss4[0] = F;
@@ -645,8 +1044,10 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_init_window(const T* meas_c
   constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
   constexpr int MB1 = ceil_div(N * (N / R1), NT);
   constexpr int MB2 = ceil_div(N * (N / R2), NT);
-  using P1f = StockhamPass<T, N, R1, 1, false, NT, MB1>;
-  using P2f = StockhamPass<T, N, R2, R1, false, NT, MB2>;
+  using P1fR = StockhamPass<T, N, R1, 1, false, NT, MB1, PITCH, 1, N>;
+  using P2fR = StockhamPass<T, N, R2, R1, false, NT, MB2, PITCH, 1, N>;
+  using P1fC = StockhamPass<T, N, R1, 1, false, NT, MB1, 1, PITCH, N>;
+  using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH, N>;
   __shared__ cx<T> img[N * PITCH];
   __shared__ cx<T> twl[N];
   const int tid = threadIdx.x;
@@ -658,16 +1059,18 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_init_window(const T* meas_c
     img[y * PITCH + x] = cx<T>{((x + y) & 1) ? -s : s, T(0)};
   }
   __syncthreads();
-  P1f::run(img, 0, N, PITCH, 1, twl, tid);
-  P2f::run(img, 0, N, PITCH, 1, twl, tid);
-  P1f::run(img, 0, N, 1, PITCH, twl, tid);
+  P1fR::run(img, 0, N, twl, tid);
+  P2fR::run(img, 0, N, twl, tid);
+  P1fC::run(img, 0, N, twl, tid);
+  int mm[MB2], jj[MB2];
+  bool lv[MB2];
+  P2fC::coords(N, tid, mm, jj, lv);
   cx<T> Y[MB2][R2];
-  P2f::load(img, 0, N, 1, PITCH, twl, tid, Y);
+  P2fC::load(img, 0, mm, jj, lv, twl, Y);
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
-    const int b = tid + i * NT;
-    if (b < N * R1) {
-      const int j = b / N, x = b - j * N;
+    if (lv[i]) {
+      const int j = jj[i], x = mm[i];
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int y = j + r * R1;

@@ -60,12 +60,13 @@ struct UpdArgs {
   const int* xlo;
   const int* xhi;
   const int* rowoff;
-  const int* tile_ptr;  // CSR over 16 x 16 tiles of the spectrum
+  const int* tile_ptr;  // CSR over 16 x 16 tiles of the spectrum -> LEDs covering them
   const int* tile_led;
   const long long* t;
-  int n_hi, n_lo, S, ntiles_x;
+  int n_hi, n_lo, S, ntiles_x, ntiles;
   double g1, g2, eta;
   int step;             // 0: write g_out; 1: Eq. 19 update
+  int pupil_blocks;     // trailing blocks that run the pupil partial sums / pre-filter
 };
 
 struct PupilArgs {
