@@ -181,3 +181,20 @@ def test_window_outside_spectrum_is_rejected():
     prob = _problem_for(optics, far)
     with pytest.raises(ValueError):
         orc.window_origins(prob)
+
+
+def test_initial_state_of_uniform_stack_is_uniform_object():
+    """A uniform stack I = c^2 must initialise Psi to the spectrum of the uniform object c:
+    a single DC term c * n_hi (unitary transform), so that O0 = c everywhere."""
+    optics = synth.Optics(n_lo=16, upsample=4, led_grid=3)
+    pos = synth.led_grid_positions(3, optics.pitch_mm)
+    k = synth.led_wavevectors(pos, optics.height_mm, optics.wavelength_um)
+    prob = _problem_for(optics, k, flags=orc.PUPIL_SUPPORT)
+    c = 0.8
+    st = orc.init_state(np.full((prob.K, 16, 16), c * c), prob)
+    n = prob.n_hi
+    assert abs(st.psi[n // 2, n // 2] - c * n) < 1e-12
+    st.psi[n // 2, n // 2] = 0
+    assert np.max(np.abs(st.psi)) < 1e-12
+    O0 = orc.object_from_spectrum(orc.init_state(np.full((prob.K, 16, 16), c * c), prob).psi)
+    assert np.max(np.abs(O0 - c)) < 1e-12
