@@ -175,13 +175,13 @@ elfpie_status elfpie_spectrum_from_object(elfpie_plan *plan, const void *obj, vo
 elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpie_state *state,
                                 void *stream);
 
-/* Timing of the iteration's kernels in isolation: each stage is launched
- * n_rep times back to back on `stream` between two HIP events, on the state's
- * current arrays (the state is left unchanged), and ms_out (HOST, 8 floats)
- * receives the mean milliseconds per launch: [0] per-LED kernel, [1] object
- * inverse FFT, [2] Hessian kernel, [3] object forward FFT, [4] spectrum gather
- * + update kernel (gradient mode), [5] pupil kernels, [6] loss kernel,
- * [7] unused.  Synchronous. */
+/* Timing of the iteration's stages in isolation: each stage is launched n_rep
+ * times back to back on `stream` between two HIP events, on the state's current
+ * arrays (the state is left unchanged), and ms_out (HOST, 8 floats) receives the
+ * mean milliseconds per launch: [0] per-LED kernel, [1] object branch (transforms
+ * and Hessian penalties, gradient mode), [2] spectrum gather + update (gradient
+ * mode, with the pupil partial sums), [3] pupil update (gradient mode), [4] loss
+ * reduction, [5..7] unused (0).  Synchronous. */
 elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                                   int32_t n_rep, float *ms_out, void *stream);
 

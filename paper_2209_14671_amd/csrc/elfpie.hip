@@ -26,6 +26,14 @@ constexpr int kGraphIters = 8;  // iterations per replayed graph
 #define ELFPIE_FUSE_PUPIL 1
 #endif
 constexpr bool kFusePupil = ELFPIE_FUSE_PUPIL != 0;  // pupil partial sums ride in the update launch
+#ifndef ELFPIE_STRIP
+#define ELFPIE_STRIP 1
+#endif
+constexpr bool kUseStrip = ELFPIE_STRIP != 0;  // column-strip fusion of the object branch
+#ifndef ELFPIE_MERGE_FIN
+#define ELFPIE_MERGE_FIN 0
+#endif
+constexpr bool kMergeFin = ELFPIE_MERGE_FIN != 0;  // loss reduction rides in the pupil-update launch
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -36,6 +44,8 @@ struct Tables {
   int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
   int kc = 0;                      // LED nearest the optical axis
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
+  bool strip = false;              // object branch on column strips (k_obj_strip)
+  int nhp = 0;                     // Hessian loss partial pairs written per evaluation
   int nch = 0, chunk = kPupilChunk;  // pupil reduction chunks
   std::vector<int> win;            // K x 2 (y0, x0)
   std::vector<int> xlo, xhi, rowoff;
@@ -44,7 +54,7 @@ struct Tables {
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
-  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0;
+  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_done = 0;
   size_t total = 0;
 };
 
@@ -158,14 +168,23 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
       for (int tx = xa / 16; tx <= xb / 16; ++tx) lists[ty * tb->ntiles_x + tx].push_back(k);
   }
   tb->tile_ptr.assign(ntiles + 1, 0);
-  tb->tile_led.clear();
+  tb->tile_led.clear();  // (LED, window row, window column) triples
+  int nent = 0;
   for (int t = 0; t < ntiles; ++t) {
-    tb->tile_ptr[t] = (int)tb->tile_led.size();
-    tb->tile_led.insert(tb->tile_led.end(), lists[t].begin(), lists[t].end());
+    tb->tile_ptr[t] = nent;
+    for (int k : lists[t]) {
+      tb->tile_led.push_back(k);
+      tb->tile_led.push_back(tb->win[2 * k]);
+      tb->tile_led.push_back(tb->win[2 * k + 1]);
+      ++nent;
+    }
   }
-  tb->tile_ptr[ntiles] = (int)tb->tile_led.size();
-  if (tb->tile_led.empty()) tb->tile_led.push_back(0);
+  tb->tile_ptr[ntiles] = nent;
+  if (tb->tile_led.empty()) tb->tile_led.assign(3, 0);
   tb->nch = (tb->K + tb->chunk - 1) / tb->chunk;
+  // the fused column-strip object kernel keeps W + 4 columns, |O| and angle(O) in LDS
+  tb->strip = kUseStrip && (f32 || tb->n_hi <= 256);
+  tb->nhp = tb->strip ? tb->n_hi / ELFPIE_STRIP_W : ntiles;
 
   // workspace layout
   const size_t cxb = 2 * tb->elem;
@@ -193,10 +212,11 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_part = take((size_t)tb->nch * S * cxb);
   tb->o_Pf = take((size_t)n * n * cxb);
   tb->o_fid = take(tb->K * sizeof(double));
-  tb->o_hess = take((size_t)2 * tb->ntiles_x * tb->ntiles_x * sizeof(double));
+  tb->o_hess = take((size_t)2 * std::max(tb->nhp, ntiles) * sizeof(double));
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
+  tb->o_done = take(sizeof(int));
   tb->total = off;
   return ELFPIE_OK;
 }
@@ -332,7 +352,7 @@ struct Ops {
     return lines<false, false>(pl, out, out, s);
   }
 
-  static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s) {
+  static HessArgs hess_args(elfpie_plan* pl, bool grad, const void* Ot, void* Gt) {
     const Tables& tb = pl->tb;
     HessArgs a{};
     a.Ot = Ot;
@@ -346,10 +366,46 @@ struct Ops {
     a.eps = pl->prob.l1_eps;
     a.norm = pl->prob.norm;
     a.want_grad = grad ? 1 : 0;
+    return a;
+  }
+
+  static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s) {
+    const Tables& tb = pl->tb;
     dim3 grid(tb.n_hi / 16, tb.n_hi / 16);
-    k_hessian<T><<<grid, 256, 0, s>>>(a);
+    k_hessian<T><<<grid, 256, 0, s>>>(hess_args(pl, grad, Ot, Gt));
     LAUNCH_CHECK(pl, "k_hessian");
     return ELFPIE_OK;
+  }
+
+  template <int N>
+  static void launch_strip(const HessArgs& a, const C* T1, C* T2, const C* tw, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 || N <= 256)
+      k_obj_strip<T, N><<<N / StripShape<N>::W, StripShape<N>::NT, 0, s>>>(a, T1, T2, tw);
+  }
+
+  // Object branch from psi: O's penalties (loss partials) and, with grad, the
+  // gradient of the Hessian terms in out (forward DFT complete).  T1 is scratch.
+  static elfpie_status object_branch(elfpie_plan* pl, const void* psi, bool grad, void* T1, void* out,
+                                     hipStream_t s) {
+    const Tables& tb = pl->tb;
+    elfpie_status r;
+    if (!tb.strip) {
+      if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
+      if ((r = hessian(pl, grad, T1, out, s)) != ELFPIE_OK) return r;
+      return grad ? obj_forward(pl, out, out, s) : ELFPIE_OK;
+    }
+    if ((r = lines<true, false>(pl, psi, T1, s)) != ELFPIE_OK) return r;
+    const HessArgs a = hess_args(pl, grad, T1, out);
+    const C* tw = pl->at<C>(tb.o_twhi);
+    switch (tb.n_hi) {
+      case 128: launch_strip<128>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 256: launch_strip<256>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 512: launch_strip<512>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 1024: launch_strip<1024>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
+    }
+    LAUNCH_CHECK(pl, "k_obj_strip");
+    return grad ? lines<false, false>(pl, out, out, s) : ELFPIE_OK;
   }
 
   // LED gather + (gradient | Eq. 19 update) on 16 x 16 tiles, with the pupil partial
@@ -429,8 +485,28 @@ struct Ops {
     return a;
   }
 
+  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist, int64_t* t, bool bump) {
+    const Tables& tb = pl->tb;
+    FinArgs a{};
+    a.fid_partial = pl->at<double>(tb.o_fid);
+    a.K = tb.K;
+    a.hess_partial = pl->at<double>(tb.o_hess);
+    a.ntiles = tb.nhp;
+    a.alpha = pl->prob.alpha;
+    a.beta = pl->prob.beta;
+    a.loss4 = loss4;
+    a.hist = hist;
+    a.ctr = pl->at<int>(tb.o_ctr);
+    a.t = reinterpret_cast<long long*>(t);
+    a.flag = pl->at<int>(tb.o_flag);
+    a.bump_t = bump ? 1 : 0;
+    return a;
+  }
+
+  // Eq. 19 on P (st != NULL) or the pupil gradient (g_out); with fin the launch also
+  // reduces the loss terms and advances t (last block to finish).
   static elfpie_status pupil_finish(elfpie_plan* pl, const void* P, const elfpie_state* st, void* g_out,
-                                    hipStream_t s) {
+                                    const FinArgs* fin, hipStream_t s) {
     const Tables& tb = pl->tb;
     PupilArgs a = pupil_args(pl, P);
     a.g_out = g_out;
@@ -442,6 +518,10 @@ struct Ops {
       a.t = reinterpret_cast<const long long*>(st->t);
       a.step = 1;
     }
+    if (fin) {
+      a.fin = *fin;
+      a.done = pl->at<int>(tb.o_done);
+    }
     k_pupil_update<T><<<(tb.n_lo * tb.n_lo + 255) / 256, 256, 0, s>>>(a);
     LAUNCH_CHECK(pl, "k_pupil_update");
     return ELFPIE_OK;
@@ -449,21 +529,7 @@ struct Ops {
 
   static elfpie_status finalize(elfpie_plan* pl, double* loss4, double* hist, int64_t* t, bool bump,
                                 hipStream_t s) {
-    const Tables& tb = pl->tb;
-    FinArgs a{};
-    a.fid_partial = pl->at<double>(tb.o_fid);
-    a.K = tb.K;
-    a.hess_partial = pl->at<double>(tb.o_hess);
-    a.ntiles = tb.ntiles_x * tb.ntiles_x;
-    a.alpha = pl->prob.alpha;
-    a.beta = pl->prob.beta;
-    a.loss4 = loss4;
-    a.hist = hist;
-    a.ctr = pl->at<int>(tb.o_ctr);
-    a.t = reinterpret_cast<long long*>(t);
-    a.flag = pl->at<int>(tb.o_flag);
-    a.bump_t = bump ? 1 : 0;
-    k_finalize<<<1, 256, 0, s>>>(a);
+    k_finalize<<<1, 256, 0, s>>>(fin_args(pl, loss4, hist, t, bump));
     LAUNCH_CHECK(pl, "k_finalize");
     return ELFPIE_OK;
   }
@@ -481,15 +547,15 @@ struct Ops {
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
-    if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
-    if ((r = hessian(pl, true, T1, T2, s)) != ELFPIE_OK) return r;
-    if ((r = obj_forward(pl, T2, T2, s)) != ELFPIE_OK) return r;
+    if ((r = object_branch(pl, psi, true, T1, T2, s)) != ELFPIE_OK) return r;
     if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s)) != ELFPIE_OK) return r;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s)) != ELFPIE_OK) return r;
     if (learn_p) {
-      if ((r = pupil_finish(pl, P, st, g_P, s)) != ELFPIE_OK) return r;
+      const FinArgs fin = fin_args(pl, loss4, hist, st ? st->t : nullptr, st != nullptr);
+      if (kMergeFin) return pupil_finish(pl, P, st, g_P, &fin, s);
+      if ((r = pupil_finish(pl, P, st, g_P, nullptr, s)) != ELFPIE_OK) return r;
     }
     return finalize(pl, loss4, hist, st ? st->t : nullptr, st != nullptr, s);
   }
@@ -505,8 +571,7 @@ struct Ops {
     if (mode && (r = led(pl, mode, psi, P, meas, fields, intens, s)) != ELFPIE_OK) return r;
     if (!want_loss) return ELFPIE_OK;
     void* T1 = pl->at<void>(pl->tb.o_T1);
-    if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
-    if ((r = hessian(pl, false, T1, nullptr, s)) != ELFPIE_OK) return r;
+    if ((r = object_branch(pl, psi, false, T1, nullptr, s)) != ELFPIE_OK) return r;
     return finalize(pl, loss4, nullptr, nullptr, false, s);
   }
 
@@ -586,7 +651,7 @@ struct Ops {
     HIP_TRY(pl, hipEventCreate(&e0));
     HIP_TRY(pl, hipEventCreate(&e1));
     elfpie_status r = ELFPIE_OK;
-    for (int stage = 0; stage < 7 && r == ELFPIE_OK; ++stage) {
+    for (int stage = 0; stage < 5 && r == ELFPIE_OK; ++stage) {
       // warm the stage once, then time n_rep launches
       for (int rep = -1; rep < n_rep && r == ELFPIE_OK; ++rep) {
         if (rep == 0) {
@@ -594,12 +659,10 @@ struct Ops {
         }
         switch (stage) {
           case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s); break;
-          case 1: r = obj_inverse(pl, st->psi, T1, s); break;
-          case 2: r = hessian(pl, true, T1, T2, s); break;
-          case 3: r = obj_forward(pl, T2, G, s); break;
-          case 4: r = update(pl, nullptr, T1, G, st->P, true, true, s); break;
-          case 5: r = pupil_finish(pl, st->P, nullptr, gP, s); break;
-          case 6: r = finalize(pl, l4, nullptr, nullptr, false, s); break;
+          case 1: r = object_branch(pl, st->psi, true, T1, T2, s); break;
+          case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s); break;
+          case 3: r = pupil_finish(pl, st->P, nullptr, gP, nullptr, s); break;
+          case 4: r = finalize(pl, l4, nullptr, nullptr, false, s); break;
         }
       }
       if (r != ELFPIE_OK) break;
@@ -609,7 +672,7 @@ struct Ops {
       HIP_TRY(pl, hipEventElapsedTime(&t, e0, e1));
       ms[stage] = t / (float)n_rep;
     }
-    ms[7] = 0.f;
+    for (int i = 5; i < 8; ++i) ms[i] = 0.f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return r;
@@ -746,7 +809,8 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
       (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
     return cleanup(st);
   const int zero = 0;
-  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
+  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK ||
+      (st = put(t.o_done, &zero, sizeof zero)) != ELFPIE_OK)
     return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));

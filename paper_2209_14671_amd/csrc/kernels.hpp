@@ -614,6 +614,190 @@ __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<
   });
 }
 
+// All passes of an unnormalised DFT of NL lines of length N held in LDS (line m at
+// buf[m * (N + 1) + e]), NT threads, results left in place.
+template <int N> struct LineRadix;
+template <> struct LineRadix<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1; };
+template <> struct LineRadix<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
+template <> struct LineRadix<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
+template <> struct LineRadix<1024> { static constexpr int R1 = 16, R2 = 8, R3 = 8; };
+
+template <class T, int N, bool INV, int NT, int NL>
+__device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, int tid) {
+  using Rd = LineRadix<N>;
+  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3, PITCH = N + 1;
+  StockhamPass<T, N, R1, 1, INV, NT, ceil_div(NL * (N / R1), NT), PITCH, 1, NL>::run(buf, 0, NL, twl, tid);
+  StockhamPass<T, N, R2, R1, INV, NT, ceil_div(NL * (N / R2), NT), PITCH, 1, NL>::run(buf, 0, NL, twl, tid);
+  if constexpr (R3 > 1)
+    StockhamPass<T, N, R3, R1 * R2, INV, NT, ceil_div(NL * (N / R3), NT), PITCH, 1, NL>::run(buf, 0, NL, twl, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Object branch on column strips: column inverse DFT, Hessian penalties and their
+// gradient (Eq. 6, 7, 13, 14), column forward DFT, for W output columns per block.
+// ---------------------------------------------------------------------------
+// Input T1 = row-transformed Psi (unnormalised inverse DFT along rows).  The block
+// loads the W + 4 columns c0 - 2 .. c0 + W + 1 (the stencils reach two pixels),
+// finishes the inverse transform along them, so O = (-1)^(x+y) Ot / n, keeps |O| and
+// angle(O), and then, in chunks of CH rows:
+//   omega of the three H components of |O| and of angle(O) on columns c0 - 1 .. c0 + W
+//   (H zero where its stencil leaves the grid), then on the W own columns
+//   q = H^T omega, the loss terms and G = alpha q_a O / (2|O|) + beta q_phi i O / (2(|O|^2 + eta)),
+//   stored as (-1)^(x+y) G / n over O.
+// Finally the forward DFT along the W own columns, written to T2 (rows still to go).
+#ifndef ELFPIE_STRIP_W
+#define ELFPIE_STRIP_W 2      // output columns per block
+#define ELFPIE_STRIP_NT 1024  // threads per block
+#define ELFPIE_STRIP_CH 512   // rows per Hessian chunk
+#endif
+template <int N> struct StripShape {
+  static constexpr int W = ELFPIE_STRIP_W, NT = ELFPIE_STRIP_NT, CH = ELFPIE_STRIP_CH < N ? ELFPIE_STRIP_CH : N;
+};
+
+template <class T, int N>
+__global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, const cx<T>* T1, cx<T>* T2,
+                                                                  const cx<T>* tw) {
+  using Sh = StripShape<N>;
+  constexpr int W = Sh::W, NT = Sh::NT, CH = Sh::CH, NL = W + 4, PITCH = N + 1, OW = W + 2, OH = CH + 2;
+  __shared__ cx<T> buf[NL * PITCH];     // line l = column c0 - 2 + l
+  __shared__ T sa[NL * N], sp[NL * N];  // |O| and angle(O), line-major
+  __shared__ T om[6][OW * OH];          // omega: 3 components of |O|, then of angle(O)
+  __shared__ cx<T> twl[N];
+  __shared__ double red[NT / 64][2];
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * W;
+  const T inv_n = T(a.inv_n), eps = T(a.eps);
+  for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+  {
+    constexpr int EPT = ceil_div(NL * N, NT);
+    cx<T> ld[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = tid + i * NT, l = p % NL, y = p / NL, c = c0 - 2 + l;
+      ld[i] = (p < NL * N && c >= 0 && c < N) ? T1[(size_t)y * N + c] : czero<T>();
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = tid + i * NT;
+      if (p < NL * N) buf[(p % NL) * PITCH + p / NL] = ld[i];
+    }
+  }
+  __syncthreads();
+  fft_lines_inplace<T, N, true, NT, NL>(buf, twl, tid);
+  for (int p = tid; p < NL * N; p += NT) {
+    const int l = p / N, y = p % N, c = c0 - 2 + l;
+    const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
+    sa[p] = sqrt(norm2(O));
+    sp[p] = atan2(O.y, O.x);
+  }
+  __syncthreads();
+  double la = 0.0, lp = 0.0;
+  for (int r0 = 0; r0 < N; r0 += CH) {
+    // omega on lines 1 .. W + 2 (columns c0 - 1 .. c0 + W), rows r0 - 1 .. r0 + CH
+    for (int p = tid; p < OW * OH; p += NT) {
+      const int li = p / OH, yi = p % OH;
+      const int l = li + 1, y = r0 - 1 + yi, c = c0 - 2 + l;
+      const bool in = y >= 0 && y < N && c >= 0 && c < N;
+      const bool vxx = in && c >= 1 && c <= N - 2, vyy = in && y >= 1 && y <= N - 2;
+      const bool vxy = in && c <= N - 2 && y <= N - 2;
+      // rows clamped into the grid: exact for valid positions, harmless for the others
+      const int y0c = min(max(y, 0), N - 1), ymc = min(max(y - 1, 0), N - 1), ypc = min(max(y + 1, 0), N - 1);
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const T* src = f == 0 ? sa : sp;
+        const T ctr = src[l * N + y0c];
+        const T hxx = vxx ? src[(l - 1) * N + y0c] - T(2) * ctr + src[(l + 1) * N + y0c] : T(0);
+        const T hyy = vyy ? src[l * N + ymc] - T(2) * ctr + src[l * N + ypc] : T(0);
+        const T hxy = vxy ? ctr - src[(l + 1) * N + y0c] - src[l * N + ypc] + src[(l + 1) * N + ypc] : T(0);
+        T wxx, wyy, wxy;
+        if (a.norm == 0) {
+          wxx = omega(hxx, eps);
+          wyy = omega(hyy, eps);
+          wxy = omega(hxy, eps);
+        } else {
+          const T inv = inv_norm(hxx * hxx + hyy * hyy + hxy * hxy, eps);
+          wxx = hxx * inv;
+          wyy = hyy * inv;
+          wxy = hxy * inv;
+        }
+        om[3 * f + 0][p] = wxx;
+        om[3 * f + 1][p] = wyy;
+        om[3 * f + 2][p] = wxy;
+        // loss: own pixels (lines 2 .. W + 1, rows r0 .. r0 + CH - 1), each counted once
+        if (l >= 2 && l <= W + 1 && yi >= 1 && yi <= CH && in) {
+          double lv;
+          if (a.norm == 0) {
+            lv = double(rho(hxx, eps)) + double(rho(hyy, eps)) + double(rho(hxy, eps));
+          } else {
+            const T s2 = hxx * hxx + hyy * hyy + hxy * hxy;
+            lv = eps > T(0) ? double(sqrt(s2 + eps * eps) - eps) : double(sqrt(s2));
+          }
+          if (f == 0) la += lv;
+          else lp += lv;
+        }
+      }
+    }
+    __syncthreads();
+    if (a.want_grad) {
+      for (int p = tid; p < W * CH; p += NT) {
+        const int li = p / CH, yi = p % CH;
+        const int l = li + 2, y = r0 + yi, c = c0 - 2 + l;
+        const int oi = (li + 1) * OH + (yi + 1);  // omega index of the own pixel
+        T q[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          const T* wx = om[3 * f + 0];
+          const T* wy = om[3 * f + 1];
+          const T* wz = om[3 * f + 2];
+          q[f] = wx[oi - OH] - T(2) * wx[oi] + wx[oi + OH] + wy[oi - 1] - T(2) * wy[oi] + wy[oi + 1] + wz[oi] -
+                 wz[oi - OH] - wz[oi - 1] + wz[oi - OH - 1];
+        }
+        const T sgn = ((c + y) & 1) ? -inv_n : inv_n;
+        const cx<T> O = scale(buf[l * PITCH + y], sgn);
+        const T a2 = norm2(O);
+        const T am = sqrt(a2);
+        cx<T> G = czero<T>();
+        if (am > T(0)) G = scale(O, T(a.alpha) * q[0] / (T(2) * am));
+        const T den = a2 + T(a.eta_h);
+        if (den > T(0)) G = G + scale(mul_i(O), T(a.beta) * q[1] / (T(2) * den));
+        buf[l * PITCH + y] = scale(G, sgn);
+      }
+    }
+    __syncthreads();
+  }
+  // deterministic block sums of the two penalty partials
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    la += __shfl_down(la, off, 64);
+    lp += __shfl_down(lp, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = la;
+    red[tid >> 6][1] = lp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      s0 += red[w][0];
+      s1 += red[w][1];
+    }
+    a.partial[2 * blockIdx.x + 0] = s0;
+    a.partial[2 * blockIdx.x + 1] = s1;
+  }
+  if (!a.want_grad) return;
+  // forward DFT along the own columns (lines 2 .. W + 1), then store
+  fft_lines_inplace<T, N, false, NT, W>(buf + 2 * PITCH, twl, tid);
+  {
+    constexpr int EPT = ceil_div(W * N, NT);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int p = tid + i * NT, l = p % W, y = p / W;
+      if (p < W * N) T2[(size_t)y * N + c0 + l] = buf[(l + 2) * PITCH + y];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hessian penalties (Eq. 6, 7) and their gradient (Eq. 13, 14) on 16 x 16 tiles.
 // ---------------------------------------------------------------------------
@@ -820,9 +1004,9 @@ __device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid)
 #endif
 template <class T>
 __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
-  constexpr int LCH = 64, GB = ELFPIE_UPD_GB;
-  __shared__ int sxlo[kMaxLo], sxhi[kMaxLo], sroff[kMaxLo];
-  __shared__ int sk[LCH], sy0[LCH], sx0[LCH];
+  constexpr int GB = ELFPIE_UPD_GB;
+  using cint = const __attribute__((address_space(4))) int;  // read-only: wave-uniform reads go scalar
+  __shared__ int4 stab[kMaxLo];  // per support row: first column, last column, row base (rowoff - xlo)
   __shared__ double sbc[2];
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
@@ -833,11 +1017,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   const int ty0 = (tile / a.ntiles_x) * 16, tx0 = (tile % a.ntiles_x) * 16;
   const int uy = ty0 + tid / 16, ux = tx0 + tid % 16;
   const size_t u = (size_t)uy * a.n_hi + ux;
-  for (int i = tid; i < a.n_lo; i += 256) {
-    sxlo[i] = a.xlo[i];
-    sxhi[i] = a.xhi[i];
-    sroff[i] = a.rowoff[i];
-  }
+  for (int i = tid; i < a.n_lo; i += 256) stab[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   if (a.step && tid == 0) {
     const double t1 = double(*a.t + 1);
     sbc[0] = 1.0 - pow(a.g1, t1);
@@ -854,42 +1034,28 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
     v = a.v[u];
     d = static_cast<T*>(a.delta)[u];
   }
+  __syncthreads();
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
-  const int b0 = a.tile_ptr[tile], b1 = a.tile_ptr[tile + 1];
-  for (int c0 = b0; c0 < b1; c0 += LCH) {
-    const int nl = min(LCH, b1 - c0);
-    __syncthreads();
-    if (tid < nl) {
-      const int k = a.tile_led[c0 + tid];
-      sk[tid] = k;
-      sy0[tid] = a.win[2 * k];
-      sx0[tid] = a.win[2 * k + 1];
-    }
-    __syncthreads();
-    for (int l0 = 0; l0 < nl; l0 += GB) {
-      cx<T> cv[GB];
-      bool ok[GB];
+  cint* tp = (cint*)a.tile_ptr;
+  cint* tl = (cint*)a.tile_led;
+  const int b0 = tp[tile], b1 = tp[tile + 1];
+  for (int l0 = b0; l0 < b1; l0 += GB) {
+    size_t idx[GB];
+    bool ok[GB];
 #pragma unroll
-      for (int j = 0; j < GB; ++j) {
-        const int l = l0 + j;
-        size_t idx = 0;
-        ok[j] = false;
-        if (l < nl) {
-          const int dy = uy - sy0[l], dx = ux - sx0[l];
-          if (dy >= 0 && dy < a.n_lo) {
-            const int lo = sxlo[dy];
-            if (dx >= lo && dx <= sxhi[dy]) {
-              ok[j] = true;
-              idx = (size_t)sk[l] * a.S + sroff[dy] + dx - lo;
-            }
-          }
-        }
-        cv[j] = C[idx];
-      }
-#pragma unroll
-      for (int j = 0; j < GB; ++j)
-        if (ok[j]) g = g + cv[j];
+    for (int j = 0; j < GB; ++j) {
+      const int l = min(l0 + j, b1 - 1);  // wave-uniform list entry
+      const int k = tl[3 * l], dy = uy - tl[3 * l + 1], dx = ux - tl[3 * l + 2];
+      const int4 row = stab[min(max(dy, 0), a.n_lo - 1)];
+      ok[j] = l0 + j < b1 && dy >= 0 && dy < a.n_lo && dx >= row.x && dx <= row.y;
+      idx[j] = (size_t)k * a.S + row.z + dx;
     }
+    // exec-masked loads: lanes off the support issue nothing
+    cx<T> cv[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
+#pragma unroll
+    for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
   }
   if (!a.step) {
     static_cast<cx<T>*>(a.g_out)[u] = g;
@@ -903,67 +1069,10 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   static_cast<T*>(a.delta)[u] = d;
 }
 
-// The pupil partial sums and pre-filter as a launch of their own.
-template <class T>
-__global__ __launch_bounds__(256) void k_pupil_partial(PupilArgs a) {
-  pupil_block<T, 256>(a, blockIdx.x, threadIdx.x);
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
-  constexpr int GB = 8;
-  __shared__ double sbc[2];
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  const int n = a.n_lo;
-  if (a.step && threadIdx.x == 0) {
-    const double t1 = double(*a.t + 1);
-    sbc[0] = 1.0 - pow(a.g1, t1);
-    sbc[1] = 1.0 - pow(a.g2, t1);
-  }
-  __syncthreads();
-  if (p >= n * n) return;
-  const int y = p / n, x = p % n;
-  const int lo = a.xlo[y];
-  const bool in = x >= lo && x <= a.xhi[y];
-  const int s = in ? a.rowoff[y] + x - lo : 0;
-  cx<T> xv = czero<T>(), mu = czero<T>();
-  double v = 0.0;
-  T d = T(0);
-  if (a.step) {
-    xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
-    mu = static_cast<cx<T>*>(a.mu)[p];
-    v = a.v[p];
-    d = static_cast<T*>(a.delta)[p];
-  }
-  cx<T> g = czero<T>();
-  const cx<T>* part = static_cast<const cx<T>*>(a.part);
-  for (int c0 = 0; c0 < a.nch; c0 += GB) {
-    cx<T> pv[GB];
-#pragma unroll
-    for (int j = 0; j < GB; ++j) pv[j] = part[(size_t)(c0 + j < a.nch ? c0 + j : c0) * a.S + s];
-#pragma unroll
-    for (int j = 0; j < GB; ++j)
-      if (c0 + j < a.nch) g = g + pv[j];
-  }
-  if (!in) g = czero<T>();
-  if (!a.step) {
-    static_cast<cx<T>*>(a.g_out)[p] = g;
-    return;
-  }
-  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
-  if (a.support && !in) xv = czero<T>();
-  static_cast<cx<T>*>(a.P_out)[p] = xv;
-  static_cast<cx<T>*>(a.mu)[p] = mu;
-  a.v[p] = v;
-  static_cast<T*>(a.delta)[p] = d;
-}
-
 // ---------------------------------------------------------------------------
 // Loss terms of Eq. (8), deterministic FP64 reduction; step counter.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
-  __shared__ double red[3][4];
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void finalize_block(const FinArgs& a, int tid, double (*red)[4]) {
   double f = 0.0, la = 0.0, lp = 0.0;
   for (int i = tid; i < a.K; i += 256) f += a.fid_partial[i];
 #pragma unroll 4
@@ -1005,6 +1114,88 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     if (!isfinite(L)) *a.flag = 1;
     if (a.bump_t) *a.t = *a.t + 1;
   }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+  __shared__ double red[3][4];
+  finalize_block(a, threadIdx.x, red);
+}
+
+// The pupil partial sums and pre-filter as a launch of their own.
+template <class T>
+__global__ __launch_bounds__(256) void k_pupil_partial(PupilArgs a) {
+  pupil_block<T, 256>(a, blockIdx.x, threadIdx.x);
+}
+
+// Eq. (19) on the pupil.  With a.done set, the last block to finish also reduces
+// the loss terms and advances the step counter: every block reads t before taking
+// its ticket, so the increment cannot race a read.
+template <class T>
+__device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p);
+
+template <class T>
+__global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
+  __shared__ double sbc[2];
+  __shared__ double red[3][4];
+  __shared__ int last;
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x * 256 + tid;
+  if (a.step && tid == 0) {
+    const double t1 = double(*a.t + 1);
+    sbc[0] = 1.0 - pow(a.g1, t1);
+    sbc[1] = 1.0 - pow(a.g2, t1);
+  }
+  __syncthreads();
+  if (p < a.n_lo * a.n_lo) pupil_update_body<T>(a, sbc, p);
+  if (!a.done) return;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(a.done, 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finalize_block(a.fin, tid, red);
+  if (tid == 0) *a.done = 0;
+}
+
+template <class T>
+__device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p) {
+  constexpr int GB = 8;
+  const int n = a.n_lo;
+  const int y = p / n, x = p % n;
+  const int lo = a.xlo[y];
+  const bool in = x >= lo && x <= a.xhi[y];
+  const int s = in ? a.rowoff[y] + x - lo : 0;
+  cx<T> xv = czero<T>(), mu = czero<T>();
+  double v = 0.0;
+  T d = T(0);
+  if (a.step) {
+    xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
+    mu = static_cast<cx<T>*>(a.mu)[p];
+    v = a.v[p];
+    d = static_cast<T*>(a.delta)[p];
+  }
+  cx<T> g = czero<T>();
+  const cx<T>* part = static_cast<const cx<T>*>(a.part);
+  for (int c0 = 0; c0 < a.nch; c0 += GB) {
+    cx<T> pv[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) pv[j] = part[(size_t)(c0 + j < a.nch ? c0 + j : c0) * a.S + s];
+#pragma unroll
+    for (int j = 0; j < GB; ++j)
+      if (c0 + j < a.nch) g = g + pv[j];
+  }
+  if (!in) g = czero<T>();
+  if (!a.step) {
+    static_cast<cx<T>*>(a.g_out)[p] = g;
+    return;
+  }
+  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
+  if (a.support && !in) xv = czero<T>();
+  static_cast<cx<T>*>(a.P_out)[p] = xv;
+  static_cast<cx<T>*>(a.mu)[p] = mu;
+  a.v[p] = v;
+  static_cast<T*>(a.delta)[p] = d;
 }
 
 // ---------------------------------------------------------------------------

@@ -61,12 +61,26 @@ struct UpdArgs {
   const int* xhi;
   const int* rowoff;
   const int* tile_ptr;  // CSR over 16 x 16 tiles of the spectrum -> LEDs covering them
-  const int* tile_led;
+  const int* tile_led;  // entries as (LED, window row, window column) triples
   const long long* t;
   int n_hi, n_lo, S, ntiles_x, ntiles;
   double g1, g2, eta;
   int step;             // 0: write g_out; 1: Eq. 19 update
   int pupil_blocks;     // trailing blocks that run the pupil partial sums / pre-filter
+};
+
+struct FinArgs {
+  const double* fid_partial;
+  int K;
+  const double* hess_partial;
+  int ntiles;
+  double alpha, beta;
+  double* loss4;        // optional
+  double* hist;         // optional, indexed by *ctr
+  int* ctr;
+  long long* t;         // incremented when bump_t
+  int* flag;            // set to 1 when the total loss is not finite
+  int bump_t;
 };
 
 struct PupilArgs {
@@ -90,20 +104,11 @@ struct PupilArgs {
   int step;
   int filter;
   int support;
+  // When done != nullptr the block that finishes last also runs the loss reduction
+  // and step-counter increment described by fin, then resets *done to 0.
+  int* done;
+  FinArgs fin;
 };
 
-struct FinArgs {
-  const double* fid_partial;
-  int K;
-  const double* hess_partial;
-  int ntiles;
-  double alpha, beta;
-  double* loss4;        // optional
-  double* hist;         // optional, indexed by *ctr
-  int* ctr;
-  long long* t;         // incremented when bump_t
-  int* flag;            // set to 1 when the total loss is not finite
-  int bump_t;
-};
 
 }  // namespace elfpie
