@@ -64,6 +64,25 @@ def measured_traffic(src_hash):
     return d.get("traffic_bytes_per_launch")
 
 
+def copy_bandwidth(dev, mib, reps=3):
+    """Read + write GB/s of a plain device-to-device copy of `mib` MiB (larger than the
+    256 MB last-level cache at the default size), HIP-event timed on the current stream."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (n * 4) * reps / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
 def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
     """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
     import oracle as orc
@@ -95,6 +114,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=50)
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the plain device copy timed after the run (0: skip); the same copy "
+                         "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,6 +175,7 @@ def main():
     # per-kernel timing, HIP events around back-to-back launches on this stream
     log("per-stage timing")
     stages = plan.stage_timing(st, meas, args.stage_reps)
+    copy = copy_bandwidth(dev, args.copy_mib) if args.copy_mib else None
     led_bytes, it_bytes = byte_model(K, S, B, A)
     led_s = stages["led"] * 1e-3
     src_hash = kernel_source_hash()
@@ -160,6 +183,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(led_bytes / led_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(led_bytes / led_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_led<float,128>", "algorithmic_bytes": led_bytes, "avg_launch_ms": round(stages["led"], 4)}
+    if copy is not None:
+        roof["copy_GBs"] = copy
     it_gbs = it_bytes / (ms_step * 1e-3) / 1e9
 
     out = {
