@@ -180,8 +180,10 @@ elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpi
  * arrays (the state is left unchanged), and ms_out (HOST, 8 floats) receives the
  * mean milliseconds per launch: [0] per-LED kernel, [1] object branch (transforms
  * and Hessian penalties, gradient mode), [2] spectrum gather + update (gradient
- * mode, with the pupil partial sums), [3] pupil update (gradient mode), [4] loss
- * reduction, [5..7] unused (0).  Synchronous. */
+ * mode, with the pupil partial sums), [3] iteration tail launched alone (pupil
+ * gradient and loss reduction), [4..7] unused (0).  Inside elfpie_run the tail of
+ * every iteration but the last rides in the next iteration's first launch.
+ * Synchronous. */
 elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                                   int32_t n_rep, float *ms_out, void *stream);
 

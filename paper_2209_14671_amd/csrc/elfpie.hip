@@ -30,10 +30,21 @@ constexpr bool kFusePupil = ELFPIE_FUSE_PUPIL != 0;  // pupil partial sums ride 
 #define ELFPIE_STRIP 1
 #endif
 constexpr bool kUseStrip = ELFPIE_STRIP != 0;  // column-strip fusion of the object branch
-#ifndef ELFPIE_MERGE_FIN
-#define ELFPIE_MERGE_FIN 0
-#endif
-constexpr bool kMergeFin = ELFPIE_MERGE_FIN != 0;  // loss reduction rides in the pupil-update launch
+
+// The tail of an iteration (pupil update, loss) waiting to be launched, either alone
+// or as extra blocks of the next iteration's first transform launch.
+struct TailReq {
+  bool pupil = false;  // Eq. 19 on P (state) or the pupil gradient
+  TailArgs a{};
+};
+
+// Blocks of NT threads that the tail needs: pupil pixels, then one loss block.
+inline TailArgs shape_tail(const TailReq& r, int nt) {
+  TailArgs a = r.a;
+  a.pupil_blocks = r.pupil ? (a.pa.n_lo * a.pa.n_lo + nt - 1) / nt : 0;
+  a.fin_block = 1;
+  return a;
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -54,7 +65,7 @@ struct Tables {
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
-  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_done = 0;
+  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0;
   size_t total = 0;
 };
 
@@ -216,7 +227,6 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
-  tb->o_done = take(sizeof(int));
   tb->total = off;
   return ELFPIE_OK;
 }
@@ -273,7 +283,7 @@ struct Ops {
   using C = cx<T>;
 
   static elfpie_status led(elfpie_plan* pl, int mode, const void* psi, const void* P, const void* meas,
-                           void* fields, void* intens, hipStream_t s) {
+                           void* fields, void* intens, hipStream_t s, int64_t* t_bump = nullptr) {
     const Tables& tb = pl->tb;
     LedArgs a{};
     a.psi = psi;
@@ -298,6 +308,7 @@ struct Ops {
     a.inv_scale = 1.0 / ((double)pl->prob.upsample * tb.n_lo);
     a.eps = pl->prob.l1_eps;
     a.mode = mode;
+    a.t_bump = reinterpret_cast<long long*>(t_bump);
     a.fidelity = pl->prob.fidelity;
     a.norm = pl->prob.norm;
     switch (tb.n_lo) {
@@ -316,22 +327,30 @@ struct Ops {
   }
 
   template <int N, bool INV, bool COLS>
-  static void launch_lines(const C* in, C* out, const C* tw, hipStream_t s) {
+  static void launch_lines(const C* in, C* out, const C* tw, const TailReq* tail, hipStream_t s) {
     using Sh = BigShape<N, COLS>;
-    k_fft_lines<T, N, INV, COLS><<<N / Sh::RPB, Sh::NT, 0, s>>>(in, out, tw);
+    TailArgs ta{};
+    int extra = 0;
+    if (tail) {
+      ta = shape_tail(*tail, Sh::NT);
+      extra = ta.pupil_blocks + ta.fin_block;
+    }
+    k_fft_lines<T, N, INV, COLS><<<N / Sh::RPB + extra, Sh::NT, 0, s>>>(in, out, tw, ta);
   }
 
+  // Transform of every row or column of an n_hi^2 array; a pending tail rides along.
   template <bool INV, bool COLS>
-  static elfpie_status lines(elfpie_plan* pl, const void* in, void* out, hipStream_t s) {
+  static elfpie_status lines(elfpie_plan* pl, const void* in, void* out, hipStream_t s,
+                             const TailReq* tail = nullptr) {
     const Tables& tb = pl->tb;
     const C* tw = pl->at<C>(tb.o_twhi);
     const C* i = static_cast<const C*>(in);
     C* o = static_cast<C*>(out);
     switch (tb.n_hi) {
-      case 128: launch_lines<128, INV, COLS>(i, o, tw, s); break;
-      case 256: launch_lines<256, INV, COLS>(i, o, tw, s); break;
-      case 512: launch_lines<512, INV, COLS>(i, o, tw, s); break;
-      case 1024: launch_lines<1024, INV, COLS>(i, o, tw, s); break;
+      case 128: launch_lines<128, INV, COLS>(i, o, tw, tail, s); break;
+      case 256: launch_lines<256, INV, COLS>(i, o, tw, tail, s); break;
+      case 512: launch_lines<512, INV, COLS>(i, o, tw, tail, s); break;
+      case 1024: launch_lines<1024, INV, COLS>(i, o, tw, tail, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
     LAUNCH_CHECK(pl, "k_fft_lines");
@@ -339,8 +358,9 @@ struct Ops {
   }
 
   // out = unnormalised inverse DFT of psi (rows into out, then columns in place)
-  static elfpie_status obj_inverse(elfpie_plan* pl, const void* psi, void* out, hipStream_t s) {
-    elfpie_status st = lines<true, false>(pl, psi, out, s);
+  static elfpie_status obj_inverse(elfpie_plan* pl, const void* psi, void* out, hipStream_t s,
+                                   const TailReq* tail = nullptr) {
+    elfpie_status st = lines<true, false>(pl, psi, out, s, tail);
     if (st != ELFPIE_OK) return st;
     return lines<true, true>(pl, out, out, s);
   }
@@ -385,16 +405,17 @@ struct Ops {
 
   // Object branch from psi: O's penalties (loss partials) and, with grad, the
   // gradient of the Hessian terms in out (forward DFT complete).  T1 is scratch.
+  // A pending tail of the previous iteration rides in the first launch.
   static elfpie_status object_branch(elfpie_plan* pl, const void* psi, bool grad, void* T1, void* out,
-                                     hipStream_t s) {
+                                     hipStream_t s, const TailReq* tail = nullptr) {
     const Tables& tb = pl->tb;
     elfpie_status r;
     if (!tb.strip) {
-      if ((r = obj_inverse(pl, psi, T1, s)) != ELFPIE_OK) return r;
+      if ((r = obj_inverse(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
       if ((r = hessian(pl, grad, T1, out, s)) != ELFPIE_OK) return r;
       return grad ? obj_forward(pl, out, out, s) : ELFPIE_OK;
     }
-    if ((r = lines<true, false>(pl, psi, T1, s)) != ELFPIE_OK) return r;
+    if ((r = lines<true, false>(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
     const HessArgs a = hess_args(pl, grad, T1, out);
     const C* tw = pl->at<C>(tb.o_twhi);
     switch (tb.n_hi) {
@@ -485,7 +506,7 @@ struct Ops {
     return a;
   }
 
-  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist, int64_t* t, bool bump) {
+  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist) {
     const Tables& tb = pl->tb;
     FinArgs a{};
     a.fid_partial = pl->at<double>(tb.o_fid);
@@ -497,18 +518,18 @@ struct Ops {
     a.loss4 = loss4;
     a.hist = hist;
     a.ctr = pl->at<int>(tb.o_ctr);
-    a.t = reinterpret_cast<long long*>(t);
     a.flag = pl->at<int>(tb.o_flag);
-    a.bump_t = bump ? 1 : 0;
     return a;
   }
 
-  // Eq. 19 on P (st != NULL) or the pupil gradient (g_out); with fin the launch also
-  // reduces the loss terms and advances t (last block to finish).
-  static elfpie_status pupil_finish(elfpie_plan* pl, const void* P, const elfpie_state* st, void* g_out,
-                                    const FinArgs* fin, hipStream_t s) {
-    const Tables& tb = pl->tb;
-    PupilArgs a = pupil_args(pl, P);
+  // The tail of an iteration: Eq. 19 on P (st != NULL) or the pupil gradient into
+  // g_out (when pupil), and the loss terms into loss4 / the history.
+  static TailReq tail_req(elfpie_plan* pl, bool pupil, const void* P, const elfpie_state* st, void* g_out,
+                          double* loss4, double* hist) {
+    TailReq r;
+    r.pupil = pupil;
+    PupilArgs& a = r.a.pa;
+    a = pupil_args(pl, P);
     a.g_out = g_out;
     if (st) {
       a.P_out = st->P;
@@ -518,46 +539,57 @@ struct Ops {
       a.t = reinterpret_cast<const long long*>(st->t);
       a.step = 1;
     }
-    if (fin) {
-      a.fin = *fin;
-      a.done = pl->at<int>(tb.o_done);
-    }
-    k_pupil_update<T><<<(tb.n_lo * tb.n_lo + 255) / 256, 256, 0, s>>>(a);
-    LAUNCH_CHECK(pl, "k_pupil_update");
-    return ELFPIE_OK;
+    r.a.fin = fin_args(pl, loss4, hist);
+    return r;
   }
 
-  static elfpie_status finalize(elfpie_plan* pl, double* loss4, double* hist, int64_t* t, bool bump,
-                                hipStream_t s) {
-    k_finalize<<<1, 256, 0, s>>>(fin_args(pl, loss4, hist, t, bump));
-    LAUNCH_CHECK(pl, "k_finalize");
+  static elfpie_status tail(elfpie_plan* pl, const TailReq& r, hipStream_t s) {
+    const TailArgs a = shape_tail(r, 256);
+    k_tail<T><<<a.pupil_blocks + a.fin_block, 256, 0, s>>>(a);
+    LAUNCH_CHECK(pl, "k_tail");
     return ELFPIE_OK;
   }
 
   // One gradient evaluation (st == NULL) or one update step (st != NULL), all on
   // stream `s`: object branch (inverse transform, Hessian, forward transform), the
   // per-LED kernel, the spectrum update (gather, Eq. 19; pupil partial sums in the
-  // same launch), the pupil update and the loss.
+  // same launch), then the tail (pupil update, loss).  `prev` is the previous
+  // iteration's tail, run inside this iteration's first launch.  With `defer` this
+  // iteration's tail is returned there instead of launched.
   // Kernels on one queue dispatch back to back; a join across queues costs more
   // than the overlap it buys (the per-LED kernel fills every CU).
   static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
                                  const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
-                                 hipStream_t s) {
+                                 hipStream_t s, const TailReq* prev = nullptr, TailReq* defer = nullptr) {
     const Tables& tb = pl->tb;
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
-    if ((r = object_branch(pl, psi, true, T1, T2, s)) != ELFPIE_OK) return r;
-    if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s)) != ELFPIE_OK) return r;
+    if ((r = object_branch(pl, psi, true, T1, T2, s, prev)) != ELFPIE_OK) return r;
+    if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s, st ? st->t : nullptr)) != ELFPIE_OK) return r;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s)) != ELFPIE_OK) return r;
-    if (learn_p) {
-      const FinArgs fin = fin_args(pl, loss4, hist, st ? st->t : nullptr, st != nullptr);
-      if (kMergeFin) return pupil_finish(pl, P, st, g_P, &fin, s);
-      if ((r = pupil_finish(pl, P, st, g_P, nullptr, s)) != ELFPIE_OK) return r;
+    const TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist);
+    if (defer) {
+      *defer = mine;
+      return ELFPIE_OK;
     }
-    return finalize(pl, loss4, hist, st ? st->t : nullptr, st != nullptr, s);
+    return tail(pl, mine, s);
+  }
+
+  // n_iter update steps; every tail but the last rides in the next iteration.
+  static elfpie_status iterations(elfpie_plan* pl, const elfpie_state* st, const void* meas, int n_iter,
+                                  double* hist, hipStream_t s) {
+    TailReq pend;
+    elfpie_status r = ELFPIE_OK;
+    for (int it = 0; it < n_iter && r == ELFPIE_OK; ++it) {
+      TailReq next;
+      r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, it ? &pend : nullptr, &next);
+      pend = next;
+    }
+    if (r != ELFPIE_OK || n_iter == 0) return r;
+    return tail(pl, pend, s);
   }
 
   static elfpie_status forward(elfpie_plan* pl, const void* psi, const void* P, const void* meas, void* fields,
@@ -572,7 +604,7 @@ struct Ops {
     if (!want_loss) return ELFPIE_OK;
     void* T1 = pl->at<void>(pl->tb.o_T1);
     if ((r = object_branch(pl, psi, false, T1, nullptr, s)) != ELFPIE_OK) return r;
-    return finalize(pl, loss4, nullptr, nullptr, false, s);
+    return tail(pl, tail_req(pl, false, P, nullptr, nullptr, loss4, nullptr), s);
   }
 
   static elfpie_status to_object(elfpie_plan* pl, const void* psi, void* obj, hipStream_t s) {
@@ -651,7 +683,8 @@ struct Ops {
     HIP_TRY(pl, hipEventCreate(&e0));
     HIP_TRY(pl, hipEventCreate(&e1));
     elfpie_status r = ELFPIE_OK;
-    for (int stage = 0; stage < 5 && r == ELFPIE_OK; ++stage) {
+    const TailReq tq = tail_req(pl, true, st->P, nullptr, gP, l4, nullptr);
+    for (int stage = 0; stage < 4 && r == ELFPIE_OK; ++stage) {
       // warm the stage once, then time n_rep launches
       for (int rep = -1; rep < n_rep && r == ELFPIE_OK; ++rep) {
         if (rep == 0) {
@@ -661,8 +694,7 @@ struct Ops {
           case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s); break;
           case 1: r = object_branch(pl, st->psi, true, T1, T2, s); break;
           case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s); break;
-          case 3: r = pupil_finish(pl, st->P, nullptr, gP, nullptr, s); break;
-          case 4: r = finalize(pl, l4, nullptr, nullptr, false, s); break;
+          case 3: r = tail(pl, tq, s); break;
         }
       }
       if (r != ELFPIE_OK) break;
@@ -672,7 +704,7 @@ struct Ops {
       HIP_TRY(pl, hipEventElapsedTime(&t, e0, e1));
       ms[stage] = t / (float)n_rep;
     }
-    for (int i = 5; i < 8; ++i) ms[i] = 0.f;
+    for (int i = 4; i < 8; ++i) ms[i] = 0.f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return r;
@@ -809,8 +841,7 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
       (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
     return cleanup(st);
   const int zero = 0;
-  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK ||
-      (st = put(t.o_done, &zero, sizeof zero)) != ELFPIE_OK)
+  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
     return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));
@@ -911,12 +942,8 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
     for (int g = 0; g < 2; ++g) {
       const int reps = g == 0 ? kGraphIters : 1;
       HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-      elfpie_status r = ELFPIE_OK;
-      for (int it = 0; it < reps && r == ELFPIE_OK; ++it)
-        r = dispatch(pl, [&](auto ops) {
-          return decltype(ops)::iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, d_loss_hist,
-                                          pl->cap);
-        });
+      const elfpie_status r = dispatch(
+          pl, [&](auto ops) { return decltype(ops)::iterations(pl, st, meas, reps, d_loss_hist, pl->cap); });
       hipGraph_t gr = nullptr;
       const hipError_t ec = hipStreamEndCapture(pl->cap, &gr);
       if (r != ELFPIE_OK) {

@@ -76,6 +76,12 @@ template <> struct LedShape<128> { static constexpr int NT = ELFPIE_LED128_NT, R
 //   adjoint  q = grad^T omega, dL/d(conj o) = q o  or  q o / (2|o|)  (Eq. 11 / Eq. 10)
 //   forward  Y = F_B^H dL/d(conj o): all rows, then support columns
 //   outputs  C = conj(P) Y and D = conj(M_k Psi) Y on the support    (Eq. 9, Eq. 18)
+// Step mode advances the shared step counter t once per iteration, here: nothing in
+// this launch reads it, and the spectrum and pupil updates that follow read the new value.
+__device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) {
+  if (a.t_bump && k == 0 && tid == 0) *a.t_bump = *a.t_bump + 1;
+}
+
 #if ELFPIE_LED_LINES
 // Each 1-D transform of a row or column is done by L lanes of one wavefront
 // (LineFft), so the block synchronises only between the row and column phases.
@@ -101,6 +107,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const int wave = tid / 64, lane = tid % 64;
   const int grp = lane / L, jl = lane % L;        // line within the wavefront's group, lane in line
   const int k = blockIdx.x;
+  led_bump_step(a, k, tid);
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
   for (int i = tid; i < N; i += NT) {
@@ -334,6 +341,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
+  led_bump_step(a, k, tid);
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
   for (int i = tid; i < N; i += NT) {
@@ -577,11 +585,16 @@ __device__ __forceinline__ void fft_lines_lds(cx<T>* buf, const cx<T>* twl, int 
   }
 }
 
+template <class T, int NT>
+__device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, double* sbc, double (*red)[4]);
+
 // Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
-// (COLS = true) of an N x N complex array; in may equal out.
+// (COLS = true) of an N x N complex array; in may equal out.  Blocks past the
+// N / RPB line blocks run the previous iteration's tail (pupil update, loss), which
+// touches none of the arrays transformed here.
 template <class T, int N, bool INV, bool COLS>
 __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<T>* in, cx<T>* out,
-                                                                      const cx<T>* tw) {
+                                                                      const cx<T>* tw, TailArgs ta) {
   using Sh = BigShape<N, COLS>;
   constexpr int NT = Sh::NT, RPB = Sh::RPB, R1 = Sh::R1, R2 = Sh::R2, R3 = Sh::R3, PITCH = N + 1;
   constexpr int MB1 = ceil_div(RPB * (N / R1), NT);
@@ -591,7 +604,13 @@ __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<
   static_assert(EPT * NT == RPB * N, "whole elements per thread");
   __shared__ cx<T> buf[RPB * PITCH];
   __shared__ cx<T> twl[N];
+  __shared__ double tail_sbc[2];
+  __shared__ double tail_red[3][4];
   const int tid = threadIdx.x;
+  if (blockIdx.x >= N / RPB) {
+    tail_block<T, NT>(ta, blockIdx.x - N / RPB, tid, tail_sbc, tail_red);
+    return;
+  }
   const int l0 = blockIdx.x * RPB;
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
   cx<T> ld[EPT];
@@ -1019,9 +1038,9 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   const size_t u = (size_t)uy * a.n_hi + ux;
   for (int i = tid; i < a.n_lo; i += 256) stab[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   if (a.step && tid == 0) {
-    const double t1 = double(*a.t + 1);
-    sbc[0] = 1.0 - pow(a.g1, t1);
-    sbc[1] = 1.0 - pow(a.g2, t1);
+    const double t = double(*a.t);
+    sbc[0] = 1.0 - pow(a.g1, t);
+    sbc[1] = 1.0 - pow(a.g2, t);
   }
   // state loads go out first; they do not depend on the gather
   cx<T> g = static_cast<const cx<T>*>(a.gH)[u];
@@ -1070,26 +1089,37 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 }
 
 // ---------------------------------------------------------------------------
-// Loss terms of Eq. (8), deterministic FP64 reduction; step counter.
+// Loss terms of Eq. (8): deterministic FP64 reduction by one block of NT threads.
+// The summation order is that of 256 lanes whatever NT is (a thread of a smaller
+// block plays 256 / NT lanes), so every launch that carries it gives the same bits.
 // ---------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void finalize_block(const FinArgs& a, int tid, double (*red)[4]) {
-  double f = 0.0, la = 0.0, lp = 0.0;
-  for (int i = tid; i < a.K; i += 256) f += a.fid_partial[i];
-#pragma unroll 4
-  for (int i = tid; i < a.ntiles; i += 256) {
-    la += a.hess_partial[2 * i];
-    lp += a.hess_partial[2 * i + 1];
-  }
+  constexpr int V = NT >= 256 ? 1 : 256 / NT;
+  static_assert(NT % 64 == 0 && (NT >= 256 || 256 % NT == 0), "whole wavefronts");
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    f += __shfl_down(f, off, 64);
-    la += __shfl_down(la, off, 64);
-    lp += __shfl_down(lp, off, 64);
-  }
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = f;
-    red[1][tid >> 6] = la;
-    red[2][tid >> 6] = lp;
+  for (int r = 0; r < V; ++r) {
+    const int vt = tid + r * NT;
+    if (vt < 256) {  // wave-uniform
+      double f = 0.0, la = 0.0, lp = 0.0;
+      for (int i = vt; i < a.K; i += 256) f += a.fid_partial[i];
+#pragma unroll 4
+      for (int i = vt; i < a.ntiles; i += 256) {
+        la += a.hess_partial[2 * i];
+        lp += a.hess_partial[2 * i + 1];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        f += __shfl_down(f, off, 64);
+        la += __shfl_down(la, off, 64);
+        lp += __shfl_down(lp, off, 64);
+      }
+      if ((vt & 63) == 0) {
+        red[0][vt >> 6] = f;
+        red[1][vt >> 6] = la;
+        red[2][vt >> 6] = lp;
+      }
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -1112,13 +1142,7 @@ __device__ __forceinline__ void finalize_block(const FinArgs& a, int tid, double
       *a.ctr = c + 1;
     }
     if (!isfinite(L)) *a.flag = 1;
-    if (a.bump_t) *a.t = *a.t + 1;
   }
-}
-
-__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
-  __shared__ double red[3][4];
-  finalize_block(a, threadIdx.x, red);
 }
 
 // The pupil partial sums and pre-filter as a launch of their own.
@@ -1127,35 +1151,34 @@ __global__ __launch_bounds__(256) void k_pupil_partial(PupilArgs a) {
   pupil_block<T, 256>(a, blockIdx.x, threadIdx.x);
 }
 
-// Eq. (19) on the pupil.  With a.done set, the last block to finish also reduces
-// the loss terms and advances the step counter: every block reads t before taking
-// its ticket, so the increment cannot race a read.
 template <class T>
 __device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p);
 
+// Virtual block vb of an iteration's tail (block-uniform branches): Eq. 19 on NT
+// pupil pixels, or the loss reduction.  t already counts this iteration.
+template <class T, int NT>
+__device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, double* sbc, double (*red)[4]) {
+  if (vb < ta.pupil_blocks) {
+    const PupilArgs& a = ta.pa;
+    if (a.step && tid == 0) {
+      const double t = double(*a.t);
+      sbc[0] = 1.0 - pow(a.g1, t);
+      sbc[1] = 1.0 - pow(a.g2, t);
+    }
+    __syncthreads();
+    const int p = vb * NT + tid;
+    if (p < a.n_lo * a.n_lo) pupil_update_body<T>(a, sbc, p);
+  } else if (ta.fin_block && vb == ta.pupil_blocks) {
+    finalize_block<NT>(ta.fin, tid, red);
+  }
+}
+
+// An iteration's tail as a launch of its own.
 template <class T>
-__global__ __launch_bounds__(256) void k_pupil_update(PupilArgs a) {
+__global__ __launch_bounds__(256) void k_tail(TailArgs ta) {
   __shared__ double sbc[2];
   __shared__ double red[3][4];
-  __shared__ int last;
-  const int tid = threadIdx.x;
-  const int p = blockIdx.x * 256 + tid;
-  if (a.step && tid == 0) {
-    const double t1 = double(*a.t + 1);
-    sbc[0] = 1.0 - pow(a.g1, t1);
-    sbc[1] = 1.0 - pow(a.g2, t1);
-  }
-  __syncthreads();
-  if (p < a.n_lo * a.n_lo) pupil_update_body<T>(a, sbc, p);
-  if (!a.done) return;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(a.done, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  finalize_block(a.fin, tid, red);
-  if (tid == 0) *a.done = 0;
+  tail_block<T, 256>(ta, blockIdx.x, threadIdx.x, sbc, red);
 }
 
 template <class T>

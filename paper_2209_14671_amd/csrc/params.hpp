@@ -35,6 +35,7 @@ struct LedArgs {
   int mode;
   int fidelity;
   int norm;
+  long long* t_bump;    // step counter, advanced once by block 0 in step mode (else NULL)
 };
 
 struct HessArgs {
@@ -62,7 +63,7 @@ struct UpdArgs {
   const int* rowoff;
   const int* tile_ptr;  // CSR over 16 x 16 tiles of the spectrum -> LEDs covering them
   const int* tile_led;  // entries as (LED, window row, window column) triples
-  const long long* t;
+  const long long* t;   // step counter, already advanced for this iteration
   int n_hi, n_lo, S, ntiles_x, ntiles;
   double g1, g2, eta;
   int step;             // 0: write g_out; 1: Eq. 19 update
@@ -78,9 +79,7 @@ struct FinArgs {
   double* loss4;        // optional
   double* hist;         // optional, indexed by *ctr
   int* ctr;
-  long long* t;         // incremented when bump_t
   int* flag;            // set to 1 when the total loss is not finite
-  int bump_t;
 };
 
 struct PupilArgs {
@@ -104,10 +103,16 @@ struct PupilArgs {
   int step;
   int filter;
   int support;
-  // When done != nullptr the block that finishes last also runs the loss reduction
-  // and step-counter increment described by fin, then resets *done to 0.
-  int* done;
+};
+
+// End of an iteration: Eq. 19 on the pupil (or its gradient) and the loss reduction.
+// Both read only what earlier launches wrote, so their blocks are independent and
+// can ride in any later launch that leaves P, the loss partials and the counters alone.
+struct TailArgs {
+  PupilArgs pa;
   FinArgs fin;
+  int pupil_blocks;     // blocks of the pupil update (0: none)
+  int fin_block;        // 1: one more block reduces the loss
 };
 
 

@@ -278,7 +278,7 @@ class Plan:
         ms = (ctypes.c_float * 8)()
         self._check(self.lib.elfpie_stage_timing(self.handle, ctypes.byref(sc), _ptr(meas), int(n_rep), ms,
                                                  _stream()))
-        names = ["led", "object", "update", "pupil", "loss"]
+        names = ["led", "object", "update", "tail"]
         return {n: float(ms[i]) for i, n in enumerate(names)}
 
 
