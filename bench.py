@@ -83,6 +83,50 @@ def copy_bandwidth(dev, mib, reps=3):
     return round(gbs, 1)
 
 
+def autograd_bench(args, dev):
+    """Forward + backward of the differentiable loss (FP32, 256^2, K=121, 64^2): the
+    backward recomputing the per-LED fields against one reading fields the forward kept."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    case = synth.config_case(4)
+    o = case.optics
+    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=E.F32), device=dev)
+    psi_true = sim.spectrum_from_object(torch.from_numpy(case.obj).to(torch.complex64).to(dev))
+    clean = sim.forward(psi_true, torch.from_numpy(case.pupil).to(torch.complex64).to(dev), intens=True)["intens"]
+    meas = torch.from_numpy(synth.degrade(clean.cpu().numpy().astype(np.float64), case.degradation,
+                                          case.noise_seed)).to(torch.float32).to(dev)
+    sim.close()
+    plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=E.F32, flags=E.PUPIL_SUPPORT), device=dev)
+    st = plan.init_state(meas)
+    res = {}
+    for store in (False, True):
+        def once():
+            psi = st.psi.clone().requires_grad_(True)
+            P = st.P.clone().requires_grad_(True)
+            E.elfpie_loss(psi, P, plan, meas, store_fields=store).backward()
+        for _ in range(args.warmup):
+            once()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            once()
+        ev1.record()
+        torch.cuda.synchronize()
+        res["stored" if store else "recompute"] = ev0.elapsed_time(ev1) / args.steps
+    K, B = plan.K, plan.n_lo ** 2
+    print(json.dumps({
+        "metric": "forward + backward of the Elfpie loss (autograd), recomputed vs stored per-LED fields",
+        "unit": "ms", "higher_is_better": False, "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": "differentiable loss, FP32: 256x256 high-res, 11x11 LEDs "
+                                                    "(K=121), 64x64 low-res", "K": K, "n_lo": plan.n_lo,
+                                        "n_hi": plan.n_hi},
+        "ms_recompute": round(res["recompute"], 4), "ms_stored": round(res["stored"], 4),
+        "stored_fields_bytes": K * B * 8}), flush=True)
+
+
 def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
     """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
     import oracle as orc
@@ -117,6 +161,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed after the run (0: skip); the same copy "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
+    ap.add_argument("--workload", choices=["iteration", "autograd"], default="iteration",
+                    help="iteration: the throughput line (default); autograd: forward + backward of the "
+                         "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -130,6 +177,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "autograd":
+        autograd_bench(args, dev)
+        return
     case = synth.config_case(2)
     o = case.optics
     flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER

@@ -149,6 +149,15 @@ elfpie_status elfpie_forward(elfpie_plan *plan, const void *psi, const void *P, 
 elfpie_status elfpie_grad(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
                           void *g_psi, void *g_P, double *d_loss4, void *stream);
 
+/* The same loss and gradients as elfpie_grad, from stored fields: `fields`
+ * (K x n_lo x n_lo complex, DEVICE) holds the o_k that elfpie_forward wrote for
+ * this psi and P, and the per-LED kernel reads them instead of recomputing the
+ * crop and inverse transform (the trade-off of reverse-mode differentiation:
+ * K n_lo^2 complex kept between the calls against one transform per LED).
+ * Results equal elfpie_grad's bit for bit when the fields match. */
+elfpie_status elfpie_grad_fields(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
+                                 const void *fields, void *g_psi, void *g_P, double *d_loss4, void *stream);
+
 /* One iteration of Algorithm 1 on `state`: gradients at (psi, P), Eq. 19 update
  * of psi, then (ELFPIE_LEARN_PUPIL) pre-filter and Eq. 19 update of P, then t += 1.
  * d_loss4 (optional, device) receives the loss terms at the pre-update state. */

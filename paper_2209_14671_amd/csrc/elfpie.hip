@@ -560,13 +560,17 @@ struct Ops {
   // than the overlap it buys (the per-LED kernel fills every CU).
   static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
                                  const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
-                                 hipStream_t s, const TailReq* prev = nullptr, TailReq* defer = nullptr) {
+                                 hipStream_t s, const TailReq* prev = nullptr, TailReq* defer = nullptr,
+                                 const void* stored_fields = nullptr) {
     const Tables& tb = pl->tb;
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
     if ((r = object_branch(pl, psi, true, T1, T2, s, prev)) != ELFPIE_OK) return r;
-    if ((r = led(pl, LED_GRAD, psi, P, meas, nullptr, nullptr, s, st ? st->t : nullptr)) != ELFPIE_OK) return r;
+    const int mode = stored_fields ? LED_GRAD | LED_STORED : LED_GRAD;
+    if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr)) !=
+        ELFPIE_OK)
+      return r;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s)) != ELFPIE_OK) return r;
@@ -896,6 +900,23 @@ elfpie_status elfpie_grad(elfpie_plan* pl, const void* psi, const void* P, const
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(pl, [&](auto ops) {
     return decltype(ops)::iteration(pl, psi, P, meas, nullptr, g_psi, g_P, d_loss4, nullptr, s);
+  });
+}
+
+elfpie_status elfpie_grad_fields(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
+                                 const void* fields, void* g_psi, void* g_P, double* d_loss4, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, psi, "psi", false));
+  CHECK(check_ptr(pl, P, "P", false));
+  CHECK(check_ptr(pl, meas, "meas", false));
+  CHECK(check_ptr(pl, fields, "fields", false));
+  CHECK(check_ptr(pl, g_psi, "g_psi", false));
+  CHECK(check_ptr(pl, g_P, "g_P", true));
+  CHECK(check_ptr(pl, d_loss4, "d_loss4", true));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) {
+    return decltype(ops)::iteration(pl, psi, P, meas, nullptr, g_psi, g_P, d_loss4, nullptr, s, nullptr, nullptr,
+                                    fields);
   });
 }
 

@@ -99,77 +99,3 @@ struct StockhamPass {
 constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 }  // namespace elfpie
-
-namespace elfpie {
-
-// Ordering of LDS accesses within one wavefront (no block barrier): every lane's
-// earlier LDS stores are visible to the wavefront's later LDS loads.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Two-pass transform of one line (row or column of an LDS tile) of N = R1 * R2
-// points by L = N / R1 lanes of one wavefront, so a wavefront transforms LPW lines
-// with no block barrier.  Lane j of a line:
-//   pass 1: reads elements j + r L (r < R1), DFT_R1, writes j R1 + r;
-//   pass 2: butterflies jj = j + b L (b < B2 = R1 / L) read jj + r R1 (r < R2),
-//           twiddle W_N^(r jj), DFT_R2; output r of butterfly jj is element jj + r R1.
-// Element e of line t lives at t * PITCH + e (rows) or e * PITCH + t (columns); with
-// PITCH = N + L the LPW lines of a wavefront fall on distinct LDS banks.
-template <class T, int N, int R1, int R2, int PITCH>
-struct LineFft {
-  static constexpr int L = N / R1;
-  static constexpr int LPW = 64 / L;
-  static constexpr int B2 = R1 / L;
-  static_assert(R1 * R2 == N && L * LPW == 64 && B2 * L == R1, "line decomposition");
-
-  template <bool ROW>
-  __device__ static __forceinline__ int at(int t, int e) { return ROW ? t * PITCH + e : e * PITCH + t; }
-
-  // Transform line t (lanes with valid == false only take part in the wave sync);
-  // leaves the outputs in v.
-  template <bool INV, bool ROW>
-  __device__ static __forceinline__ void run(cx<T>* buf, const cx<T>* tw, int t, int j, bool valid,
-                                             cx<T> (&v)[B2][R2]) {
-    if (valid) {
-      cx<T> a[R1];
-#pragma unroll
-      for (int r = 0; r < R1; ++r) a[r] = buf[at<ROW>(t, j + r * L)];
-      dft<T, R1, INV>(a);
-#pragma unroll
-      for (int r = 0; r < R1; ++r) buf[at<ROW>(t, j * R1 + r)] = a[r];
-    }
-    wave_sync();
-    if (valid) {
-#pragma unroll
-      for (int b = 0; b < B2; ++b) {
-        const int jj = j + b * L;
-#pragma unroll
-        for (int r = 0; r < R2; ++r) {
-          cx<T> x = buf[at<ROW>(t, jj + r * R1)];
-          if (r > 0) {
-            cx<T> w = tw[r * jj];
-            if (INV) w.y = -w.y;
-            x = x * w;
-          }
-          v[b][r] = x;
-        }
-        dft<T, R2, INV>(v[b]);
-      }
-    }
-  }
-
-  template <bool ROW>
-  __device__ static __forceinline__ void store(cx<T>* buf, int t, int j, bool valid, const cx<T> (&v)[B2][R2]) {
-    if (valid) {
-#pragma unroll
-      for (int b = 0; b < B2; ++b)
-#pragma unroll
-        for (int r = 0; r < R2; ++r) buf[at<ROW>(t, j + b * L + r * R1)] = v[b][r];
-    }
-  }
-};
-
-}  // namespace elfpie

@@ -56,9 +56,6 @@ __device__ __forceinline__ T inv_norm(T s2, T eps) {
 // ---------------------------------------------------------------------------
 // Per-LED fused kernel: one workgroup per LED, the n_lo x n_lo tile in LDS.
 // ---------------------------------------------------------------------------
-#ifndef ELFPIE_LED_LINES
-#define ELFPIE_LED_LINES 0  // 1: each row / column transform by one wavefront (LineFft)
-#endif
 
 template <int N> struct LedShape;
 template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 8, R2 = 4; };
@@ -82,237 +79,6 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
   if (a.t_bump && k == 0 && tid == 0) *a.t_bump = *a.t_bump + 1;
 }
 
-#if ELFPIE_LED_LINES
-// Each 1-D transform of a row or column is done by L lanes of one wavefront
-// (LineFft), so the block synchronises only between the row and column phases.
-template <class T, int N>
-__global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
-  using Sh = LedShape<N>;
-  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2;
-  constexpr int NW = NT / 64;                     // wavefronts per block
-  using LF = LineFft<T, N, R1, R2, N + N / R1>;
-  constexpr int PITCH = N + LF::L, L = LF::L, LPW = LF::LPW, B2 = LF::B2;
-  constexpr int GPW = (N / LPW) / NW;             // dense line groups per wavefront
-  static_assert(GPW * NW * LPW == N, "dense phases split evenly over the wavefronts");
-  constexpr int PPT = N * N / NT;                 // pixels per thread in the gather
-  constexpr int GB = PPT < 8 ? PPT : 8;           // loads kept in flight per batch
-  static_assert(GPW * B2 * R2 == PPT, "pixel ownership after the column phase");
-
-  __shared__ cx<T> img[N * PITCH];
-  __shared__ cx<T> twl[N];
-  __shared__ int sxlo[N], sxhi[N], sroff[N];
-  __shared__ double red[NW];
-
-  const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid % 64;
-  const int grp = lane / L, jl = lane % L;        // line within the wavefront's group, lane in line
-  const int k = blockIdx.x;
-  led_bump_step(a, k, tid);
-  const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
-  const cx<T>* P = static_cast<const cx<T>*>(a.P);
-  for (int i = tid; i < N; i += NT) {
-    twl[i] = static_cast<const cx<T>*>(a.tw)[i];
-    sxlo[i] = a.xlo[i];
-    sxhi[i] = a.xhi[i];
-    sroff[i] = a.rowoff[i];
-  }
-  const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
-  const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
-  __syncthreads();
-
-  // gather X = P * window, zeros off the support.  Every address of the window is
-  // valid, so the loads are unconditional and a batch of them is in flight at once.
-#pragma unroll
-  for (int i0 = 0; i0 < PPT; i0 += GB) {
-    cx<T> pv[GB], wv[GB];
-#pragma unroll
-    for (int i = 0; i < GB; ++i) {
-      const int p = tid + (i0 + i) * NT;
-      pv[i] = P[p];
-      wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
-    }
-#pragma unroll
-    for (int i = 0; i < GB; ++i) {
-      const int p = tid + (i0 + i) * NT;
-      const int y = p / N, x = p % N;
-      const bool in = x >= sxlo[y] && x <= sxhi[y];
-      img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
-    }
-  }
-  __syncthreads();
-
-  // inverse DFT along the rows that hold support pixels (the others are zero)
-  const int nband = a.y_max - a.y_min + 1;
-  for (int g = wave; g * LPW < nband; g += NW) {
-    const int t = a.y_min + g * LPW + grp;
-    const bool ok = t <= a.y_max;
-    cx<T> v[B2][R2];
-    LF::template run<true, true>(img, twl, t, jl, ok, v);
-    LF::template store<true>(img, t, jl, ok, v);
-  }
-  __syncthreads();
-  // ... then along every column; the results stay in registers:
-  // o[gi][b][r] is pixel (row j + b L + r R1, column (wave + gi NW) LPW + grp)
-  cx<T> o[GPW][B2][R2];
-#pragma unroll
-  for (int gi = 0; gi < GPW; ++gi) {
-    const int t = (wave + gi * NW) * LPW + grp;
-    LF::template run<true, false>(img, twl, t, jl, true, o[gi]);
-  }
-  __syncthreads();
-
-  const T sc = T(a.inv_scale);
-  const T eps = T(a.eps);
-  const int mode = a.mode;
-  const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
-  const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
-  T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
-#pragma unroll
-  for (int gi = 0; gi < GPW; ++gi) {
-    const int x = (wave + gi * NW) * LPW + grp;
-    T mv[B2][R2];
-    if (need_e) {
-#pragma unroll
-      for (int b = 0; b < B2; ++b)
-#pragma unroll
-        for (int r = 0; r < R2; ++r) mv[b][r] = meas[(size_t)(jl + b * L + r * R1) * N + x];
-    }
-#pragma unroll
-    for (int b = 0; b < B2; ++b)
-#pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        const int y = jl + b * L + r * R1;
-        const cx<T> ov = scale(o[gi][b][r], sc);
-        o[gi][b][r] = ov;
-        const size_t pix = (size_t)k * N * N + (size_t)y * N + x;
-        if (mode & LED_FIELDS) {
-          const cx<T> f = ((x + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
-          static_cast<cx<T>*>(a.fields)[pix] = f;
-        }
-        const T i2 = norm2(ov);
-        if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
-        if (need_e) {
-          const T m = mv[b][r];
-          eb[y * PITCH + x] = (a.fidelity == 0) ? sqrt(i2) - sqrt(m > T(0) ? m : T(0)) : i2 - m;
-        }
-      }
-  }
-  if (!need_e) return;
-  __syncthreads();
-
-  // features, loss and dL/d(conj o), written over the field registers
-  auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
-  double lsum = 0.0;
-#pragma unroll
-  for (int gi = 0; gi < GPW; ++gi) {
-    const int x = (wave + gi * NW) * LPW + grp;
-#pragma unroll
-    for (int b = 0; b < B2; ++b)
-#pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        const int y = jl + b * L + r * R1;
-        const T e = E(y, x);
-        const T dx0 = (x < N - 1) ? E(y, x + 1) - e : T(0);
-        const T dy0 = (y < N - 1) ? E(y + 1, x) - e : T(0);
-        T q;
-        if (a.norm == 0) {
-          const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
-          const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
-          q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
-          lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
-        } else {
-          const T s0 = dx0 * dx0 + dy0 * dy0;
-          const T inv0 = inv_norm(s0, eps);
-          q = -(dx0 + dy0) * inv0;
-          if (x > 0) {  // normaliser at (y, x-1)
-            const T el = E(y, x - 1);
-            const T gx = e - el;
-            const T gy = (y < N - 1) ? E(y + 1, x - 1) - el : T(0);
-            q += gx * inv_norm(gx * gx + gy * gy, eps);
-          }
-          if (y > 0) {  // normaliser at (y-1, x)
-            const T eu = E(y - 1, x);
-            const T gy = e - eu;
-            const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
-            q += gy * inv_norm(gx * gx + gy * gy, eps);
-          }
-          lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
-        }
-        const cx<T> ov = o[gi][b][r];
-        if (a.fidelity == 0) {
-          const T am = sqrt(norm2(ov));
-          o[gi][b][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
-        } else {
-          o[gi][b][r] = scale(ov, q);
-        }
-      }
-  }
-  __syncthreads();  // every residual read is done; the tile can be overwritten
-
-  const bool grad = (mode & LED_GRAD) != 0;
-  if (grad) {
-#pragma unroll
-    for (int gi = 0; gi < GPW; ++gi) {
-      const int x = (wave + gi * NW) * LPW + grp;
-#pragma unroll
-      for (int b = 0; b < B2; ++b)
-#pragma unroll
-        for (int r = 0; r < R2; ++r) img[(jl + b * L + r * R1) * PITCH + x] = o[gi][b][r];
-    }
-  }
-  const double tot = block_sum<NT>(lsum, red);  // contains barriers
-  if (tid == 0) a.fid_partial[k] = tot;
-  if (!grad) return;
-
-  // forward DFT of dL/d(conj o): every row, then the columns that hold support
-#pragma unroll
-  for (int gi = 0; gi < GPW; ++gi) {
-    const int t = (wave + gi * NW) * LPW + grp;
-    cx<T> v[B2][R2];
-    LF::template run<false, true>(img, twl, t, jl, true, v);
-    LF::template store<true>(img, t, jl, true, v);
-  }
-  __syncthreads();
-  const int ncol = a.x_max - a.x_min + 1;
-  cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
-  cx<T>* D = static_cast<cx<T>*>(a.D) + (size_t)k * a.S;
-#pragma unroll
-  for (int gi = 0; gi < GPW; ++gi) {
-    const int g = wave + gi * NW;
-    if (g * LPW >= ncol) break;  // uniform per wavefront
-    const int x = a.x_min + g * LPW + grp;
-    const bool ok = x <= a.x_max;
-    cx<T> Y[B2][R2];
-    LF::template run<false, false>(img, twl, x, jl, ok, Y);
-    // contributions on the support; each butterfly's window and pupil loads go out together
-    const int xs = ok ? x : a.x_min;
-#pragma unroll
-    for (int b = 0; b < B2; ++b) {
-      cx<T> pw[R2], ww[R2];
-#pragma unroll
-      for (int r = 0; r < R2; ++r) {
-        const int y = jl + b * L + r * R1;
-        pw[r] = P[y * N + xs];
-        ww[r] = win[(size_t)y * a.n_hi + xs];
-      }
-      if (ok) {
-#pragma unroll
-        for (int r = 0; r < R2; ++r) {
-          const int y = jl + b * L + r * R1;
-          const int lo = sxlo[y];
-          if (x >= lo && x <= sxhi[y]) {
-            const int s = sroff[y] + x - lo;
-            const cx<T> yv = scale(Y[b][r], sc);
-            C[s] = cmulc(pw[r], yv);
-            D[s] = cmulc(ww[r], yv);
-          }
-        }
-      }
-    }
-  }
-}
-
-#else
 // Every pass of each 2-D transform is spread over the whole block (StockhamPass).
 template <class T, int N>
 __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
@@ -352,45 +118,61 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   }
   const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
   const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
+  const int mode = a.mode;
+  const bool stored = (mode & LED_STORED) != 0;
   __syncthreads();
 
-  // gather X = P * window, zeros off the support.  Every address of the window is
-  // valid, so the loads are unconditional and a batch of them is in flight at once.
-#pragma unroll
-  for (int i0 = 0; i0 < PPT; i0 += GB) {
-    cx<T> pv[GB], wv[GB];
-#pragma unroll
-    for (int i = 0; i < GB; ++i) {
-      const int p = tid + (i0 + i) * NT;
-      pv[i] = P[p];
-      wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
-    }
-#pragma unroll
-    for (int i = 0; i < GB; ++i) {
-      const int p = tid + (i0 + i) * NT;
-      const int y = p / N, x = p % N;
-      const bool in = x >= sxlo[y] && x <= sxhi[y];
-      img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
-    }
-  }
-  __syncthreads();
-
-  // inverse DFT: rows that hold support pixels, then every column
-  const int nband = a.y_max - a.y_min + 1;
-  P1iR::run(img, a.y_min, nband, twl, tid);
-  P2iR::run(img, a.y_min, nband, twl, tid);
-  P1iC::run(img, 0, N, twl, tid);
   // register (i, r) of the last column pass holds pixel y = jj[i] + r R1, x = mm[i]
   int mm[MB2], jj[MB2];
   bool lv[MB2];
   P2iC::coords(N, tid, mm, jj, lv);
   cx<T> o[MB2][R2];
-  P2iC::load(img, 0, mm, jj, lv, twl, o);
+  if (stored) {
+    // o from the fields of a forward call, in the kernel's (-1)^(x+y) frame
+    const cx<T>* fk = static_cast<const cx<T>*>(a.fields) + (size_t)k * N * N;
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = jj[i] + r * R1, x = mm[i];
+        const cx<T> f = fk[y * N + x];
+        o[i][r] = ((x + y) & 1) ? cx<T>{-f.x, -f.y} : f;
+      }
+    }
+  } else {
+    // gather X = P * window, zeros off the support.  Every address of the window is
+    // valid, so the loads are unconditional and a batch of them is in flight at once.
+#pragma unroll
+    for (int i0 = 0; i0 < PPT; i0 += GB) {
+      cx<T> pv[GB], wv[GB];
+#pragma unroll
+      for (int i = 0; i < GB; ++i) {
+        const int p = tid + (i0 + i) * NT;
+        pv[i] = P[p];
+        wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
+      }
+#pragma unroll
+      for (int i = 0; i < GB; ++i) {
+        const int p = tid + (i0 + i) * NT;
+        const int y = p / N, x = p % N;
+        const bool in = x >= sxlo[y] && x <= sxhi[y];
+        img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
+      }
+    }
+    __syncthreads();
+
+    // inverse DFT: rows that hold support pixels, then every column
+    const int nband = a.y_max - a.y_min + 1;
+    P1iR::run(img, a.y_min, nband, twl, tid);
+    P2iR::run(img, a.y_min, nband, twl, tid);
+    P1iC::run(img, 0, N, twl, tid);
+    P2iC::load(img, 0, mm, jj, lv, twl, o);
+  }
   __syncthreads();
 
   const T sc = T(a.inv_scale);
+  const T osc = stored ? T(1) : sc;  // stored fields are scaled already
   const T eps = T(a.eps);
-  const int mode = a.mode;
   const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
   const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
   T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
@@ -409,7 +191,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
       const int y = j + r * R1;
-      const cx<T> ov = scale(o[i][r], sc);
+      const cx<T> ov = scale(o[i][r], osc);
       o[i][r] = ov;
       const size_t pix = (size_t)k * N * N + (size_t)y * N + x;
       if (mode & LED_FIELDS) {
@@ -526,7 +308,6 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     }
   }
 }
-#endif
 
 // ---------------------------------------------------------------------------
 // Object-branch FFTs on the n_hi x n_hi spectrum: RPB rows (or columns) per block.

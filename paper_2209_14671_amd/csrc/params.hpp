@@ -9,7 +9,8 @@ enum LedMode : int {
   LED_GRAD = 1,     // residual, W and the back-projected contributions C, D
   LED_FIELDS = 2,   // write the complex low-resolution fields
   LED_INTENS = 4,   // write |o|^2
-  LED_LOSS = 8      // fidelity loss partial per LED
+  LED_LOSS = 8,     // fidelity loss partial per LED
+  LED_STORED = 16   // read the fields (as written by LED_FIELDS) instead of recomputing them
 };
 
 struct LedArgs {
@@ -18,7 +19,7 @@ struct LedArgs {
   const void* meas;     // K x n_lo x n_lo real
   void* C;              // K x S complex: conj(P) Y_k on the support (spectrum gradient part)
   void* D;              // K x S complex: conj(M_k Psi) Y_k on the support (pupil gradient part)
-  void* fields;         // K x n_lo x n_lo complex (optional)
+  void* fields;         // K x n_lo x n_lo complex (optional; input in LED_STORED mode)
   void* intens;         // K x n_lo x n_lo real (optional)
   double* fid_partial;  // K doubles
   const int* win;       // K x 2: (row y0, column x0) of each window

@@ -231,8 +231,10 @@ class Plan:
             out["loss4"] = l4
         return out
 
-    def grad(self, psi, P, meas, want_gP=True):
-        """(loss4, dL/d conj(psi), dL_fid/d conj(P) or None) at (psi, P) (Eq. 8, 15, 18)."""
+    def grad(self, psi, P, meas, want_gP=True, fields=None):
+        """(loss4, dL/d conj(psi), dL_fid/d conj(P) or None) at (psi, P) (Eq. 8, 15, 18).
+        With `fields` (the K x n_lo x n_lo complex fields of forward at the same psi, P)
+        the per-LED fields are read instead of recomputed."""
         self._need(psi, self.spec_shape, self.cdtype, "psi")
         self._need(P, self.pupil_shape, self.cdtype, "P")
         self._need(meas, self.stack_shape, self.rdtype, "meas")
@@ -240,8 +242,13 @@ class Plan:
         g = torch.empty(self.spec_shape, dtype=self.cdtype, **kw)
         gP = torch.empty(self.pupil_shape, dtype=self.cdtype, **kw) if want_gP else None
         l4 = torch.empty(4, dtype=torch.float64, **kw)
-        self._check(self.lib.elfpie_grad(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(g), _ptr(gP),
-                                         _ptr(l4), _stream()))
+        if fields is None:
+            self._check(self.lib.elfpie_grad(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(g), _ptr(gP),
+                                             _ptr(l4), _stream()))
+        else:
+            self._need(fields, self.stack_shape, self.cdtype, "fields")
+            self._check(self.lib.elfpie_grad_fields(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(fields),
+                                                    _ptr(g), _ptr(gP), _ptr(l4), _stream()))
         return l4, g, gP
 
     def step(self, st: State, meas, want_loss=True):
@@ -283,27 +290,50 @@ class Plan:
 
 
 class ElfpieLoss(torch.autograd.Function):
-    """L(psi, P) of Eq. (8) as an autograd function.  backward calls the library's
-    closed-form gradient (Eq. 15, 18), recomputing the per-LED fields.  torch stores
-    2 dL/d(conj z) as the gradient of a real loss wrt a complex z."""
+    """L(psi, P) of Eq. (8) as an autograd function whose backward is the library's
+    closed-form gradient (Eq. 15, 18).  With store_fields=False the backward
+    recomputes the per-LED fields; with True the forward keeps them (K n_lo^2
+    complex) and the backward reads them.  torch's gradient of a real loss with
+    respect to a complex tensor z is 2 dL/d(conj z)."""
 
     @staticmethod
-    def forward(ctx, psi, P, plan: Plan, meas):
-        out = plan.forward(psi.detach().contiguous(), P.detach().contiguous(), meas, loss=True)
+    def forward(ctx, psi, P, plan: Plan, meas, store_fields=False):
+        psi_c, P_c = psi.detach().contiguous(), P.detach().contiguous()
+        out = plan.forward(psi_c, P_c, meas, fields=store_fields, loss=True)
         ctx.plan = plan
-        ctx.save_for_backward(psi, P, meas)
+        saved = [psi_c, P_c, meas] + ([out["fields"]] if store_fields else [])
+        ctx.save_for_backward(*saved)
         return out["loss4"][3].clone()
 
     @staticmethod
     def backward(ctx, g_out):
-        psi, P, meas = ctx.saved_tensors
-        _, g, gP = ctx.plan.grad(psi.detach().contiguous(), P.detach().contiguous(), meas,
-                                 want_gP=ctx.needs_input_grad[1])
+        psi, P, meas, *kept = ctx.saved_tensors
+        _, g, gP = ctx.plan.grad(psi, P, meas, want_gP=ctx.needs_input_grad[1], fields=kept[0] if kept else None)
         s = (2.0 * g_out).to(ctx.plan.rdtype)
         gpsi = g * s if ctx.needs_input_grad[0] else None
         gp = gP * s if (gP is not None and ctx.needs_input_grad[1]) else None
-        return gpsi, gp, None, None
+        return gpsi, gp, None, None, None
 
 
-def elfpie_loss(psi, P, plan: Plan, meas):
-    return ElfpieLoss.apply(psi, P, plan, meas)
+class SpectrumFromObject(torch.autograd.Function):
+    """Psi = fftshift(fft2(O)) / n_hi on the library's transform.  The map is
+    unitary, so its backward is the inverse transform."""
+
+    @staticmethod
+    def forward(ctx, obj, plan: Plan):
+        ctx.plan = plan
+        return plan.spectrum_from_object(obj.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.object_from_spectrum(g.contiguous()), None
+
+
+def elfpie_loss(psi, P, plan: Plan, meas, store_fields=False):
+    """L(psi, P), differentiable in psi and P."""
+    return ElfpieLoss.apply(psi, P, plan, meas, store_fields)
+
+
+def elfpie_loss_object(obj, P, plan: Plan, meas, store_fields=False):
+    """L as a function of the object O (Psi = fftshift(fft2 O) / n_hi) and P."""
+    return ElfpieLoss.apply(SpectrumFromObject.apply(obj, plan), P, plan, meas, store_fields)
