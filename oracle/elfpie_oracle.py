@@ -11,7 +11,8 @@ iterative engine", arXiv 2209.14671):
 
 * forward model, Sec. 3.1 Eq. (1) with one LED per exposure (M = 1, Sec. 4.1);
 * data fidelity on image gradients, Sec. 3.2 Eq. (4) amplitude / Eq. (5) intensity,
-  with the L1 normaliser of Eq. (12) (anisotropic sign or isotropic);
+  with the L1 normaliser of Eq. (12) (anisotropic sign or isotropic), and the other
+  scalings g of Eq. (3) that Sec. 6.3 tries: x^gamma and ln(x + 1);
 * Hessian penalties on amplitude and phase, Eq. (6), (7), combined by Eq. (8);
 * closed-form Wirtinger gradients, Eq. (9)-(11), (13)-(15) for the spectrum and
   Eq. (18) for the pupil;
@@ -55,6 +56,8 @@ import numpy as np
 
 FID_AMPLITUDE = 0
 FID_INTENSITY = 1
+FID_GAMMA = 2     # g(x) = x^gamma in Eq. (3), Sec. 6.3
+FID_LOG = 3       # g(x) = ln(x + 1) in Eq. (3), Sec. 6.3
 NORM_ANISO = 0
 NORM_ISO = 1
 LEARN_PUPIL = 1
@@ -79,9 +82,10 @@ class Problem:
     eta_opt: float = 1e-8             # Eq. (19)
     eta_h: float = 1e-6               # Eq. (14)
     l1_eps: float = 0.0               # smoothing of the L1 terms (0 = exact)
-    fidelity: int = FID_INTENSITY     # Eq. (4) or Eq. (5)
+    fidelity: int = FID_INTENSITY     # Eq. (4), Eq. (5), or g of Eq. (3) (Sec. 6.3)
     norm: int = NORM_ANISO            # Eq. (12)
     flags: int = PUPIL_SUPPORT
+    fid_gamma: float = 0.5            # the exponent of FID_GAMMA
 
     @property
     def n_hi(self) -> int:
@@ -333,19 +337,47 @@ def l1_value_and_omega(comps, norm: int, eps: float):
 # Loss and closed-form gradients
 # ----------------------------------------------------------------------------
 
-def fidelity_residual(o: np.ndarray, meas: np.ndarray, fidelity: int):
-    """Residual inside the gradient operator: |o| - sqrt(I) (Eq. 4) or |o|^2 - I (Eq. 5)."""
+def scaling(x: np.ndarray, fidelity: int, gamma: float = 0.5) -> np.ndarray:
+    """The pixel-wise scaling g of Eq. (3) applied to intensities x >= 0: sqrt (Eq. 4),
+    identity (Eq. 5), x^gamma or ln(x + 1) (Sec. 6.3)."""
+    if fidelity == FID_AMPLITUDE:
+        return np.sqrt(x)
+    if fidelity == FID_GAMMA:
+        return x ** gamma
+    if fidelity == FID_LOG:
+        return np.log1p(x)
+    return x
+
+
+def scaling_slope(x: np.ndarray, fidelity: int, gamma: float = 0.5) -> np.ndarray:
+    """g'(x) for x > 0; 0 where x = 0 for the powers (their slope is unbounded there)."""
+    if fidelity == FID_AMPLITUDE:
+        return np.divide(0.5, np.sqrt(x), out=np.zeros_like(x), where=x > 0)
+    if fidelity == FID_GAMMA:
+        return np.where(x > 0, gamma * np.power(np.where(x > 0, x, 1.0), gamma - 1.0), 0.0)
+    if fidelity == FID_LOG:
+        return 1.0 / (1.0 + x)
+    return np.ones_like(x)
+
+
+def fidelity_residual(o: np.ndarray, meas: np.ndarray, fidelity: int, gamma: float = 0.5):
+    """Residual inside the gradient operator, g(|o|^2) - g(I): |o| - sqrt(I) (Eq. 4),
+    |o|^2 - I (Eq. 5), or the gamma / log scalings of Sec. 6.3 (negative readings of a
+    noisy I are taken as 0 wherever g needs x >= 0)."""
     if fidelity == FID_AMPLITUDE:
         return np.abs(o) - np.sqrt(np.clip(meas, 0.0, None))
-    return np.abs(o) ** 2 - meas
+    if fidelity == FID_INTENSITY:
+        return np.abs(o) ** 2 - meas
+    return scaling(np.abs(o) ** 2, fidelity, gamma) - scaling(np.clip(meas, 0.0, None), fidelity, gamma)
 
 
 def fidelity_loss_and_grad(psi, P, meas, prob: Problem, want_grad: bool = True):
     """L_fid and its Wirtinger gradients wrt conj(Psi) (Eq. 9) and conj(P) (Eq. 18).
 
     For every LED: o = F_B P M Psi; e = residual; L += rho(grad e);
-    dL/de = grad^T omega; dL/d(conj o) = dL/de * o / (2|o|) (amplitude) or * o
-    (intensity); back-projection Y = F_B^H dL/d(conj o); then
+    dL/de = grad^T omega; dL/d(conj o) = dL/de * g'(|o|^2) * o, which is
+    dL/de * o / (2|o|) for the amplitude and dL/de * o for the intensity;
+    back-projection Y = F_B^H dL/d(conj o); then
     g_Psi += M^T (conj(P) Y) and g_P += conj(M Psi) Y, LEDs in ascending order.
     """
     org = window_origins(prob)
@@ -357,7 +389,7 @@ def fidelity_loss_and_grad(psi, P, meas, prob: Problem, want_grad: bool = True):
     for k in range(prob.K):
         c = crop(psi, org[k], n)
         o = lowres_field(Pe * c, prob.upsample)
-        e = fidelity_residual(o, meas[k], prob.fidelity)
+        e = fidelity_residual(o, meas[k], prob.fidelity, prob.fid_gamma)
         val, (wx, wy) = l1_value_and_omega([dx(e), dy(e)], prob.norm, prob.l1_eps)
         L += val
         if not want_grad:
@@ -366,8 +398,10 @@ def fidelity_loss_and_grad(psi, P, meas, prob: Problem, want_grad: bool = True):
         if prob.fidelity == FID_AMPLITUDE:
             a = np.abs(o)
             dob = np.divide(q * o, 2.0 * a, out=np.zeros_like(o), where=a > 0)
-        else:
+        elif prob.fidelity == FID_INTENSITY:
             dob = q * o
+        else:
+            dob = q * scaling_slope(np.abs(o) ** 2, prob.fidelity, prob.fid_gamma) * o
         Y = lowres_field_adjoint(dob, prob.upsample)
         g_psi[org[k][0]:org[k][0] + n, org[k][1]:org[k][1] + n] += np.conj(Pe) * Y
         g_P += np.conj(c) * Y
@@ -517,11 +551,15 @@ def noise_level(clean: np.ndarray, noisy: np.ndarray, dark: np.ndarray) -> float
     return 100.0 * float(np.mean(r)) if r else 0.0
 
 
-def auto_penalty(meas: np.ndarray, fidelity: int) -> float:
+def auto_penalty(meas: np.ndarray, fidelity: int, gamma: float = 0.5) -> float:
     """Eq. (16) (intensity) / Eq. (17) (amplitude): alpha = beta from the stack, with the
-    3x3 mask as printed and a 'valid' convolution averaged over W*H pixels."""
+    3x3 mask as printed and a 'valid' convolution averaged over W*H pixels.  For the
+    Sec. 6.3 scalings the mask is applied to g(I), as Eq. (17) applies it to sqrt(I)."""
     mask = np.array([[-1.0, 2.0, -1.0], [-2.0, 4.0, -2.0], [-1.0, 2.0, -1.0]])
-    src = np.sqrt(np.clip(meas, 0, None)) if fidelity == FID_AMPLITUDE else meas
+    if fidelity == FID_INTENSITY:
+        src = meas
+    else:
+        src = scaling(np.clip(meas, 0, None), fidelity, gamma)
     K, H, W = src.shape
     acc = 0.0
     for k in range(K):

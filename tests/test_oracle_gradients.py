@@ -18,12 +18,12 @@ from helpers import rand_complex, smooth_object
 
 
 def make_problem(fidelity, norm, *, n_lo=8, upsample=2, grid=3, na=0.15, eps=1e-2,
-                 alpha=0.3, beta=0.2, flags=orc.PUPIL_SUPPORT, seed=0):
+                 alpha=0.3, beta=0.2, flags=orc.PUPIL_SUPPORT, seed=0, gamma=0.5):
     optics = synth.Optics(n_lo=n_lo, upsample=upsample, na=na, led_grid=grid)
     pos = synth.led_grid_positions(grid, optics.pitch_mm)
     k = synth.led_wavevectors(pos, optics.height_mm, optics.wavelength_um)
     prob = orc.problem_from_optics(optics, k, fidelity=fidelity, norm=norm, l1_eps=eps,
-                                   eta_h=0.0, alpha=alpha, beta=beta, flags=flags)
+                                   eta_h=0.0, alpha=alpha, beta=beta, flags=flags, fid_gamma=gamma)
     rng = np.random.default_rng(seed)
     O = smooth_object(seed, prob.n_hi)
     psi = orc.spectrum_from_object(O)
@@ -45,19 +45,23 @@ def fd_check(fun, z, g, rng, n_dir=4, h=1e-5):
 
 
 CASES = [(f, n) for f in (orc.FID_AMPLITUDE, orc.FID_INTENSITY) for n in (orc.NORM_ANISO, orc.NORM_ISO)]
+# the scalings g(x) = x^gamma and ln(x + 1) of Sec. 6.3, as (fidelity, gamma)
+SCALINGS = [(orc.FID_GAMMA, 0.125), (orc.FID_GAMMA, 0.375), (orc.FID_GAMMA, 0.875), (orc.FID_LOG, 0.5)]
+GCASES = [(f, n, g) for f, n in CASES for g in (0.5,)] + [(f, n, g) for f, g in SCALINGS
+                                                         for n in (orc.NORM_ANISO, orc.NORM_ISO)]
 
 
-@pytest.mark.parametrize("fidelity,norm", CASES)
-def test_psi_gradient_matches_finite_differences(fidelity, norm):
-    prob, psi, P, meas = make_problem(fidelity, norm)
+@pytest.mark.parametrize("fidelity,norm,gamma", GCASES)
+def test_psi_gradient_matches_finite_differences(fidelity, norm, gamma):
+    prob, psi, P, meas = make_problem(fidelity, norm, gamma=gamma)
     _, g_psi, _ = orc.loss_and_grad(psi, P, meas, prob)
     err = fd_check(lambda z: orc.loss(z, P, meas, prob), psi, g_psi, np.random.default_rng(1))
     assert err < 1e-6, err
 
 
-@pytest.mark.parametrize("fidelity,norm", CASES)
-def test_pupil_gradient_matches_finite_differences(fidelity, norm):
-    prob, psi, P, meas = make_problem(fidelity, norm, flags=0)
+@pytest.mark.parametrize("fidelity,norm,gamma", GCASES)
+def test_pupil_gradient_matches_finite_differences(fidelity, norm, gamma):
+    prob, psi, P, meas = make_problem(fidelity, norm, flags=0, gamma=gamma)
     _, _, g_P = orc.loss_and_grad(psi, P, meas, prob)
     err = fd_check(lambda z: orc.loss(psi, z, meas, prob), P, g_P, np.random.default_rng(2))
     assert err < 1e-6, err
@@ -125,6 +129,12 @@ def brute_fidelity(psi, P, meas, prob):
                 o[yy, xx] = acc / (r * n)
         if prob.fidelity == orc.FID_AMPLITUDE:
             e = np.abs(o) - np.sqrt(meas[kk])
+        elif prob.fidelity == orc.FID_GAMMA:
+            e = np.array([[math.pow(abs(o[yy, xx]) ** 2, prob.fid_gamma) - math.pow(meas[kk, yy, xx], prob.fid_gamma)
+                           for xx in range(n)] for yy in range(n)])
+        elif prob.fidelity == orc.FID_LOG:
+            e = np.array([[math.log(1 + abs(o[yy, xx]) ** 2) - math.log(1 + meas[kk, yy, xx])
+                           for xx in range(n)] for yy in range(n)])
         else:
             e = np.abs(o) ** 2 - meas[kk]
         for yy in range(n):
@@ -138,9 +148,9 @@ def brute_fidelity(psi, P, meas, prob):
     return total
 
 
-@pytest.mark.parametrize("fidelity,norm", CASES)
-def test_fidelity_loss_matches_brute_force(fidelity, norm):
-    prob, psi, P, meas = make_problem(fidelity, norm, eps=0.0, n_lo=6, upsample=2, grid=2, na=0.2)
+@pytest.mark.parametrize("fidelity,norm,gamma", GCASES)
+def test_fidelity_loss_matches_brute_force(fidelity, norm, gamma):
+    prob, psi, P, meas = make_problem(fidelity, norm, eps=0.0, n_lo=6, upsample=2, grid=2, na=0.2, gamma=gamma)
     Lf, _, _ = orc.fidelity_loss_and_grad(psi, P, meas, prob, want_grad=False)
     assert abs(Lf - brute_fidelity(psi, P, meas, prob)) < 1e-10 * max(1.0, Lf)
 
@@ -192,3 +202,34 @@ def test_phase_gradient_is_tangent_to_object_modulus():
     G = orc.object_from_spectrum(gH)
     O = orc.object_from_spectrum(psi)
     assert np.max(np.abs(np.real(np.conj(O) * G))) < 1e-12 * np.max(np.abs(G))
+
+
+@pytest.mark.parametrize("gamma,same_as", [(0.5, orc.FID_AMPLITUDE), (1.0, orc.FID_INTENSITY)])
+@pytest.mark.parametrize("norm", [orc.NORM_ANISO, orc.NORM_ISO])
+def test_gamma_scaling_reduces_to_amplitude_and_intensity(gamma, same_as, norm):
+    """g(x) = x^gamma is Eq. (4) at gamma = 1/2 and Eq. (5) at gamma = 1 (Sec. 6.3): the
+    general branch must give their losses and gradients."""
+    prob_g, psi, P, meas = make_problem(orc.FID_GAMMA, norm, gamma=gamma, flags=0)
+    prob_r, _, _, _ = make_problem(same_as, norm, flags=0)
+    lg, gg, pg = orc.loss_and_grad(psi, P, meas, prob_g)
+    lr, gr, pr = orc.loss_and_grad(psi, P, meas, prob_r)
+    assert np.allclose(lg, lr, rtol=1e-12, atol=0)
+    assert np.linalg.norm(gg - gr) <= 1e-12 * np.linalg.norm(gr)
+    assert np.linalg.norm(pg - pr) <= 1e-12 * np.linalg.norm(pr)
+
+
+@pytest.mark.parametrize("fidelity,gamma", SCALINGS)
+def test_scaling_zero_residual(fidelity, gamma):
+    """With I from the forward model itself, every scaling gives a zero loss and gradient."""
+    prob, psi, P, _ = make_problem(fidelity, orc.NORM_ANISO, eps=0.0, gamma=gamma)
+    meas = orc.intensities(psi, P, prob)
+    Lf, g_psi, g_P = orc.fidelity_loss_and_grad(psi, P, meas, prob)
+    assert Lf < 1e-9
+    assert np.max(np.abs(g_psi)) < 1e-9 and np.max(np.abs(g_P)) < 1e-9
+
+
+def test_log_scaling_slope_is_exact_at_zero():
+    """ln(x + 1) is smooth at x = 0 (slope 1), unlike the powers, whose slope is taken as 0."""
+    x = np.array([0.0, 1.0, 3.0])
+    assert np.allclose(orc.scaling_slope(x, orc.FID_LOG), [1.0, 0.5, 0.25])
+    assert np.allclose(orc.scaling_slope(x, orc.FID_GAMMA, 0.5), [0.0, 0.5, 0.5 / math.sqrt(3.0)])
