@@ -60,7 +60,12 @@ typedef enum {
   ELFPIE_E_NONFINITE = 6     /* a checked run produced a NaN / Inf loss            */
 } elfpie_status;
 
-enum { ELFPIE_FID_AMPLITUDE = 0, ELFPIE_FID_INTENSITY = 1 }; /* Eq. 4 / Eq. 5 */
+/* The scaling g of the data fidelity (Eq. 3): g(x) = sqrt(x) (Eq. 4), x (Eq. 5), and
+ * the two Sec. 6.3 tries, x^gamma (gamma = fid_gamma) and ln(x + 1).  The residual
+ * inside the gradient operator is g(|o|^2) - g(I) with negative readings of I taken
+ * as 0 (except for g(x) = x); the gradient carries g'(|o|^2), taken as 0 at |o| = 0
+ * for the powers. */
+enum { ELFPIE_FID_AMPLITUDE = 0, ELFPIE_FID_INTENSITY = 1, ELFPIE_FID_GAMMA = 2, ELFPIE_FID_LOG = 3 };
 enum { ELFPIE_NORM_ANISO = 0, ELFPIE_NORM_ISO = 1 };          /* Eq. 12        */
 enum { ELFPIE_F64 = 0, ELFPIE_F32 = 1 };                      /* arithmetic    */
 enum {
@@ -88,6 +93,7 @@ typedef struct {
   int32_t norm;            /* ELFPIE_NORM_* (fidelity and Hessian terms)                    */
   int32_t precision;       /* ELFPIE_F32 or ELFPIE_F64                                      */
   uint32_t flags;          /* ELFPIE_LEARN_PUPIL | ELFPIE_PUPIL_SUPPORT | ELFPIE_PUPIL_FILTER */
+  double fid_gamma;        /* exponent of ELFPIE_FID_GAMMA, in (0, 4]; ignored otherwise    */
 } elfpie_problem;
 
 /* Optimiser state (Eq. 19), all DEVICE pointers owned by the caller.
@@ -112,7 +118,8 @@ typedef struct elfpie_plan elfpie_plan;
 
 /* Fill `p` with the defaults of Eq. 19 and Sec. 4.1: alpha = beta = 1e-3,
  * lr = 1e-2, gamma1 = 0.9, gamma2 = 0.999, eta_opt = 1e-8, eta_h = 1e-6,
- * l1_eps = 0, intensity fidelity, anisotropic norm, F32, PUPIL_SUPPORT.
+ * l1_eps = 0, intensity fidelity (fid_gamma = 0.5), anisotropic norm, F32,
+ * PUPIL_SUPPORT.
  * Geometry fields are zeroed. */
 elfpie_status elfpie_problem_defaults(elfpie_problem *p);
 

@@ -99,8 +99,10 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   if (!(p->eta_opt >= 0) || !(p->eta_h >= 0) || !(p->l1_eps >= 0) || !std::isfinite(p->eta_opt) ||
       !std::isfinite(p->eta_h) || !std::isfinite(p->l1_eps))
     return fail(ELFPIE_E_INVALID, "eta_opt, eta_h and l1_eps must be finite and >= 0");
-  if (p->fidelity != ELFPIE_FID_AMPLITUDE && p->fidelity != ELFPIE_FID_INTENSITY)
-    return fail(ELFPIE_E_INVALID, "fidelity must be ELFPIE_FID_AMPLITUDE or ELFPIE_FID_INTENSITY");
+  if (p->fidelity < ELFPIE_FID_AMPLITUDE || p->fidelity > ELFPIE_FID_LOG)
+    return fail(ELFPIE_E_INVALID, "fidelity must be one of ELFPIE_FID_*");
+  if (p->fidelity == ELFPIE_FID_GAMMA && !(p->fid_gamma > 0 && p->fid_gamma <= 4))
+    return fail(ELFPIE_E_INVALID, "fid_gamma must lie in (0, 4]");
   if (p->norm != ELFPIE_NORM_ANISO && p->norm != ELFPIE_NORM_ISO)
     return fail(ELFPIE_E_INVALID, "norm must be ELFPIE_NORM_ANISO or ELFPIE_NORM_ISO");
   if (p->flags & ~7u) return fail(ELFPIE_E_INVALID, "unknown flag bits");
@@ -310,6 +312,7 @@ struct Ops {
     a.mode = mode;
     a.t_bump = reinterpret_cast<long long*>(t_bump);
     a.fidelity = pl->prob.fidelity;
+    a.fid_gamma = pl->prob.fid_gamma;
     a.norm = pl->prob.norm;
     switch (tb.n_lo) {
       case 32: k_led<T, 32><<<tb.K, LedShape<32>::NT, 0, s>>>(a); break;
@@ -758,6 +761,7 @@ elfpie_status elfpie_problem_defaults(elfpie_problem* p) {
   p->eta_h = 1e-6;
   p->l1_eps = 0.0;
   p->fidelity = ELFPIE_FID_INTENSITY;
+  p->fid_gamma = 0.5;
   p->norm = ELFPIE_NORM_ANISO;
   p->precision = ELFPIE_F32;
   p->flags = ELFPIE_PUPIL_SUPPORT;

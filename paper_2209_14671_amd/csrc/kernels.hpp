@@ -47,6 +47,35 @@ __device__ __forceinline__ T omega(T d, T eps) {
   return T((d > T(0)) - (d < T(0)));
 }
 // 1 / ||c|| for the isotropic normaliser (0 at the origin when eps = 0).
+// The scaling g of the fidelity (Eq. 3) on an intensity: sqrt, identity, x^gamma, ln(x + 1).
+__device__ __forceinline__ float pow_t(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double pow_t(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float log1p_t(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_t(double x) { return log1p(x); }
+
+// Residual g(|o|^2) - g(I) from i2 = |o|^2 and the reading m.
+template <class T>
+__device__ __forceinline__ T fid_residual(int fid, T i2, T m, T gam) {
+  const T mp = m > T(0) ? m : T(0);
+  if (fid == 0) return sqrt(i2) - sqrt(mp);
+  if (fid == 2) return pow_t(i2, gam) - pow_t(mp, gam);
+  if (fid == 3) return log1p_t(i2) - log1p_t(mp);
+  return i2 - m;
+}
+
+// dL/d(conj o) = q g'(|o|^2) o; g'(0) is taken as 0 for the powers.
+template <class T>
+__device__ __forceinline__ cx<T> fid_wirtinger(int fid, cx<T> ov, T q, T gam) {
+  const T i2 = norm2(ov);
+  if (fid == 1) return scale(ov, q);
+  if (fid == 0) {
+    const T am = sqrt(i2);
+    return am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
+  }
+  if (fid == 2) return i2 > T(0) ? scale(ov, q * gam * pow_t(i2, gam - T(1))) : czero<T>();
+  return scale(ov, q / (T(1) + i2));
+}
+
 template <class T>
 __device__ __forceinline__ T inv_norm(T s2, T eps) {
   if (eps > T(0)) return T(1) / sqrt(s2 + eps * eps);
@@ -173,6 +202,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const T sc = T(a.inv_scale);
   const T osc = stored ? T(1) : sc;  // stored fields are scaled already
   const T eps = T(a.eps);
+  const T gam = T(a.fid_gamma);
   const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
   const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
   T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
@@ -202,7 +232,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
       if (need_e) {
         const T m = mv[i][r];
-        eb[y * PITCH + x] = (a.fidelity == 0) ? sqrt(i2) - sqrt(m > T(0) ? m : T(0)) : i2 - m;
+        eb[y * PITCH + x] = fid_residual(a.fidelity, i2, m, gam);
       }
     }
   }
@@ -245,13 +275,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         }
         lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
       }
-      const cx<T> ov = o[i][r];
-      if (a.fidelity == 0) {
-        const T am = sqrt(norm2(ov));
-        o[i][r] = am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
-      } else {
-        o[i][r] = scale(ov, q);
-      }
+      o[i][r] = fid_wirtinger(a.fidelity, o[i][r], q, gam);
     }
   }
   __syncthreads();  // every residual read is done; the tile can be overwritten

@@ -34,8 +34,9 @@ struct LedArgs {
   double inv_scale;     // 1 / (r n_lo)
   double eps;           // L1 smoothing
   int mode;
-  int fidelity;
+  int fidelity;         // ELFPIE_FID_*: the scaling g of the residual
   int norm;
+  double fid_gamma;     // exponent of g(x) = x^gamma
   long long* t_bump;    // step counter, advanced once by block 0 in step mode (else NULL)
 };
 

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (F32, F64, FID_AMPLITUDE, FID_INTENSITY, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
+from ._lib import (F32, F64, FID_AMPLITUDE, FID_GAMMA, FID_INTENSITY, FID_LOG, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
                    PUPIL_FILTER, PUPIL_SUPPORT, ElfpieError)
 
 
@@ -41,6 +41,7 @@ class Problem:
     norm: int = NORM_ANISO
     precision: int = F32
     flags: int = PUPIL_SUPPORT
+    fid_gamma: float = 0.5          # exponent of FID_GAMMA
 
     def to_c(self):
         k = np.ascontiguousarray(np.asarray(self.led_k, dtype=np.float64).reshape(-1, 2))
@@ -52,6 +53,7 @@ class Problem:
         p.gamma1, p.gamma2, p.eta_opt = float(self.gamma1), float(self.gamma2), float(self.eta_opt)
         p.eta_h, p.l1_eps = float(self.eta_h), float(self.l1_eps)
         p.fidelity, p.norm, p.precision, p.flags = int(self.fidelity), int(self.norm), int(self.precision), int(self.flags)
+        p.fid_gamma = float(self.fid_gamma)
         return p, k  # keep k alive while p is used
 
 

@@ -105,6 +105,8 @@ def test_workspace_size_accounts_for_every_buffer(lib):
     (dict(lr=0.0), 1),
     (dict(alpha=-1.0), 1),
     (dict(fidelity=5), 1),
+    (dict(fidelity=2, fid_gamma=0.0), 1),      # x^gamma needs gamma > 0
+    (dict(fidelity=2, fid_gamma=5.0), 1),
     (dict(norm=3), 1),
     (dict(flags=64), 1),
     (dict(dx_lo_um=0.0), 1),                   # pixel size must be positive

@@ -80,28 +80,32 @@ def test_forward_fields_intensities_loss(n_lo, up, grid, f32):
     assert np.all(el < tol["loss"])
 
 
-GRAD_CASES = [(f, n, f32) for f in (orc.FID_INTENSITY, orc.FID_AMPLITUDE) for n in (orc.NORM_ANISO, orc.NORM_ISO)
+GRAD_CASES = [(f, n, f32, 0.5) for f in (orc.FID_INTENSITY, orc.FID_AMPLITUDE) for n in (orc.NORM_ANISO, orc.NORM_ISO)
               for f32 in (False, True)]
+# the Sec. 6.3 scalings g(x) = x^gamma and ln(x + 1)
+GRAD_CASES += [(orc.FID_GAMMA, n, f32, g) for g in (0.375, 0.875) for n in (orc.NORM_ANISO, orc.NORM_ISO)
+               for f32 in (False, True)]
+GRAD_CASES += [(orc.FID_LOG, n, f32, 0.5) for n in (orc.NORM_ANISO, orc.NORM_ISO) for f32 in (False, True)]
 
 
-@pytest.mark.parametrize("fidelity,norm,f32", GRAD_CASES)
-def test_gradients_match_oracle(fidelity, norm, f32):
-    pair = make_pair(32, 4, 5, f32=f32, fidelity=fidelity, norm=norm)
+@pytest.mark.parametrize("fidelity,norm,f32,gamma", GRAD_CASES)
+def test_gradients_match_oracle(fidelity, norm, f32, gamma):
+    pair = make_pair(32, 4, 5, f32=f32, fidelity=fidelity, norm=norm, fid_gamma=gamma)
     plan = make_plan(pair, f32)
     l4, g, gP = plan.grad(dev(pair.psi, f32), dev(pair.P, f32), dev(pair.meas, f32))
     torch.cuda.synchronize()
     rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
     eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
     el = np.abs(host(l4) - rl4) / np.abs(rl4)
-    print(f"fid={fidelity} norm={norm} f32={f32}: g_psi {eg:.2e} g_P {egp:.2e} loss {el}")
+    print(f"fid={fidelity} gamma={gamma} norm={norm} f32={f32}: g_psi {eg:.2e} g_P {egp:.2e} loss {el}")
     tol = TOL[f32]
     assert eg < tol["grad"] and egp < tol["grad"]
     assert np.all(el < tol["loss"])
 
 
-@pytest.mark.parametrize("fidelity,norm,f32", GRAD_CASES)
-def test_step_matches_oracle(fidelity, norm, f32):
-    pair = make_pair(32, 4, 5, f32=f32, fidelity=fidelity, norm=norm)
+@pytest.mark.parametrize("fidelity,norm,f32,gamma", GRAD_CASES)
+def test_step_matches_oracle(fidelity, norm, f32, gamma):
+    pair = make_pair(32, 4, 5, f32=f32, fidelity=fidelity, norm=norm, fid_gamma=gamma)
     plan = make_plan(pair, f32)
     st = gpu_state(plan, pair, f32)
     l4 = plan.step(st, dev(pair.meas, f32))
@@ -109,7 +113,8 @@ def test_step_matches_oracle(fidelity, norm, f32):
     ref, rl4 = orc.step(pair.state, pair.meas, pair.oprob)
     res = {k: rel_l2(host(getattr(st, k)), getattr(ref, k)) for k in ("psi", "P", "mu_psi", "mu_P", "delta_psi")}
     res["v_psi"] = rel_l2(host(st.v_psi), ref.v_psi)
-    print(f"fid={fidelity} norm={norm} f32={f32}: " + " ".join(f"{k} {v:.2e}" for k, v in res.items()))
+    print(f"fid={fidelity} gamma={gamma} norm={norm} f32={f32}: " +
+          " ".join(f"{k} {v:.2e}" for k, v in res.items()))
     assert int(st.t.item()) == ref.t
     tol = TOL[f32]
     assert res["psi"] < tol["state"] and res["P"] < tol["state"]
