@@ -17,7 +17,10 @@ iterative engine", arXiv 2209.14671):
 * closed-form Wirtinger gradients, Eq. (9)-(11), (13)-(15) for the spectrum and
   Eq. (18) for the pupil;
 * the modified AdaBelief update, Eq. (19), and the order of Algorithm 1, including
-  the 3x3 Gaussian pre-filter of the pupil noted under Algorithm 1.
+  the 3x3 Gaussian pre-filter of the pupil noted under Algorithm 1; for the
+  comparison of Sec. 6.2 also plain gradient descent, NAdam and AdaBelief, from
+  their published definitions;
+* the automatic penalty weight of Eq. (16) / (17).
 
 Where the paper is silent or inconsistent the readings below are used (each is
 listed with its reason in the design notes):
@@ -63,6 +66,11 @@ NORM_ISO = 1
 LEARN_PUPIL = 1
 PUPIL_SUPPORT = 2
 PUPIL_FILTER = 4
+# optimisers compared in Sec. 6.2 (Fig. 13): the paper's Eq. (19) and three published ones
+OPT_ELFPIE = 0      # Eq. (19)
+OPT_SGD = 1         # plain gradient descent
+OPT_NADAM = 2       # Nesterov-accelerated Adam (Dozat, 2016), constant momentum
+OPT_ADABELIEF = 3   # AdaBelief (Zhuang et al., 2020)
 
 
 @dataclasses.dataclass
@@ -86,6 +94,7 @@ class Problem:
     norm: int = NORM_ANISO            # Eq. (12)
     flags: int = PUPIL_SUPPORT
     fid_gamma: float = 0.5            # the exponent of FID_GAMMA
+    optimizer: int = OPT_ELFPIE       # update rule for Psi and P (Sec. 6.2)
 
     @property
     def n_hi(self) -> int:
@@ -462,6 +471,48 @@ def adabelief(x, g, mu, v, delta, t: int, prob: Problem):
     return x, mu, v, delta
 
 
+def sgd(x, g, prob: Problem):
+    """Gradient descent with step lr along g = dL/d(conj x)."""
+    return x - prob.lr * g
+
+
+def nadam(x, g, m, v, t: int, prob: Problem):
+    """Adam with a Nesterov look-ahead of the first moment (Dozat, 2016; constant
+    momentum gamma1): m and v are the usual moments (v of the squared modulus), the
+    step uses gamma1 m_t / (1 - gamma1^(t+1)) + (1 - gamma1) g / (1 - gamma1^t)."""
+    g1, g2, eps = prob.gamma1, prob.gamma2, prob.eta_opt
+    m = g1 * m + (1.0 - g1) * g
+    v = g2 * v + (1.0 - g2) * np.abs(g) ** 2
+    m_hat = g1 * m / (1.0 - g1 ** (t + 1)) + (1.0 - g1) * g / (1.0 - g1 ** t)
+    v_hat = v / (1.0 - g2 ** t)
+    return x - prob.lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def adabelief_plain(x, g, m, s, t: int, prob: Problem):
+    """AdaBelief (Zhuang et al., 2020): the second moment tracks (g - m)^2 (squared
+    modulus here) plus eps; step lr * m_hat / (sqrt(s_hat) + eps)."""
+    g1, g2, eps = prob.gamma1, prob.gamma2, prob.eta_opt
+    m = g1 * m + (1.0 - g1) * g
+    s = g2 * s + (1.0 - g2) * np.abs(g - m) ** 2 + eps
+    m_hat = m / (1.0 - g1 ** t)
+    s_hat = s / (1.0 - g2 ** t)
+    return x - prob.lr * m_hat / (np.sqrt(s_hat) + eps), m, s
+
+
+def optimizer_step(x, g, mu, v, delta, t: int, prob: Problem):
+    """The update rule selected by prob.optimizer; returns (x, mu, v, delta).  delta is
+    used by Eq. (19) only, mu and v by the moment methods."""
+    if prob.optimizer == OPT_SGD:
+        return sgd(x, g, prob), mu, v, delta
+    if prob.optimizer == OPT_NADAM:
+        x, mu, v = nadam(x, g, mu, v, t, prob)
+        return x, mu, v, delta
+    if prob.optimizer == OPT_ADABELIEF:
+        x, mu, v = adabelief_plain(x, g, mu, v, t, prob)
+        return x, mu, v, delta
+    return adabelief(x, g, mu, v, delta, t, prob)
+
+
 def gauss3_weights() -> np.ndarray:
     """Normalised 3x3 Gaussian kernel of standard deviation 1 pixel."""
     d = np.arange(-1, 2)
@@ -514,11 +565,11 @@ def step(state: State, meas: np.ndarray, prob: Problem):
     loss4, g_psi, g_P = loss_and_grad(state.psi, state.P, meas, prob)
     s = state.copy()
     s.t = state.t + 1
-    s.psi, s.mu_psi, s.v_psi, s.delta_psi = adabelief(
+    s.psi, s.mu_psi, s.v_psi, s.delta_psi = optimizer_step(
         state.psi, g_psi, state.mu_psi, state.v_psi, state.delta_psi, s.t, prob)
     if prob.flags & LEARN_PUPIL:
         P = gauss3(state.P) if prob.flags & PUPIL_FILTER else state.P
-        s.P, s.mu_P, s.v_P, s.delta_P = adabelief(
+        s.P, s.mu_P, s.v_P, s.delta_P = optimizer_step(
             P, g_P, state.mu_P, state.v_P, state.delta_P, s.t, prob)
         if prob.flags & PUPIL_SUPPORT:
             s.P = s.P * pupil_support(prob)
