@@ -92,12 +92,7 @@ def autograd_bench(args, dev):
     import paper_2209_14671_amd as E
     case = synth.config_case(4)
     o = case.optics
-    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=E.F32), device=dev)
-    psi_true = sim.spectrum_from_object(torch.from_numpy(case.obj).to(torch.complex64).to(dev))
-    clean = sim.forward(psi_true, torch.from_numpy(case.pupil).to(torch.complex64).to(dev), intens=True)["intens"]
-    meas = torch.from_numpy(synth.degrade(clean.cpu().numpy().astype(np.float64), case.degradation,
-                                          case.noise_seed)).to(torch.float32).to(dev)
-    sim.close()
+    meas = simulated_stack(case, dev)
     plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=E.F32, flags=E.PUPIL_SUPPORT), device=dev)
     st = plan.init_state(meas)
     res = {}
@@ -125,6 +120,59 @@ def autograd_bench(args, dev):
                                         "n_hi": plan.n_hi},
         "ms_recompute": round(res["recompute"], 4), "ms_stored": round(res["stored"], 4),
         "stored_fields_bytes": K * B * 8}), flush=True)
+
+
+def simulated_stack(case, dev):
+    """The measured stack of a synthetic case, simulated with the library's forward model
+    at the true (jittered) LED positions, then degraded on the host."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    o = case.optics
+    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=E.F32), device=dev)
+    psi_true = sim.spectrum_from_object(torch.from_numpy(case.obj).to(torch.complex64).to(dev))
+    clean = sim.forward(psi_true, torch.from_numpy(case.pupil).to(torch.complex64).to(dev), intens=True)["intens"]
+    meas = synth.degrade(clean.cpu().numpy().astype(np.float64), case.degradation, case.noise_seed)
+    sim.close()
+    return torch.from_numpy(meas).to(torch.float32).to(dev)
+
+
+def optimizer_bench(args, dev):
+    """Sec. 6.2 / Fig. 13 on synthetic data: the loss after 0, 10, 20, 50 and 100 iterations
+    of Eq. 19 and of NAdam, AdaBelief and SGD on the same stack, with the time per
+    iteration.  Steps: lr 1e-2 for the moment methods (the same parameters); SGD, whose
+    step has the units of the gradient, at three sizes.  A diverged loss is null."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    case = synth.config_case(2)
+    meas = simulated_stack(case, dev)
+    flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+    rows = {}
+    for name, opt, lr in (("eq19", E.OPT_ELFPIE, 1e-2), ("nadam", E.OPT_NADAM, 1e-2),
+                          ("adabelief", E.OPT_ADABELIEF, 1e-2), ("sgd_1e-4", E.OPT_SGD, 1e-4),
+                          ("sgd_1e-3", E.OPT_SGD, 1e-3), ("sgd_1e-2", E.OPT_SGD, 1e-2)):
+        plan = E.Plan(E.problem_from_optics(case.optics, case.led_k, precision=E.F32, flags=flags, optimizer=opt,
+                                            lr=lr), device=dev)
+        st = plan.init_state(meas)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        h = plan.run(st, meas, 100)
+        ev1.record()
+        torch.cuda.synchronize()
+        L = h[:, 3].cpu().numpy()
+        pick = {str(i): L[i] for i in (0, 10, 20, 50)} | {"100": L[-1]}
+        rows[name] = {"lr": lr, "us_per_iter": round(ev0.elapsed_time(ev1) * 10.0, 2),
+                      "loss": {k: (float(v) if np.isfinite(v) else None) for k, v in pick.items()}}
+        log(f"{name}: loss {L[0]:.4e} -> {L[-1]:.4e}")
+        plan.close()
+    print(json.dumps({"metric": "loss after n iterations per update rule (Sec. 6.2 comparison)", "data": "synthetic",
+                      "dtype": "f32", "config": {"workload": "single FOV, FP32: 512x512 high-res, 15x15 LEDs (K=225), "
+                                                             "128x128 low-res, degraded stack"},
+                      "optimizers": rows}), flush=True)
 
 
 def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
@@ -161,9 +209,11 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed after the run (0: skip); the same copy "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
-    ap.add_argument("--workload", choices=["iteration", "autograd"], default="iteration",
+    ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers"], default="iteration",
                     help="iteration: the throughput line (default); autograd: forward + backward of the "
-                         "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields")
+                         "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields; "
+                         "optimizers: loss curves of Eq. 19 and the Sec. 6.2 alternatives on the "
+                         "512^2 / K=225 / 128^2 stack")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -179,6 +229,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "autograd":
         autograd_bench(args, dev)
+        return
+    if args.workload == "optimizers":
+        optimizer_bench(args, dev)
         return
     case = synth.config_case(2)
     o = case.optics

@@ -67,6 +67,14 @@ typedef enum {
  * for the powers. */
 enum { ELFPIE_FID_AMPLITUDE = 0, ELFPIE_FID_INTENSITY = 1, ELFPIE_FID_GAMMA = 2, ELFPIE_FID_LOG = 3 };
 enum { ELFPIE_NORM_ANISO = 0, ELFPIE_NORM_ISO = 1 };          /* Eq. 12        */
+/* The update rule for Psi and P: Eq. 19 (delta^0 = lr^2), or the three rules the
+ * paper compares it with (Sec. 6.2, Fig. 13), each with step size lr, decay rates
+ * gamma1 / gamma2 and eps = eta_opt: plain gradient descent x -= lr g; NAdam
+ * (Dozat 2016, constant momentum: x -= lr m^ / (sqrt(v^) + eps) with
+ * m^ = gamma1 m_t / (1 - gamma1^(t+1)) + (1 - gamma1) g / (1 - gamma1^t)); AdaBelief
+ * (Zhuang et al. 2020: second moment of (g - m) plus eps).  g = dL/d(conj x);
+ * squared magnitudes are squared moduli. */
+enum { ELFPIE_OPT_ELFPIE = 0, ELFPIE_OPT_SGD = 1, ELFPIE_OPT_NADAM = 2, ELFPIE_OPT_ADABELIEF = 3 };
 enum { ELFPIE_F64 = 0, ELFPIE_F32 = 1 };                      /* arithmetic    */
 enum {
   ELFPIE_LEARN_PUPIL = 1u,    /* update P with Eq. 19 after each Psi update          */
@@ -94,6 +102,7 @@ typedef struct {
   int32_t precision;       /* ELFPIE_F32 or ELFPIE_F64                                      */
   uint32_t flags;          /* ELFPIE_LEARN_PUPIL | ELFPIE_PUPIL_SUPPORT | ELFPIE_PUPIL_FILTER */
   double fid_gamma;        /* exponent of ELFPIE_FID_GAMMA, in (0, 4]; ignored otherwise    */
+  int32_t optimizer;       /* ELFPIE_OPT_* (default Eq. 19)                                 */
 } elfpie_problem;
 
 /* Optimiser state (Eq. 19), all DEVICE pointers owned by the caller.
@@ -140,6 +149,18 @@ elfpie_status elfpie_plan_destroy(elfpie_plan *plan);
  * pixel count S, out[2] = K, out[3] = n_lo, out[4] = index of the LED nearest
  * the optical axis. `out` is HOST, 5 int32. */
 elfpie_status elfpie_plan_info(const elfpie_plan *plan, int32_t *out);
+
+/* Automatic penalty weight, Eq. 16 (intensity) / Eq. 17 (amplitude):
+ * alpha = beta = (1/5) sqrt(pi/2) (1/K) sum_k sum |L (x) g(I_k)| / (n_lo^2), with the
+ * mask L = [-1 2 -1; -2 4 -2; -1 2 -1] applied where it fits in the image and g the
+ * plan's scaling (the Sec. 6.3 ones included).  meas: DEVICE, K x n_lo x n_lo real.
+ * Per-LED sums run on the device in FP64; *alpha_out (HOST) receives the weight.
+ * Synchronises `stream`.  The plan's own alpha and beta are not changed. */
+elfpie_status elfpie_auto_penalty(elfpie_plan *plan, const void *meas, double *alpha_out, void *stream);
+
+/* Sets the plan's penalty weights (Eq. 8), e.g. to elfpie_auto_penalty's value.
+ * Host-only; later calls use the new weights.  alpha, beta finite and >= 0. */
+elfpie_status elfpie_plan_set_penalty(elfpie_plan *plan, double alpha, double beta);
 
 /* Forward model, Eq. (1) with M = 1: for every LED, o_k = F_B P M_k Psi.
  * psi: n_hi^2 complex; P: n_lo^2 complex.  Optional outputs (NULL to skip):

@@ -13,6 +13,7 @@ OK, E_INVALID, E_RANGE, E_UNSUPPORTED, E_WORKSPACE, E_DEVICE, E_NONFINITE = rang
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_RANGE", 3: "E_UNSUPPORTED", 4: "E_WORKSPACE",
                 5: "E_DEVICE", 6: "E_NONFINITE"}
 FID_AMPLITUDE, FID_INTENSITY, FID_GAMMA, FID_LOG = 0, 1, 2, 3
+OPT_ELFPIE, OPT_SGD, OPT_NADAM, OPT_ADABELIEF = 0, 1, 2, 3
 NORM_ANISO, NORM_ISO = 0, 1
 F64, F32 = 0, 1
 LEARN_PUPIL, PUPIL_SUPPORT, PUPIL_FILTER = 1, 2, 4
@@ -27,7 +28,7 @@ class ProblemC(ctypes.Structure):
         ("gamma1", c_double), ("gamma2", c_double), ("eta_opt", c_double),
         ("eta_h", c_double), ("l1_eps", c_double),
         ("fidelity", c_int32), ("norm", c_int32), ("precision", c_int32), ("flags", c_uint32),
-        ("fid_gamma", c_double),
+        ("fid_gamma", c_double), ("optimizer", c_int32),
     ]
 
 
@@ -42,6 +43,8 @@ FUNCTIONS = {
     "elfpie_plan_create": (c_int32, [ctypes.POINTER(ProblemC), c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
     "elfpie_plan_destroy": (c_int32, [c_void_p]),
     "elfpie_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
+    "elfpie_auto_penalty": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]),
+    "elfpie_plan_set_penalty": (c_int32, [c_void_p, c_double, c_double]),
     "elfpie_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "elfpie_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "elfpie_grad_fields": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

@@ -106,6 +106,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   if (p->norm != ELFPIE_NORM_ANISO && p->norm != ELFPIE_NORM_ISO)
     return fail(ELFPIE_E_INVALID, "norm must be ELFPIE_NORM_ANISO or ELFPIE_NORM_ISO");
   if (p->flags & ~7u) return fail(ELFPIE_E_INVALID, "unknown flag bits");
+  if (p->optimizer < ELFPIE_OPT_ELFPIE || p->optimizer > ELFPIE_OPT_ADABELIEF)
+    return fail(ELFPIE_E_INVALID, "optimizer must be one of ELFPIE_OPT_*");
 
   tb->n_lo = p->n_lo;
   tb->n_hi = (int)nh;
@@ -462,6 +464,8 @@ struct Ops {
     a.g1 = pl->prob.gamma1;
     a.g2 = pl->prob.gamma2;
     a.eta = pl->prob.eta_opt;
+    a.lr = pl->prob.lr;
+    a.opt = pl->prob.optimizer;
     a.step = st ? 1 : 0;
     PupilArgs pa = pupil_args(pl, P);
     pa.filter = prefilter ? 1 : 0;
@@ -504,6 +508,8 @@ struct Ops {
     a.g1 = pl->prob.gamma1;
     a.g2 = pl->prob.gamma2;
     a.eta = pl->prob.eta_opt;
+    a.lr = pl->prob.lr;
+    a.opt = pl->prob.optimizer;
     a.filter = (pl->prob.flags & ELFPIE_PUPIL_FILTER) ? 1 : 0;
     a.support = (pl->prob.flags & ELFPIE_PUPIL_SUPPORT) ? 1 : 0;
     return a;
@@ -678,6 +684,22 @@ struct Ops {
     return ELFPIE_OK;
   }
 
+  static elfpie_status auto_penalty(elfpie_plan* pl, const void* meas, double* alpha, hipStream_t s) {
+    const Tables& tb = pl->tb;
+    double* part = pl->at<double>(tb.o_fid);
+    k_auto_penalty<T><<<tb.K, 256, 0, s>>>(static_cast<const T*>(meas), tb.n_lo, pl->prob.fidelity,
+                                           pl->prob.fid_gamma, part);
+    LAUNCH_CHECK(pl, "k_auto_penalty");
+    std::vector<double> h(tb.K);
+    HIP_TRY(pl, hipMemcpyAsync(h.data(), part, tb.K * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(pl, hipStreamSynchronize(s));
+    double acc = 0.0;
+    const double wh = (double)tb.n_lo * tb.n_lo;
+    for (int k = 0; k < tb.K; ++k) acc += h[k] / wh;
+    *alpha = 0.2 * std::sqrt(M_PI / 2.0) * acc / tb.K;
+    return ELFPIE_OK;
+  }
+
   static elfpie_status stage_timing(elfpie_plan* pl, const elfpie_state* st, const void* meas, int n_rep,
                                     float* ms, hipStream_t s) {
     const Tables& tb = pl->tb;
@@ -762,6 +784,7 @@ elfpie_status elfpie_problem_defaults(elfpie_problem* p) {
   p->l1_eps = 0.0;
   p->fidelity = ELFPIE_FID_INTENSITY;
   p->fid_gamma = 0.5;
+  p->optimizer = ELFPIE_OPT_ELFPIE;
   p->norm = ELFPIE_NORM_ANISO;
   p->precision = ELFPIE_F32;
   p->flags = ELFPIE_PUPIL_SUPPORT;
@@ -1019,6 +1042,24 @@ elfpie_status elfpie_init_state(elfpie_plan* pl, const void* meas, const elfpie_
   CHECK(check_ptr(pl, meas, "meas", false));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(pl, [&](auto ops) { return decltype(ops)::init_state(pl, meas, st, s); });
+}
+
+elfpie_status elfpie_auto_penalty(elfpie_plan* pl, const void* meas, double* alpha_out, void* stream) {
+  if (!pl) return ELFPIE_E_INVALID;
+  CHECK(check_ptr(pl, meas, "meas", false));
+  if (!alpha_out) return set_err(pl, ELFPIE_E_INVALID, "alpha_out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dispatch(pl, [&](auto ops) { return decltype(ops)::auto_penalty(pl, meas, alpha_out, s); });
+}
+
+elfpie_status elfpie_plan_set_penalty(elfpie_plan* pl, double alpha, double beta) {
+  if (!pl) return ELFPIE_E_INVALID;
+  if (!(alpha >= 0) || !(beta >= 0) || !std::isfinite(alpha) || !std::isfinite(beta))
+    return set_err(pl, ELFPIE_E_INVALID, "alpha and beta must be finite and >= 0");
+  pl->prob.alpha = alpha;
+  pl->prob.beta = beta;
+  pl->gexec = nullptr;  // captured graphs hold the old weights in their launch arguments
+  return ELFPIE_OK;
 }
 
 elfpie_status elfpie_stage_timing(elfpie_plan* pl, const elfpie_state* st, const void* meas, int32_t n_rep,

@@ -409,7 +409,7 @@ __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<
   static_assert(EPT * NT == RPB * N, "whole elements per thread");
   __shared__ cx<T> buf[RPB * PITCH];
   __shared__ cx<T> twl[N];
-  __shared__ double tail_sbc[2];
+  __shared__ double tail_sbc[3];
   __shared__ double tail_red[3][4];
   const int tid = threadIdx.x;
   if (blockIdx.x >= N / RPB) {
@@ -761,6 +761,46 @@ __device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, dou
   v = vn;
 }
 
+// 1 - g1^t, 1 - g2^t and 1 - g1^(t+1) for step t.
+__device__ __forceinline__ void bias_corrections(double g1, double g2, double t, double* bc) {
+  bc[0] = 1.0 - pow(g1, t);
+  bc[1] = 1.0 - pow(g2, t);
+  bc[2] = 1.0 - pow(g1, t + 1.0);
+}
+
+// The update rule of the plan (ELFPIE_OPT_*) for one element: Eq. 19, or for the
+// comparison of Sec. 6.2 plain gradient descent, NAdam (constant momentum) or
+// AdaBelief.  v and the normaliser are FP64; delta is used by Eq. 19 only.
+template <class T>
+__device__ __forceinline__ void optimizer_elem(int opt, cx<T>& x, cx<T> g, cx<T>& mu, double& v, T& delta,
+                                               double g1, double g2, double eta, double lr, const double* bc) {
+  if (opt == 0) {
+    adabelief_elem(x, g, mu, v, delta, g1, g2, eta, bc[0], bc[1]);
+    return;
+  }
+  if (opt == 1) {
+    x = x - cx<T>{T(lr * double(g.x)), T(lr * double(g.y))};
+    return;
+  }
+  const T tg1 = T(g1);
+  const cx<T> m = {tg1 * mu.x + (T(1) - tg1) * g.x, tg1 * mu.y + (T(1) - tg1) * g.y};
+  double sx, sy, vn;
+  if (opt == 2) {  // NAdam: moments of g; look-ahead mean
+    vn = g2 * v + (1.0 - g2) * (double(g.x) * double(g.x) + double(g.y) * double(g.y));
+    sx = g1 * double(m.x) / bc[2] + (1.0 - g1) * double(g.x) / bc[0];
+    sy = g1 * double(m.y) / bc[2] + (1.0 - g1) * double(g.y) / bc[0];
+  } else {  // AdaBelief: belief (g - m)^2 plus eps
+    const double dxr = double(g.x) - double(m.x), dxi = double(g.y) - double(m.y);
+    vn = g2 * v + (1.0 - g2) * (dxr * dxr + dxi * dxi) + eta;
+    sx = double(m.x) / bc[0];
+    sy = double(m.y) / bc[0];
+  }
+  const double f = lr / (sqrt(vn / bc[1]) + eta);
+  x = x - cx<T>{T(f * sx), T(f * sy)};
+  mu = m;
+  v = vn;
+}
+
 // ---------------------------------------------------------------------------
 // Pupil: partial sums over LED chunks (Eq. 18) and the Gaussian pre-filter in one
 // launch (blocks with blockIdx.y == nch filter), then the update.
@@ -831,7 +871,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   constexpr int GB = ELFPIE_UPD_GB;
   using cint = const __attribute__((address_space(4))) int;  // read-only: wave-uniform reads go scalar
   __shared__ int4 stab[kMaxLo];  // per support row: first column, last column, row base (rowoff - xlo)
-  __shared__ double sbc[2];
+  __shared__ double sbc[3];
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   if (tile >= a.ntiles) {
@@ -844,8 +884,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   for (int i = tid; i < a.n_lo; i += 256) stab[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   if (a.step && tid == 0) {
     const double t = double(*a.t);
-    sbc[0] = 1.0 - pow(a.g1, t);
-    sbc[1] = 1.0 - pow(a.g2, t);
+    bias_corrections(a.g1, a.g2, t, sbc);
   }
   // state loads go out first; they do not depend on the gather
   cx<T> g = static_cast<const cx<T>*>(a.gH)[u];
@@ -886,7 +925,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
     return;
   }
   __syncthreads();
-  adabelief_elem(x, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
+  optimizer_elem(a.opt, x, g, mu, v, d, a.g1, a.g2, a.eta, a.lr, sbc);
   static_cast<cx<T>*>(a.x)[u] = x;
   static_cast<cx<T>*>(a.mu)[u] = mu;
   a.v[u] = v;
@@ -967,8 +1006,7 @@ __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, 
     const PupilArgs& a = ta.pa;
     if (a.step && tid == 0) {
       const double t = double(*a.t);
-      sbc[0] = 1.0 - pow(a.g1, t);
-      sbc[1] = 1.0 - pow(a.g2, t);
+      bias_corrections(a.g1, a.g2, t, sbc);
     }
     __syncthreads();
     const int p = vb * NT + tid;
@@ -981,7 +1019,7 @@ __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, 
 // An iteration's tail as a launch of its own.
 template <class T>
 __global__ __launch_bounds__(256) void k_tail(TailArgs ta) {
-  __shared__ double sbc[2];
+  __shared__ double sbc[3];
   __shared__ double red[3][4];
   tail_block<T, 256>(ta, blockIdx.x, threadIdx.x, sbc, red);
 }
@@ -1018,12 +1056,49 @@ __device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const doub
     static_cast<cx<T>*>(a.g_out)[p] = g;
     return;
   }
-  adabelief_elem(xv, g, mu, v, d, a.g1, a.g2, a.eta, sbc[0], sbc[1]);
+  optimizer_elem(a.opt, xv, g, mu, v, d, a.g1, a.g2, a.eta, a.lr, sbc);
   if (a.support && !in) xv = czero<T>();
   static_cast<cx<T>*>(a.P_out)[p] = xv;
   static_cast<cx<T>*>(a.mu)[p] = mu;
   a.v[p] = v;
   static_cast<T*>(a.delta)[p] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Automatic penalty weight, Eq. (16) / (17): per LED, the FP64 sum over the
+// (n-2)^2 positions where the 3x3 mask fits of |mask (x) g(I_k)|, with the mask
+// rows [-1 2 -1], [-2 4 -2], [-1 2 -1] and g the plan's scaling (the identity for
+// Eq. 16, sqrt for Eq. 17).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double scaled_reading(double x, int fid, double gam) {
+  if (fid == 1) return x;
+  const double xp = x > 0.0 ? x : 0.0;
+  if (fid == 0) return sqrt(xp);
+  if (fid == 2) return pow(xp, gam);
+  return log1p(xp);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_auto_penalty(const T* meas, int n, int fid, double gam, double* part) {
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  const T* I = meas + (size_t)k * n * n;
+  const int m = n - 2;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < m * m; p += 256) {
+    const int y = p / m, x = p % m;
+    double c = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double w = (j == 1 ? 2.0 : -1.0) * (i == 1 ? 2.0 : 1.0);
+        c += w * scaled_reading(double(I[(y + i) * n + x + j]), fid, gam);
+      }
+    acc += fabs(c);
+  }
+  const double tot = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) part[k] = tot;
 }
 
 // ---------------------------------------------------------------------------

@@ -68,7 +68,9 @@ struct UpdArgs {
   const long long* t;   // step counter, already advanced for this iteration
   int n_hi, n_lo, S, ntiles_x, ntiles;
   double g1, g2, eta;
-  int step;             // 0: write g_out; 1: Eq. 19 update
+  double lr;            // step size of the moment methods and SGD
+  int opt;              // ELFPIE_OPT_*
+  int step;             // 0: write g_out; 1: update with the plan's rule
   int pupil_blocks;     // trailing blocks that run the pupil partial sums / pre-filter
 };
 
@@ -102,6 +104,8 @@ struct PupilArgs {
   int n_lo, S, K, chunk, nch;
   double w_c, w_e, w_k;  // Gaussian weights: centre, edge, corner
   double g1, g2, eta;
+  double lr;
+  int opt;
   int step;
   int filter;
   int support;

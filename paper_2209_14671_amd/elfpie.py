@@ -17,7 +17,7 @@ import torch
 
 from . import _lib
 from ._lib import (F32, F64, FID_AMPLITUDE, FID_GAMMA, FID_INTENSITY, FID_LOG, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
-                   PUPIL_FILTER, PUPIL_SUPPORT, ElfpieError)
+                   OPT_ADABELIEF, OPT_ELFPIE, OPT_NADAM, OPT_SGD, PUPIL_FILTER, PUPIL_SUPPORT, ElfpieError)
 
 
 @dataclasses.dataclass
@@ -42,6 +42,7 @@ class Problem:
     precision: int = F32
     flags: int = PUPIL_SUPPORT
     fid_gamma: float = 0.5          # exponent of FID_GAMMA
+    optimizer: int = OPT_ELFPIE     # update rule (Eq. 19 or a Sec. 6.2 alternative)
 
     def to_c(self):
         k = np.ascontiguousarray(np.asarray(self.led_k, dtype=np.float64).reshape(-1, 2))
@@ -54,6 +55,7 @@ class Problem:
         p.eta_h, p.l1_eps = float(self.eta_h), float(self.l1_eps)
         p.fidelity, p.norm, p.precision, p.flags = int(self.fidelity), int(self.norm), int(self.precision), int(self.flags)
         p.fid_gamma = float(self.fid_gamma)
+        p.optimizer = int(self.optimizer)
         return p, k  # keep k alive while p is used
 
 
@@ -279,6 +281,17 @@ class Plan:
         p = torch.empty_like(obj)
         self._check(self.lib.elfpie_spectrum_from_object(self.handle, _ptr(obj), _ptr(p), _stream()))
         return p
+
+    def auto_penalty(self, meas) -> float:
+        """alpha = beta of Eq. 16 / 17 from the measured stack (computed on the device)."""
+        self._need(meas, self.stack_shape, self.rdtype, "meas")
+        out = ctypes.c_double(0.0)
+        self._check(self.lib.elfpie_auto_penalty(self.handle, _ptr(meas), ctypes.byref(out), _stream()))
+        return float(out.value)
+
+    def set_penalty(self, alpha: float, beta: float):
+        """New Eq. 8 weights for later calls."""
+        self._check(self.lib.elfpie_plan_set_penalty(self.handle, float(alpha), float(beta)))
 
     def stage_timing(self, st: State, meas, n_rep: int = 20):
         """Mean ms per launch of each stage in isolation (see elfpie_stage_timing)."""

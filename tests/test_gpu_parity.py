@@ -121,6 +121,75 @@ def test_step_matches_oracle(fidelity, norm, f32, gamma):
     assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < tol["loss"])
 
 
+OPT_CASES = [(o, f32) for o in (orc.OPT_SGD, orc.OPT_NADAM, orc.OPT_ADABELIEF) for f32 in (False, True)]
+
+
+@pytest.mark.parametrize("opt,f32", OPT_CASES)
+def test_step_with_other_optimisers_matches_oracle(opt, f32):
+    """The Sec. 6.2 alternatives to Eq. 19, with pupil learning and non-trivial moments."""
+    pair = make_pair(32, 4, 5, f32=f32, optimizer=opt)
+    plan = make_plan(pair, f32)
+    st = gpu_state(plan, pair, f32)
+    l4 = plan.step(st, dev(pair.meas, f32))
+    torch.cuda.synchronize()
+    ref, rl4 = orc.step(pair.state, pair.meas, pair.oprob)
+    res = {k: rel_l2(host(getattr(st, k)), getattr(ref, k)) for k in ("psi", "P", "mu_psi", "mu_P")}
+    res["v_psi"] = rel_l2(host(st.v_psi), ref.v_psi) if opt != orc.OPT_SGD else 0.0
+    print(f"opt={opt} f32={f32}: " + " ".join(f"{k} {v:.2e}" for k, v in res.items()))
+    tol = TOL[f32]
+    assert int(st.t.item()) == ref.t
+    assert res["psi"] < tol["state"] and res["P"] < tol["state"]
+    if opt != orc.OPT_SGD:
+        assert res["mu_psi"] < tol["grad"] and res["v_psi"] < tol["grad"]
+    assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < tol["loss"])
+
+
+def test_run_with_nadam_equals_repeated_steps():
+    """Bias corrections of NAdam use t and t + 1 across graph replays."""
+    pair = make_pair(32, 4, 5, f32=False, optimizer=orc.OPT_NADAM)
+    plan = make_plan(pair, False)
+    meas = dev(pair.meas, False)
+    a = gpu_state(plan, pair, False)
+    b = a.clone()
+    plan.run(a, meas, 9)
+    for _ in range(9):
+        plan.step(b, meas)
+    torch.cuda.synchronize()
+    for k in ("psi", "P", "mu_psi", "v_psi", "mu_P", "v_P", "t"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    ref, _ = orc.run(pair.state, pair.meas, pair.oprob, 9)
+    assert rel_l2(host(a.psi), ref.psi) < 1e-11
+
+
+@pytest.mark.parametrize("fidelity,gamma", [(orc.FID_INTENSITY, 0.5), (orc.FID_AMPLITUDE, 0.5),
+                                            (orc.FID_GAMMA, 0.375), (orc.FID_LOG, 0.5)])
+@pytest.mark.parametrize("f32", [False, True])
+def test_auto_penalty_matches_oracle(fidelity, gamma, f32):
+    pair = make_pair(64, 4, 7, f32=f32, fidelity=fidelity, fid_gamma=gamma, warm_steps=0)
+    plan = make_plan(pair, f32)
+    a = plan.auto_penalty(dev(pair.meas, f32))
+    ref = orc.auto_penalty(pair.meas, fidelity, gamma)
+    print(f"auto alpha fid={fidelity} f32={f32}: {a:.6e} vs {ref:.6e}")
+    assert abs(a - ref) <= 1e-12 * ref
+
+
+def test_set_penalty_changes_the_loss_weights():
+    """New weights reach a plan whose graphs were captured with the old ones."""
+    pair = make_pair(32, 4, 5, f32=False, warm_steps=0)
+    plan = make_plan(pair, False)
+    meas = dev(pair.meas, False)
+    st = gpu_state(plan, pair, False)
+    plan.run(st, meas, 1)  # captures graphs for these pointers, old weights
+    plan.set_penalty(0.05, 0.02)
+    hist = plan.run(st, meas, 1)
+    torch.cuda.synchronize()
+    mid, _ = orc.run(pair.state, pair.meas, pair.oprob, 1)
+    oprob = orc.Problem(**{**pair.oprob.__dict__, "alpha": 0.05, "beta": 0.02})
+    ref, rh = orc.run(mid, pair.meas, oprob, 1)
+    assert np.max(np.abs(host(hist) - rh) / np.abs(rh)) < 1e-12
+    assert rel_l2(host(st.psi), ref.psi) < 1e-12
+
+
 def test_exact_sign_mode_gradient_close():
     """l1_eps = 0 (literal L1): FP32 sign decisions of near-zero differences may differ."""
     pair = make_pair(32, 4, 5, f32=True, l1_eps=0.0)
