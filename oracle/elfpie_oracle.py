@@ -9,7 +9,8 @@ Everything is NumPy complex128 / float64, written to be read against the paper
 (Zhang, Berendschot, Zhou, "ELFPIE: an error-laxity Fourier ptychographic
 iterative engine", arXiv 2209.14671):
 
-* forward model, Sec. 3.1 Eq. (1) with one LED per exposure (M = 1, Sec. 4.1);
+* forward model, Sec. 3.1 Eq. (1), one LED per exposure (M = 1, Sec. 4.1) or M
+  LEDs lit together (multiplexed illumination, the general form of Eq. 1);
 * data fidelity on image gradients, Sec. 3.2 Eq. (4) amplitude / Eq. (5) intensity,
   with the L1 normaliser of Eq. (12) (anisotropic sign or isotropic), and the other
   scalings g of Eq. (3) that Sec. 6.3 tries: x^gamma and ln(x + 1);
@@ -95,14 +96,21 @@ class Problem:
     flags: int = PUPIL_SUPPORT
     fid_gamma: float = 0.5            # the exponent of FID_GAMMA
     optimizer: int = OPT_ELFPIE       # update rule for Psi and P (Sec. 6.2)
+    mux: int = 1                      # M of Eq. (1): LEDs lit together per image
 
     @property
     def n_hi(self) -> int:
         return self.n_lo * self.upsample
 
     @property
-    def K(self) -> int:
+    def n_led(self) -> int:
+        """Number of LEDs (rows of led_k); image n is lit by LEDs n M .. n M + M - 1."""
         return int(self.led_k.shape[0])
+
+    @property
+    def K(self) -> int:
+        """Number of images (N of Eq. 1)."""
+        return self.n_led // self.mux
 
     @property
     def fov_um(self) -> float:
@@ -137,12 +145,12 @@ def round_half_away(x):
 
 
 def led_offsets(prob: Problem) -> np.ndarray:
-    """(K, 2) integer spectral offsets (off_x, off_y) = round(k * FOV)."""
+    """(n_led, 2) integer spectral offsets (off_x, off_y) = round(k * FOV)."""
     return round_half_away(prob.led_k * prob.fov_um)
 
 
 def window_origins(prob: Problem) -> np.ndarray:
-    """(K, 2) top-left corner (row y0, column x0) of each LED's crop window in Psi."""
+    """(n_led, 2) top-left corner (row y0, column x0) of each LED's crop window in Psi."""
     off = led_offsets(prob)
     c = prob.n_hi // 2 - prob.n_lo // 2
     y0 = c + off[:, 1]
@@ -214,22 +222,23 @@ def lowres_field_adjoint(w: np.ndarray, upsample: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# Forward model, Eq. (1) with M = 1
+# Forward model, Eq. (1)
 # ----------------------------------------------------------------------------
 
 def fields(psi: np.ndarray, P: np.ndarray, prob: Problem) -> np.ndarray:
-    """(K, n_lo, n_lo) complex low-resolution fields o_k = F_B P M_k Psi."""
+    """(n_led, n_lo, n_lo) complex low-resolution fields o_k = F_B P M_k Psi, one per LED."""
     org = window_origins(prob)
     Pe = effective_pupil(P, prob)
-    out = np.empty((prob.K, prob.n_lo, prob.n_lo), dtype=np.complex128)
-    for k in range(prob.K):
+    out = np.empty((prob.n_led, prob.n_lo, prob.n_lo), dtype=np.complex128)
+    for k in range(prob.n_led):
         out[k] = lowres_field(Pe * crop(psi, org[k], prob.n_lo), prob.upsample)
     return out
 
 
 def intensities(psi: np.ndarray, P: np.ndarray, prob: Problem) -> np.ndarray:
-    """Ideal measured stack, Eq. (1): |o_k|^2."""
-    return np.abs(fields(psi, P, prob)) ** 2
+    """Ideal measured stack, Eq. (1): image n is sum_m |o_(n, m)|^2 over its M LEDs."""
+    p = np.abs(fields(psi, P, prob)) ** 2
+    return p.reshape(prob.K, prob.mux, prob.n_lo, prob.n_lo).sum(axis=1)
 
 
 # ----------------------------------------------------------------------------
@@ -383,11 +392,12 @@ def fidelity_residual(o: np.ndarray, meas: np.ndarray, fidelity: int, gamma: flo
 def fidelity_loss_and_grad(psi, P, meas, prob: Problem, want_grad: bool = True):
     """L_fid and its Wirtinger gradients wrt conj(Psi) (Eq. 9) and conj(P) (Eq. 18).
 
-    For every LED: o = F_B P M Psi; e = residual; L += rho(grad e);
-    dL/de = grad^T omega; dL/d(conj o) = dL/de * g'(|o|^2) * o, which is
-    dL/de * o / (2|o|) for the amplitude and dL/de * o for the intensity;
-    back-projection Y = F_B^H dL/d(conj o); then
-    g_Psi += M^T (conj(P) Y) and g_P += conj(M Psi) Y, LEDs in ascending order.
+    For every image n: o_m = F_B P M_(n, m) Psi for its M LEDs, S = sum_m |o_m|^2
+    (Eq. 1); e = g(S) - g(I_n); L += rho(grad e); dL/de = grad^T omega;
+    dL/d(conj o_m) = dL/de * g'(S) * o_m, which is dL/de * o / (2|o|) for the
+    amplitude and dL/de * o for the intensity when M = 1; back-projection
+    Y_m = F_B^H dL/d(conj o_m); then g_Psi += M^T (conj(P) Y_m) and
+    g_P += conj(M Psi) Y_m, LEDs in ascending order.
     """
     org = window_origins(prob)
     Pe = effective_pupil(P, prob)
@@ -395,25 +405,37 @@ def fidelity_loss_and_grad(psi, P, meas, prob: Problem, want_grad: bool = True):
     L = 0.0
     g_psi = np.zeros_like(psi, dtype=np.complex128) if want_grad else None
     g_P = np.zeros((n, n), dtype=np.complex128) if want_grad else None
-    for k in range(prob.K):
-        c = crop(psi, org[k], n)
-        o = lowres_field(Pe * c, prob.upsample)
-        e = fidelity_residual(o, meas[k], prob.fidelity, prob.fid_gamma)
+    for img in range(prob.K):
+        leds = range(img * prob.mux, (img + 1) * prob.mux)
+        cs = [crop(psi, org[k], n) for k in leds]
+        os_ = [lowres_field(Pe * c, prob.upsample) for c in cs]
+        if prob.mux == 1:
+            e = fidelity_residual(os_[0], meas[img], prob.fidelity, prob.fid_gamma)
+        else:
+            S = sum(np.abs(o) ** 2 for o in os_)
+            if prob.fidelity == FID_INTENSITY:
+                e = S - meas[img]
+            else:
+                e = scaling(S, prob.fidelity, prob.fid_gamma) - scaling(np.clip(meas[img], 0.0, None),
+                                                                        prob.fidelity, prob.fid_gamma)
         val, (wx, wy) = l1_value_and_omega([dx(e), dy(e)], prob.norm, prob.l1_eps)
         L += val
         if not want_grad:
             continue
         q = dx_T(wx) + dy_T(wy)
-        if prob.fidelity == FID_AMPLITUDE:
-            a = np.abs(o)
-            dob = np.divide(q * o, 2.0 * a, out=np.zeros_like(o), where=a > 0)
-        elif prob.fidelity == FID_INTENSITY:
-            dob = q * o
-        else:
-            dob = q * scaling_slope(np.abs(o) ** 2, prob.fidelity, prob.fid_gamma) * o
-        Y = lowres_field_adjoint(dob, prob.upsample)
-        g_psi[org[k][0]:org[k][0] + n, org[k][1]:org[k][1] + n] += np.conj(Pe) * Y
-        g_P += np.conj(c) * Y
+        for k, c, o in zip(leds, cs, os_):
+            if prob.mux > 1:
+                dob = q * scaling_slope(S, prob.fidelity, prob.fid_gamma) * o
+            elif prob.fidelity == FID_AMPLITUDE:
+                a = np.abs(o)
+                dob = np.divide(q * o, 2.0 * a, out=np.zeros_like(o), where=a > 0)
+            elif prob.fidelity == FID_INTENSITY:
+                dob = q * o
+            else:
+                dob = q * scaling_slope(np.abs(o) ** 2, prob.fidelity, prob.fid_gamma) * o
+            Y = lowres_field_adjoint(dob, prob.upsample)
+            g_psi[org[k][0]:org[k][0] + n, org[k][1]:org[k][1] + n] += np.conj(Pe) * Y
+            g_P += np.conj(c) * Y
     if want_grad and prob.flags & PUPIL_SUPPORT:
         g_P *= pupil_support(prob)
     return L, g_psi, g_P
@@ -554,7 +576,8 @@ def init_state(meas: np.ndarray, prob: Problem) -> State:
     kc = int(np.argmin(np.sum(prob.led_k ** 2, axis=1)))
     n = prob.n_lo
     S = pupil_support(prob) if prob.flags & PUPIL_SUPPORT else np.ones((n, n), dtype=bool)
-    spec = (prob.upsample / n) * np.fft.fftshift(np.fft.fft2(np.sqrt(np.clip(meas[kc], 0, None))))
+    img = kc // prob.mux  # the image that the on-axis-most LED lights
+    spec = (prob.upsample / n) * np.fft.fftshift(np.fft.fft2(np.sqrt(np.clip(meas[img], 0, None))))
     psi0 = np.zeros((prob.n_hi, prob.n_hi), dtype=np.complex128)
     psi0[org[kc][0]:org[kc][0] + n, org[kc][1]:org[kc][1] + n] = spec * S
     return new_state(psi0, S.astype(np.complex128), prob)
