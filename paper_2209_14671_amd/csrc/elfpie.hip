@@ -286,6 +286,19 @@ template <class T>
 struct Ops {
   using C = cx<T>;
 
+  // The Sec. 6.3 scalings and the stored-fields mode run in their own
+  // instantiations, so that the common kernel carries no code for them.
+  template <int N>
+  static void launch_led(const LedArgs& a, int K, hipStream_t s) {
+    const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
+    const bool stored = (a.mode & LED_STORED) != 0;
+    constexpr int NT = LedShape<N>::NT;
+    if (stored && scaled) k_led<T, N, true, true><<<K, NT, 0, s>>>(a);
+    else if (stored) k_led<T, N, false, true><<<K, NT, 0, s>>>(a);
+    else if (scaled) k_led<T, N, true, false><<<K, NT, 0, s>>>(a);
+    else k_led<T, N, false, false><<<K, NT, 0, s>>>(a);
+  }
+
   static elfpie_status led(elfpie_plan* pl, int mode, const void* psi, const void* P, const void* meas,
                            void* fields, void* intens, hipStream_t s, int64_t* t_bump = nullptr) {
     const Tables& tb = pl->tb;
@@ -317,11 +330,11 @@ struct Ops {
     a.fid_gamma = pl->prob.fid_gamma;
     a.norm = pl->prob.norm;
     switch (tb.n_lo) {
-      case 32: k_led<T, 32><<<tb.K, LedShape<32>::NT, 0, s>>>(a); break;
-      case 64: k_led<T, 64><<<tb.K, LedShape<64>::NT, 0, s>>>(a); break;
+      case 32: launch_led<32>(a, tb.K, s); break;
+      case 64: launch_led<64>(a, tb.K, s); break;
       case 128:
         if constexpr (sizeof(T) == 4) {
-          k_led<T, 128><<<tb.K, LedShape<128>::NT, 0, s>>>(a);
+          launch_led<128>(a, tb.K, s);
           break;
         }
         [[fallthrough]];

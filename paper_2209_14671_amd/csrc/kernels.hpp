@@ -53,27 +53,33 @@ __device__ __forceinline__ double pow_t(double x, double y) { return pow(x, y); 
 __device__ __forceinline__ float log1p_t(float x) { return log1pf(x); }
 __device__ __forceinline__ double log1p_t(double x) { return log1p(x); }
 
-// Residual g(|o|^2) - g(I) from i2 = |o|^2 and the reading m.
-template <class T>
+// Residual g(|o|^2) - g(I) from i2 = |o|^2 and the reading m.  SCALED adds the
+// Sec. 6.3 scalings (x^gamma, ln(x + 1)); without it only Eq. 4 and Eq. 5 are
+// compiled, which keeps the per-pixel code of the common kernel small.
+template <bool SCALED, class T>
 __device__ __forceinline__ T fid_residual(int fid, T i2, T m, T gam) {
   const T mp = m > T(0) ? m : T(0);
   if (fid == 0) return sqrt(i2) - sqrt(mp);
-  if (fid == 2) return pow_t(i2, gam) - pow_t(mp, gam);
-  if (fid == 3) return log1p_t(i2) - log1p_t(mp);
+  if constexpr (SCALED) {
+    if (fid == 2) return pow_t(i2, gam) - pow_t(mp, gam);
+    if (fid == 3) return log1p_t(i2) - log1p_t(mp);
+  }
   return i2 - m;
 }
 
 // dL/d(conj o) = q g'(|o|^2) o; g'(0) is taken as 0 for the powers.
-template <class T>
+template <bool SCALED, class T>
 __device__ __forceinline__ cx<T> fid_wirtinger(int fid, cx<T> ov, T q, T gam) {
   const T i2 = norm2(ov);
-  if (fid == 1) return scale(ov, q);
   if (fid == 0) {
     const T am = sqrt(i2);
     return am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
   }
-  if (fid == 2) return i2 > T(0) ? scale(ov, q * gam * pow_t(i2, gam - T(1))) : czero<T>();
-  return scale(ov, q / (T(1) + i2));
+  if constexpr (SCALED) {
+    if (fid == 2) return i2 > T(0) ? scale(ov, q * gam * pow_t(i2, gam - T(1))) : czero<T>();
+    if (fid == 3) return scale(ov, q / (T(1) + i2));
+  }
+  return scale(ov, q);
 }
 
 template <class T>
@@ -109,7 +115,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 }
 
 // Every pass of each 2-D transform is spread over the whole block (StockhamPass).
-template <class T, int N>
+// SCALED: compiled with the Sec. 6.3 fidelity scalings (used only for them).
+// STORED: the LED_STORED mode (fields read, not recomputed), in its own instantiation.
+template <class T, int N, bool SCALED = false, bool STORED = false>
 __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   using Sh = LedShape<N>;
   constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
@@ -148,15 +156,15 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
   const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
   const int mode = a.mode;
-  const bool stored = (mode & LED_STORED) != 0;
+  constexpr bool stored = STORED;
   __syncthreads();
 
   // register (i, r) of the last column pass holds pixel y = jj[i] + r R1, x = mm[i]
   int mm[MB2], jj[MB2];
   bool lv[MB2];
-  P2iC::coords(N, tid, mm, jj, lv);
   cx<T> o[MB2][R2];
-  if (stored) {
+  if constexpr (stored) {
+    P2iC::coords(N, tid, mm, jj, lv);
     // o from the fields of a forward call, in the kernel's (-1)^(x+y) frame
     const cx<T>* fk = static_cast<const cx<T>*>(a.fields) + (size_t)k * N * N;
 #pragma unroll
@@ -195,6 +203,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     P1iR::run(img, a.y_min, nband, twl, tid);
     P2iR::run(img, a.y_min, nband, twl, tid);
     P1iC::run(img, 0, N, twl, tid);
+    P2iC::coords(N, tid, mm, jj, lv);
     P2iC::load(img, 0, mm, jj, lv, twl, o);
   }
   __syncthreads();
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
       if (need_e) {
         const T m = mv[i][r];
-        eb[y * PITCH + x] = fid_residual(a.fidelity, i2, m, gam);
+        eb[y * PITCH + x] = fid_residual<SCALED>(a.fidelity, i2, m, gam);
       }
     }
   }
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         }
         lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
       }
-      o[i][r] = fid_wirtinger(a.fidelity, o[i][r], q, gam);
+      o[i][r] = fid_wirtinger<SCALED>(a.fidelity, o[i][r], q, gam);
     }
   }
   __syncthreads();  // every residual read is done; the tile can be overwritten
