@@ -86,7 +86,7 @@ enum {
 typedef struct {
   int32_t n_lo;            /* low-res image side; power of two, 32..128 (F32), 32..64 (F64) */
   int32_t upsample;        /* r = n_hi / n_lo; n_hi must be a power of two, 128..1024       */
-  int32_t K;               /* number of LEDs (images), >= 1                                 */
+  int32_t K;               /* number of LEDs (rows of led_k), >= 1; images = K / mux         */
   double wavelength_um;    /* illumination wavelength, > 0                                  */
   double na;               /* objective numerical aperture, > 0                             */
   double dx_lo_um;         /* sample-plane pixel = camera pixel / magnification, > 0         */
@@ -103,6 +103,9 @@ typedef struct {
   uint32_t flags;          /* ELFPIE_LEARN_PUPIL | ELFPIE_PUPIL_SUPPORT | ELFPIE_PUPIL_FILTER */
   double fid_gamma;        /* exponent of ELFPIE_FID_GAMMA, in (0, 4]; ignored otherwise    */
   int32_t optimizer;       /* ELFPIE_OPT_* (default Eq. 19)                                 */
+  int32_t mux;             /* M of Eq. 1: LEDs lit together per image, divides K (default 1);
+                              image n is lit by LEDs n M .. n M + M - 1 and measures the sum
+                              of their intensities.  Every "meas" below has K / mux images.  */
 } elfpie_problem;
 
 /* Optimiser state (Eq. 19), all DEVICE pointers owned by the caller.
@@ -153,7 +156,8 @@ elfpie_status elfpie_plan_info(const elfpie_plan *plan, int32_t *out);
 /* Automatic penalty weight, Eq. 16 (intensity) / Eq. 17 (amplitude):
  * alpha = beta = (1/5) sqrt(pi/2) (1/K) sum_k sum |L (x) g(I_k)| / (n_lo^2), with the
  * mask L = [-1 2 -1; -2 4 -2; -1 2 -1] applied where it fits in the image and g the
- * plan's scaling (the Sec. 6.3 ones included).  meas: DEVICE, K x n_lo x n_lo real.
+ * plan's scaling (the Sec. 6.3 ones included).  meas: DEVICE, (K / mux) x n_lo x n_lo
+ * real.
  * Per-LED sums run on the device in FP64; *alpha_out (HOST) receives the weight.
  * Synchronises `stream`.  The plan's own alpha and beta are not changed. */
 elfpie_status elfpie_auto_penalty(elfpie_plan *plan, const void *meas, double *alpha_out, void *stream);
@@ -162,10 +166,12 @@ elfpie_status elfpie_auto_penalty(elfpie_plan *plan, const void *meas, double *a
  * Host-only; later calls use the new weights.  alpha, beta finite and >= 0. */
 elfpie_status elfpie_plan_set_penalty(elfpie_plan *plan, double alpha, double beta);
 
-/* Forward model, Eq. (1) with M = 1: for every LED, o_k = F_B P M_k Psi.
+/* Forward model, Eq. (1): for every LED, o_k = F_B P M_k Psi; image n is the sum
+ * of |o_k|^2 over its mux LEDs.
  * psi: n_hi^2 complex; P: n_lo^2 complex.  Optional outputs (NULL to skip):
- * fields: K x n_lo x n_lo complex o_k; intens: K x n_lo x n_lo real |o_k|^2.
- * If meas (K x n_lo x n_lo real) and d_loss4 (4 doubles) are both given, writes
+ * fields: K x n_lo x n_lo complex o_k, one per LED; intens: (K / mux) x n_lo x n_lo
+ * real, sum_m |o_(n, m)|^2 per image.
+ * If meas ((K / mux) x n_lo x n_lo real) and d_loss4 (4 doubles) are both given, writes
  * [L_fid, L_A, L_Phi, L_fid + alpha L_A + beta L_Phi] (Eq. 4/5, 6, 7, 8). */
 elfpie_status elfpie_forward(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
                              void *fields, void *intens, double *d_loss4, void *stream);
@@ -208,7 +214,7 @@ elfpie_status elfpie_spectrum_from_object(elfpie_plan *plan, const void *obj, vo
 /* Initial state: psi = the on-axis LED's window filled, on the pupil support,
  * with (r / n_lo) fftshift(fft2(sqrt(I_c))); zero elsewhere; P = 1 on the
  * support (everywhere without ELFPIE_PUPIL_SUPPORT); mu = v = 0; delta = lr^2;
- * t = 0.  meas: K x n_lo x n_lo real. */
+ * t = 0.  meas: (K / mux) x n_lo x n_lo real; the image of the on-axis LED is used. */
 elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpie_state *state,
                                 void *stream);
 

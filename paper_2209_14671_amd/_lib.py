@@ -28,7 +28,7 @@ class ProblemC(ctypes.Structure):
         ("gamma1", c_double), ("gamma2", c_double), ("eta_opt", c_double),
         ("eta_h", c_double), ("l1_eps", c_double),
         ("fidelity", c_int32), ("norm", c_int32), ("precision", c_int32), ("flags", c_uint32),
-        ("fid_gamma", c_double), ("optimizer", c_int32),
+        ("fid_gamma", c_double), ("optimizer", c_int32), ("mux", c_int32),
     ]
 
 

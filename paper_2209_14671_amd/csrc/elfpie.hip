@@ -52,6 +52,7 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 // Everything the host derives from the problem statement before touching the device.
 struct Tables {
   int n_lo = 0, n_hi = 0, K = 0, S = 0, prec = 0;
+  int mux = 1, nimg = 0;           // LEDs per image; images (K / mux)
   int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
   int kc = 0;                      // LED nearest the optical axis
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
@@ -65,7 +66,7 @@ struct Tables {
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
-  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0;
+  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0;
   size_t total = 0;
 };
 
@@ -108,10 +109,14 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   if (p->flags & ~7u) return fail(ELFPIE_E_INVALID, "unknown flag bits");
   if (p->optimizer < ELFPIE_OPT_ELFPIE || p->optimizer > ELFPIE_OPT_ADABELIEF)
     return fail(ELFPIE_E_INVALID, "optimizer must be one of ELFPIE_OPT_*");
+  if (p->mux < 1 || p->mux > 64 || p->K % p->mux != 0)
+    return fail(ELFPIE_E_INVALID, "mux must lie in 1..64 and divide K");
 
   tb->n_lo = p->n_lo;
   tb->n_hi = (int)nh;
   tb->K = p->K;
+  tb->mux = p->mux;
+  tb->nimg = p->K / p->mux;
   tb->prec = p->precision;
   tb->elem = f32 ? 4 : 8;
   const int n = tb->n_lo;
@@ -231,6 +236,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
+  // multiplexed plans keep every LED's field between the two passes of the image
+  tb->o_mux = tb->mux > 1 ? take((size_t)tb->K * n * n * cxb) : 0;
   tb->total = off;
   return ELFPIE_OK;
 }
@@ -293,7 +300,10 @@ struct Ops {
     const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
     const bool stored = (a.mode & LED_STORED) != 0;
     constexpr int NT = LedShape<N>::NT;
-    if (stored && scaled) k_led<T, N, true, true><<<K, NT, 0, s>>>(a);
+    if (a.mux > 1) {  // one block per image
+      if (scaled) k_led_mux<T, N, true><<<K / a.mux, NT, 0, s>>>(a);
+      else k_led_mux<T, N, false><<<K / a.mux, NT, 0, s>>>(a);
+    } else if (stored && scaled) k_led<T, N, true, true><<<K, NT, 0, s>>>(a);
     else if (stored) k_led<T, N, false, true><<<K, NT, 0, s>>>(a);
     else if (scaled) k_led<T, N, true, false><<<K, NT, 0, s>>>(a);
     else k_led<T, N, false, false><<<K, NT, 0, s>>>(a);
@@ -326,6 +336,8 @@ struct Ops {
     a.eps = pl->prob.l1_eps;
     a.mode = mode;
     a.t_bump = reinterpret_cast<long long*>(t_bump);
+    a.mux = tb.mux;
+    if (tb.mux > 1 && !fields) a.fields = pl->at<void>(tb.o_mux);
     a.fidelity = pl->prob.fidelity;
     a.fid_gamma = pl->prob.fid_gamma;
     a.norm = pl->prob.norm;
@@ -532,7 +544,7 @@ struct Ops {
     const Tables& tb = pl->tb;
     FinArgs a{};
     a.fid_partial = pl->at<double>(tb.o_fid);
-    a.K = tb.K;
+    a.K = tb.nimg;
     a.hess_partial = pl->at<double>(tb.o_hess);
     a.ntiles = tb.nhp;
     a.alpha = pl->prob.alpha;
@@ -675,7 +687,7 @@ struct Ops {
     k_init_pupil<T><<<(B + 255) / 256, 256, 0, s>>>(static_cast<C*>(st->P), pl->at<int>(tb.o_xlo),
                                                    pl->at<int>(tb.o_xhi), tb.n_lo);
     LAUNCH_CHECK(pl, "k_init_pupil");
-    const T* mc = static_cast<const T*>(meas) + (size_t)tb.kc * B;
+    const T* mc = static_cast<const T*>(meas) + (size_t)(tb.kc / tb.mux) * B;  // the image that LED kc lights
     const int y0 = tb.win[2 * tb.kc], x0 = tb.win[2 * tb.kc + 1];
     const T sc = T((double)pl->prob.upsample / tb.n_lo);
     C* psi = static_cast<C*>(st->psi);
@@ -700,16 +712,16 @@ struct Ops {
   static elfpie_status auto_penalty(elfpie_plan* pl, const void* meas, double* alpha, hipStream_t s) {
     const Tables& tb = pl->tb;
     double* part = pl->at<double>(tb.o_fid);
-    k_auto_penalty<T><<<tb.K, 256, 0, s>>>(static_cast<const T*>(meas), tb.n_lo, pl->prob.fidelity,
-                                           pl->prob.fid_gamma, part);
+    k_auto_penalty<T><<<tb.nimg, 256, 0, s>>>(static_cast<const T*>(meas), tb.n_lo, pl->prob.fidelity,
+                                              pl->prob.fid_gamma, part);
     LAUNCH_CHECK(pl, "k_auto_penalty");
-    std::vector<double> h(tb.K);
-    HIP_TRY(pl, hipMemcpyAsync(h.data(), part, tb.K * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> h(tb.nimg);
+    HIP_TRY(pl, hipMemcpyAsync(h.data(), part, tb.nimg * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(pl, hipStreamSynchronize(s));
     double acc = 0.0;
     const double wh = (double)tb.n_lo * tb.n_lo;
-    for (int k = 0; k < tb.K; ++k) acc += h[k] / wh;
-    *alpha = 0.2 * std::sqrt(M_PI / 2.0) * acc / tb.K;
+    for (int k = 0; k < tb.nimg; ++k) acc += h[k] / wh;
+    *alpha = 0.2 * std::sqrt(M_PI / 2.0) * acc / tb.nimg;
     return ELFPIE_OK;
   }
 
@@ -798,6 +810,7 @@ elfpie_status elfpie_problem_defaults(elfpie_problem* p) {
   p->fidelity = ELFPIE_FID_INTENSITY;
   p->fid_gamma = 0.5;
   p->optimizer = ELFPIE_OPT_ELFPIE;
+  p->mux = 1;
   p->norm = ELFPIE_NORM_ANISO;
   p->precision = ELFPIE_F32;
   p->flags = ELFPIE_PUPIL_SUPPORT;

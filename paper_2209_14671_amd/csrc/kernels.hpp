@@ -342,6 +342,234 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   }
 }
 
+// dL/d(conj o_m) = f o_m for every LED m of an image: the real factor
+// f = q g'(S) with S the image's summed intensity (g'(0) taken as 0 for the powers).
+template <bool SCALED, class T>
+__device__ __forceinline__ T fid_slope(int fid, T S, T q, T gam) {
+  if (fid == 0) return S > T(0) ? q / (T(2) * sqrt(S)) : T(0);
+  if constexpr (SCALED) {
+    if (fid == 2) return S > T(0) ? q * gam * pow_t(S, gam - T(1)) : T(0);
+    if (fid == 3) return q / (T(1) + S);
+  }
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// Multiplexed illumination (Eq. 1 with M > 1): one workgroup per image, whose M
+// LEDs are handled in turn through the same LDS tile.
+//   for each LED m: gather, inverse transform, o_m to `fields` (the caller's
+//     output, its stored fields, or plan scratch), S += |o_m|^2;
+//   residual g(S) - g(I), features, loss and the factor f = q g'(S);
+//   for each LED m: W_m = f o_m read back, forward transform, contributions.
+// The fields are kept in the true (centred) frame, as elfpie_forward writes them.
+// ---------------------------------------------------------------------------
+template <class T, int N, bool SCALED>
+__global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
+  using Sh = LedShape<N>;
+  constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
+  constexpr int MB1 = ceil_div(N * (N / R1), NT);
+  constexpr int MB2 = ceil_div(N * (N / R2), NT);
+  static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
+  constexpr int PPT = N * N / NT;
+  constexpr int GB = PPT < 8 ? PPT : 8;
+  using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
+  using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1>;
+  using P1iC = StockhamPass<T, N, R1, 1, true, NT, MB1, 1, PITCH, N>;
+  using P2iC = StockhamPass<T, N, R2, R1, true, NT, MB2, 1, PITCH, N>;
+  using P1fR = StockhamPass<T, N, R1, 1, false, NT, MB1, PITCH, 1, N>;
+  using P2fR = StockhamPass<T, N, R2, R1, false, NT, MB2, PITCH, 1, N>;
+  using P1fC = StockhamPass<T, N, R1, 1, false, NT, MB1, 1, PITCH>;
+  using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH>;
+
+  __shared__ cx<T> img[N * PITCH];
+  __shared__ cx<T> twl[N];
+  __shared__ int sxlo[N], sxhi[N], sroff[N];
+  __shared__ double red[NT / 64];
+
+  const int tid = threadIdx.x;
+  const int im = blockIdx.x;  // image
+  const int M = a.mux;
+  led_bump_step(a, im, tid);
+  const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
+  const cx<T>* P = static_cast<const cx<T>*>(a.P);
+  cx<T>* F = static_cast<cx<T>*>(a.fields);
+  for (int i = tid; i < N; i += NT) {
+    twl[i] = static_cast<const cx<T>*>(a.tw)[i];
+    sxlo[i] = a.xlo[i];
+    sxhi[i] = a.xhi[i];
+    sroff[i] = a.rowoff[i];
+  }
+  const int mode = a.mode;
+  const bool stored = (mode & LED_STORED) != 0;
+  const T sc = T(a.inv_scale);
+  __syncthreads();
+
+  int mm[MB2], jj[MB2];
+  bool lv[MB2];
+  P2iC::coords(N, tid, mm, jj, lv);
+  T S[MB2][R2];
+#pragma unroll
+  for (int i = 0; i < MB2; ++i)
+#pragma unroll
+    for (int r = 0; r < R2; ++r) S[i][r] = T(0);
+
+  for (int m = 0; m < M; ++m) {
+    const int k = im * M + m;
+    cx<T>* Fk = F + (size_t)k * N * N;
+    cx<T> o[MB2][R2];
+    if (stored) {
+#pragma unroll
+      for (int i = 0; i < MB2; ++i)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) o[i][r] = Fk[(jj[i] + r * R1) * N + mm[i]];
+    } else {
+      const cx<T>* win = psi + (size_t)a.win[2 * k] * a.n_hi + a.win[2 * k + 1];
+#pragma unroll
+      for (int i0 = 0; i0 < PPT; i0 += GB) {
+        cx<T> pv[GB], wv[GB];
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+          const int p = tid + (i0 + i) * NT;
+          pv[i] = P[p];
+          wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
+        }
+#pragma unroll
+        for (int i = 0; i < GB; ++i) {
+          const int p = tid + (i0 + i) * NT;
+          const int y = p / N, x = p % N;
+          img[y * PITCH + x] = (x >= sxlo[y] && x <= sxhi[y]) ? pv[i] * wv[i] : czero<T>();
+        }
+      }
+      __syncthreads();
+      const int nband = a.y_max - a.y_min + 1;
+      P1iR::run(img, a.y_min, nband, twl, tid);
+      P2iR::run(img, a.y_min, nband, twl, tid);
+      P1iC::run(img, 0, N, twl, tid);
+      P2iC::load(img, 0, mm, jj, lv, twl, o);
+      __syncthreads();  // the next LED's gather overwrites the tile
+#pragma unroll
+      for (int i = 0; i < MB2; ++i)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const int y = jj[i] + r * R1, x = mm[i];
+          const cx<T> ov = scale(o[i][r], sc);
+          o[i][r] = ((x + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;  // true frame
+          Fk[y * N + x] = o[i][r];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MB2; ++i)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) S[i][r] += norm2(o[i][r]);
+  }
+
+  if (mode & LED_INTENS) {
+#pragma unroll
+    for (int i = 0; i < MB2; ++i)
+#pragma unroll
+      for (int r = 0; r < R2; ++r)
+        static_cast<T*>(a.intens)[(size_t)im * N * N + (jj[i] + r * R1) * N + mm[i]] = S[i][r];
+  }
+  if (!(mode & (LED_GRAD | LED_LOSS))) return;
+
+  const T eps = T(a.eps), gam = T(a.fid_gamma);
+  const T* meas = static_cast<const T*>(a.meas) + (size_t)im * N * N;
+  T* eb = reinterpret_cast<T*>(img);
+#pragma unroll
+  for (int i = 0; i < MB2; ++i)
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int y = jj[i] + r * R1, x = mm[i];
+      eb[y * PITCH + x] = fid_residual<SCALED>(a.fidelity, S[i][r], meas[y * N + x], gam);
+    }
+  __syncthreads();
+
+  auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < MB2; ++i) {
+    const int j = jj[i], x = mm[i];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int y = j + r * R1;
+      const T e = E(y, x);
+      const T dx0 = (x < N - 1) ? E(y, x + 1) - e : T(0);
+      const T dy0 = (y < N - 1) ? E(y + 1, x) - e : T(0);
+      T q;
+      if (a.norm == 0) {
+        const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
+        const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
+        q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
+        lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+      } else {
+        const T s0 = dx0 * dx0 + dy0 * dy0;
+        q = -(dx0 + dy0) * inv_norm(s0, eps);
+        if (x > 0) {
+          const T el = E(y, x - 1);
+          const T gx = e - el;
+          const T gy = (y < N - 1) ? E(y + 1, x - 1) - el : T(0);
+          q += gx * inv_norm(gx * gx + gy * gy, eps);
+        }
+        if (y > 0) {
+          const T eu = E(y - 1, x);
+          const T gy = e - eu;
+          const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
+          q += gy * inv_norm(gx * gx + gy * gy, eps);
+        }
+        lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+      }
+      S[i][r] = fid_slope<SCALED>(a.fidelity, S[i][r], q, gam);  // S now holds f
+    }
+  }
+  const double tot = block_sum<NT>(lsum, red);  // contains barriers: the residual reads are done
+  if (tid == 0) a.fid_partial[im] = tot;
+  if (!(mode & LED_GRAD)) return;
+
+  const int ncol = a.x_max - a.x_min + 1;
+  for (int m = 0; m < M; ++m) {
+    const int k = im * M + m;
+    const cx<T>* Fk = F + (size_t)k * N * N;
+#pragma unroll
+    for (int i = 0; i < MB2; ++i)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = jj[i] + r * R1, x = mm[i];
+        const cx<T> f = Fk[y * N + x];
+        const cx<T> ov = ((x + y) & 1) ? cx<T>{-f.x, -f.y} : f;  // kernel frame
+        img[y * PITCH + x] = scale(ov, S[i][r]);
+      }
+    __syncthreads();
+    P1fR::run(img, 0, N, twl, tid);
+    P2fR::run(img, 0, N, twl, tid);
+    P1fC::run(img, a.x_min, ncol, twl, tid);
+    int fm[MB2], fj[MB2];
+    bool fl[MB2];
+    P2fC::coords(ncol, tid, fm, fj, fl);
+    cx<T> Y[MB2][R2];
+    P2fC::load(img, a.x_min, fm, fj, fl, twl, Y);
+    const cx<T>* win = psi + (size_t)a.win[2 * k] * a.n_hi + a.win[2 * k + 1];
+    cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
+    cx<T>* D = static_cast<cx<T>*>(a.D) + (size_t)k * a.S;
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+      if (!fl[i]) continue;
+      const int x = a.x_min + fm[i];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = fj[i] + r * R1;
+        const int lo = sxlo[y];
+        if (x >= lo && x <= sxhi[y]) {
+          const int s = sroff[y] + x - lo;
+          const cx<T> yv = scale(Y[i][r], sc);
+          C[s] = cmulc(P[y * N + x], yv);
+          D[s] = cmulc(win[(size_t)y * a.n_hi + x], yv);
+        }
+      }
+    }
+    __syncthreads();  // the next LED's W overwrites the tile
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Object-branch FFTs on the n_hi x n_hi spectrum: RPB rows (or columns) per block.
 // ---------------------------------------------------------------------------

@@ -38,6 +38,7 @@ struct LedArgs {
   int norm;
   double fid_gamma;     // exponent of g(x) = x^gamma
   long long* t_bump;    // step counter, advanced once by block 0 in step mode (else NULL)
+  int mux;              // LEDs per image (Eq. 1's M); block b serves LEDs b M .. b M + M - 1
 };
 
 struct HessArgs {

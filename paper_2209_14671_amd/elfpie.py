@@ -43,6 +43,7 @@ class Problem:
     flags: int = PUPIL_SUPPORT
     fid_gamma: float = 0.5          # exponent of FID_GAMMA
     optimizer: int = OPT_ELFPIE     # update rule (Eq. 19 or a Sec. 6.2 alternative)
+    mux: int = 1                    # LEDs lit together per image (Eq. 1's M)
 
     def to_c(self):
         k = np.ascontiguousarray(np.asarray(self.led_k, dtype=np.float64).reshape(-1, 2))
@@ -56,6 +57,7 @@ class Problem:
         p.fidelity, p.norm, p.precision, p.flags = int(self.fidelity), int(self.norm), int(self.precision), int(self.flags)
         p.fid_gamma = float(self.fid_gamma)
         p.optimizer = int(self.optimizer)
+        p.mux = int(self.mux)
         return p, k  # keep k alive while p is used
 
 
@@ -130,6 +132,8 @@ class Plan:
         info = (ctypes.c_int32 * 5)()
         _lib.check(self.lib.elfpie_plan_info(self.handle, info), self.handle)
         self.n_hi, self.S, self.K, self.n_lo, self.kc = (int(v) for v in info)
+        self.mux = int(problem.mux)
+        self.n_img = self.K // self.mux
         self.rdtype = torch.float32 if problem.precision == F32 else torch.float64
         self.cdtype = torch.complex64 if problem.precision == F32 else torch.complex128
 
@@ -168,6 +172,12 @@ class Plan:
 
     @property
     def stack_shape(self):
+        """Measured (and predicted) images: K / mux of n_lo x n_lo."""
+        return (self.n_img, self.n_lo, self.n_lo)
+
+    @property
+    def fields_shape(self):
+        """Low-resolution fields: one n_lo x n_lo per LED."""
         return (self.K, self.n_lo, self.n_lo)
 
     # -- state ----------------------------------------------------------------------
@@ -220,7 +230,7 @@ class Plan:
             self._need(meas, self.stack_shape, self.rdtype, "meas")
         out = {}
         kw = dict(device=self.device)
-        f = torch.empty(self.stack_shape, dtype=self.cdtype, **kw) if fields else None
+        f = torch.empty(self.fields_shape, dtype=self.cdtype, **kw) if fields else None
         i = torch.empty(self.stack_shape, dtype=self.rdtype, **kw) if intens else None
         l4 = torch.empty(4, dtype=torch.float64, **kw) if loss else None
         if loss and meas is None:
@@ -250,7 +260,7 @@ class Plan:
             self._check(self.lib.elfpie_grad(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(g), _ptr(gP),
                                              _ptr(l4), _stream()))
         else:
-            self._need(fields, self.stack_shape, self.cdtype, "fields")
+            self._need(fields, self.fields_shape, self.cdtype, "fields")
             self._check(self.lib.elfpie_grad_fields(self.handle, _ptr(psi), _ptr(P), _ptr(meas), _ptr(fields),
                                                     _ptr(g), _ptr(gP), _ptr(l4), _stream()))
         return l4, g, gP

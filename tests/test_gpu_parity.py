@@ -291,3 +291,65 @@ def test_config2_full_size_step(l1_eps):
     print(f"config2 l1_eps={l1_eps}: psi {e_psi:.2e} P {e_P:.2e} loss {el}")
     assert e_psi < (1e-5 if l1_eps > 0 else 5e-5) and e_P < 1e-5
     assert np.all(el < 1e-5)
+
+
+# --- multiplexed illumination (Eq. 1 with M LEDs per image) ---
+
+MUX_CASES = [(2, orc.FID_INTENSITY, orc.NORM_ANISO, 0.5, True), (3, orc.FID_AMPLITUDE, orc.NORM_ISO, 0.5, True),
+             (2, orc.FID_GAMMA, orc.NORM_ANISO, 0.375, False), (3, orc.FID_INTENSITY, orc.NORM_ISO, 0.5, False),
+             (2, orc.FID_LOG, orc.NORM_ANISO, 0.5, True)]
+
+
+@pytest.mark.parametrize("mux,fidelity,norm,gamma,f32", MUX_CASES)
+def test_multiplexed_forward_and_step_match_oracle(mux, fidelity, norm, gamma, f32):
+    pair = make_pair(32, 4, 5, f32=f32, fidelity=fidelity, norm=norm, fid_gamma=gamma, mux=mux)
+    plan = make_plan(pair, f32)
+    assert plan.n_img == pair.oprob.K and plan.K == pair.oprob.n_led
+    psi, P, meas = dev(pair.psi, f32), dev(pair.P, f32), dev(pair.meas, f32)
+    out = plan.forward(psi, P, meas, fields=True, intens=True, loss=True)
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    tol = TOL[f32]
+    assert rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob)) < tol["field"]
+    assert rel_l2(host(out["intens"]), orc.intensities(pair.psi, pair.P, pair.oprob)) < tol["field"]
+    assert np.all(np.abs(host(out["loss4"]) - rl4) / np.abs(rl4) < tol["loss"])
+    l4, g, gP = plan.grad(psi, P, meas)
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    _, g2, gP2 = plan.grad(psi, P, meas, fields=out["fields"])
+    st = gpu_state(plan, pair, f32)
+    plan.step(st, meas)
+    torch.cuda.synchronize()
+    ref, _ = orc.step(pair.state, pair.meas, pair.oprob)
+    es = rel_l2(host(st.psi), ref.psi)
+    print(f"mux={mux} fid={fidelity} f32={f32}: g_psi {eg:.2e} g_P {egp:.2e} step psi {es:.2e}")
+    assert eg < tol["grad"] and egp < tol["grad"]
+    assert torch.equal(g, g2) and torch.equal(gP, gP2)  # stored fields give the same bits
+    assert es < tol["state"] and rel_l2(host(st.P), ref.P) < tol["state"]
+
+
+def test_multiplexed_run_equals_repeated_steps():
+    pair = make_pair(32, 4, 5, f32=False, mux=2)
+    plan = make_plan(pair, False)
+    meas = dev(pair.meas, False)
+    a = gpu_state(plan, pair, False)
+    b = a.clone()
+    plan.run(a, meas, 9)
+    for _ in range(9):
+        plan.step(b, meas)
+    torch.cuda.synchronize()
+    for k in ("psi", "P", "mu_psi", "v_psi", "t"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    ref, _ = orc.run(pair.state, pair.meas, pair.oprob, 9)
+    assert rel_l2(host(a.psi), ref.psi) < 1e-11
+
+
+def test_multiplexed_full_tile_gradient_matches_oracle():
+    """The 128^2 tile of the multiplexed kernel (FP32, two LEDs per image)."""
+    pair = make_pair(128, 4, 5, f32=True, mux=2, warm_steps=0)
+    plan = make_plan(pair, True)
+    l4, g, gP = plan.grad(dev(pair.psi, True), dev(pair.P, True), dev(pair.meas, True))
+    torch.cuda.synchronize()
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    print(f"mux=2 n_lo=128: g_psi {eg:.2e} g_P {egp:.2e}")
+    assert eg < TOL[True]["grad"] and egp < TOL[True]["grad"]
+    assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < TOL[True]["loss"])
