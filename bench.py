@@ -175,6 +175,57 @@ def optimizer_bench(args, dev):
                       "optimizers": rows}), flush=True)
 
 
+def sweep_bench(args, dev, iters=100):
+    """Sec. 4.2 grid on synthetic stacks of the paper's shape (512^2 / K=225 / 128^2, FP32):
+    LED shift d in {0, 0.5, 2} mm, uneven illumination c in {0.25, 0.75} (radial fall-off of
+    strength c), and Gaussian (sigma 1e-3 of the peak), Poisson (1e3 photons at the peak) or
+    salt-and-pepper (1e-3) noise.  Each case: simulate, degrade, reconstruct for `iters`
+    iterations from the standard initial state, report LSNR of |O| and angle(O) against the
+    ground truth, the dark-field noise level (Eq. 21) and the GPU time."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    from paper_2209_14671_amd import metrics
+    optics = synth.Optics(n_lo=128, upsample=4, led_grid=15)
+    flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+    noises = {"gaussian": dict(gauss_sigma_rel=1e-3), "poisson": dict(photons=1e3), "snp": dict(snp_prob=1e-3)}
+    rows = []
+    for d in (0.0, 0.5, 2.0):
+        for c in (0.25, 0.75):
+            for name, kw in noises.items():
+                case = synth.make_case(optics, [5, int(d * 10), int(c * 100), len(rows)], jitter_mm=d,
+                                       degradation=synth.Degradation(vignetting=c, **kw))
+                sim = E.Plan(E.problem_from_optics(optics, case.led_k_true, precision=E.F32), device=dev)
+                psi_true = sim.spectrum_from_object(torch.from_numpy(case.obj).to(torch.complex64).to(dev))
+                clean = sim.forward(psi_true, torch.from_numpy(case.pupil).to(torch.complex64).to(dev),
+                                    intens=True)["intens"].cpu().numpy().astype(np.float64)
+                sim.close()
+                noisy = synth.degrade(clean, case.degradation, case.noise_seed)
+                meas = torch.from_numpy(noisy).to(torch.float32).to(dev)
+                plan = E.Plan(E.problem_from_optics(optics, case.led_k, precision=E.F32, flags=flags), device=dev)
+                st = plan.init_state(meas)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                plan.run(st, meas, iters)
+                ev1.record()
+                torch.cuda.synchronize()
+                O = plan.object_from_spectrum(st.psi).cpu().numpy().astype(np.complex128)
+                plan.close()
+                dark = metrics.dark_field(case.led_k_true, optics.n_lo, optics.dx_lo_um, optics.wavelength_um,
+                                          optics.na)
+                la = metrics.lsnr(np.abs(O), np.abs(case.obj))
+                lp = metrics.lsnr(np.angle(O), np.angle(case.obj))
+                rows.append({"d_mm": d, "c": c, "noise": name, "NL_pct": round(metrics.noise_level(clean, noisy, dark), 2),
+                             "lsnr_amp_db": round(la, 2), "lsnr_phase_db": round(lp, 2),
+                             "lsnr_mean_db": round((la + lp) / 2, 2), "gpu_ms": round(ev0.elapsed_time(ev1), 2)})
+                log(f"d={d} c={c} {name}: LSNR amp {la:.2f} dB, phase {lp:.2f} dB")
+    print(json.dumps({"metric": "reconstruction LSNR (Eq. 22) over the Sec. 4.2 grid, synthetic stacks",
+                      "unit": "dB", "iterations": iters, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, circular pupil"},
+                      "rows": rows}), flush=True)
+
+
 def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
     """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
     import oracle as orc
@@ -209,11 +260,12 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed after the run (0: skip); the same copy "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
-    ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers"], default="iteration",
+    ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers", "sweep"], default="iteration",
                     help="iteration: the throughput line (default); autograd: forward + backward of the "
                          "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields; "
                          "optimizers: loss curves of Eq. 19 and the Sec. 6.2 alternatives on the "
-                         "512^2 / K=225 / 128^2 stack")
+                         "512^2 / K=225 / 128^2 stack; sweep: reconstruction quality (LSNR, Eq. 22) over LED "
+                         "shift, uneven illumination and noise (the Tables 2-4 grid) on synthetic stacks")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -232,6 +284,9 @@ def main():
         return
     if args.workload == "optimizers":
         optimizer_bench(args, dev)
+        return
+    if args.workload == "sweep":
+        sweep_bench(args, dev)
         return
     case = synth.config_case(2)
     o = case.optics
