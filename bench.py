@@ -44,11 +44,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def byte_model(K, S, B, A):
-    """Algorithmic HBM bytes (FP32): per-LED kernel and whole iteration."""
-    led_kernel = K * (24 * S + 4 * B) + 8 * S          # window of psi + image in, C and D out; P once
-    iteration = K * (40 * S + 4 * B) + 112 * A         # + C, D re-read; object FFTs, Hessian, update
+def byte_model(K, S, B, A, elem=4):
+    """Algorithmic HBM bytes: per-LED branch and whole iteration, for reals of `elem`
+    bytes (complex 2 elem; the Eq. 19 second moment is 8 bytes in both precisions).
+    FP32: per LED 24 S + 4 B (window of psi on the support, image, C and D) plus P once;
+    per iteration 40 S + 4 B per LED (C and D re-read) plus 112 A (object transforms,
+    Hessian, update)."""
+    c, r = 2 * elem, elem
+    led_kernel = K * (3 * c * S + r * B) + c * S
+    iteration = K * (5 * c * S + r * B) + (11 * c + 16 + 2 * r) * A
     return led_kernel, iteration
+
+
+WORKLOADS = {
+    1: ("f64", "config 1, FP64: 128x128 high-res, 5x5 LEDs (K=25), 32x32 low-res, circular pupil, noise-free"),
+    2: ("f32", "single FOV, FP32: 512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, "
+               "Zernike pupil, noise + salt-and-pepper + vignetting + LED jitter"),
+    4: ("f32", "FP32: 256x256 high-res, 11x11 LEDs (K=121), 64x64 low-res, circular pupil, noise-free"),
+    5: ("f32", "FP32: 1024x1024 high-res, 15x15 LEDs (K=225), 256x256 low-res, circular pupil, noise-free"),
+}
+LED_KERNEL = {1: "k_led<double,32>", 2: "k_led<float,128>", 4: "k_led<float,64>",
+              5: "k_big_rows_inv + k_big_cols + k_big_rows_fwd (256^2 tile through HBM)"}
 
 
 def measured_traffic(src_hash):
@@ -260,6 +276,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed after the run (0: skip); the same copy "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
+    ap.add_argument("--config", type=int, choices=sorted(WORKLOADS), default=2,
+                    help="workload of the iteration line: 2 is the headline (512^2 / K=225 / 128^2, FP32); "
+                         "1, 4 and 5 give the absolute numbers of the other single-FOV shapes")
     ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers", "sweep"], default="iteration",
                     help="iteration: the throughput line (default); autograd: forward + backward of the "
                          "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields; "
@@ -288,22 +307,25 @@ def main():
     if args.workload == "sweep":
         sweep_bench(args, dev)
         return
-    case = synth.config_case(2)
+    case = synth.config_case(args.config)
     o = case.optics
     flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+    dtype, workload = WORKLOADS[args.config]
+    prec = E.F64 if dtype == "f64" else E.F32
+    cdt, rdt = (torch.complex128, torch.float64) if dtype == "f64" else (torch.complex64, torch.float32)
 
     # simulate the measured stack on the GPU (library forward model, true LED positions)
     log("simulating the measured stack")
-    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=E.F32), device=dev)
-    obj = torch.from_numpy(case.obj).to(torch.complex64).to(dev)
+    sim = E.Plan(E.problem_from_optics(o, case.led_k_true, precision=prec), device=dev)
+    obj = torch.from_numpy(case.obj).to(cdt).to(dev)
     psi_true = sim.spectrum_from_object(obj)
-    p_true = torch.from_numpy(case.pupil).to(torch.complex64).to(dev)
+    p_true = torch.from_numpy(case.pupil).to(cdt).to(dev)
     clean = sim.forward(psi_true, p_true, intens=True)["intens"].cpu().numpy().astype(np.float64)
     meas_np = synth.degrade(clean, case.degradation, case.noise_seed)
-    meas = torch.from_numpy(meas_np).to(torch.float32).to(dev)
+    meas = torch.from_numpy(meas_np).to(rdt).to(dev)
     sim.close()
 
-    plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=E.F32, flags=flags), device=dev)
+    plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=prec, flags=flags), device=dev)
     K, S, B, A = plan.K, plan.S, plan.n_lo ** 2, plan.n_hi ** 2
     st = plan.init_state(meas)
     stream = torch.cuda.current_stream()
@@ -334,23 +356,24 @@ def main():
     log("per-stage timing")
     stages = plan.stage_timing(st, meas, args.stage_reps)
     copy = copy_bandwidth(dev, args.copy_mib) if args.copy_mib else None
-    led_bytes, it_bytes = byte_model(K, S, B, A)
+    led_bytes, it_bytes = byte_model(K, S, B, A, 8 if dtype == "f64" else 4)
     led_s = stages["led"] * 1e-3
     src_hash = kernel_source_hash()
-    traffic = measured_traffic(src_hash)
+    traffic = measured_traffic(src_hash) if args.config == 2 else None
     roof = {"bound": "hbm", "achieved": round(led_bytes / led_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(led_bytes / led_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_led<float,128>", "algorithmic_bytes": led_bytes, "avg_launch_ms": round(stages["led"], 4)}
+            "kernel": LED_KERNEL[args.config], "algorithmic_bytes": led_bytes,
+            "avg_launch_ms": round(stages["led"], 4)}
     if copy is not None:
         roof["copy_GBs"] = copy
     it_gbs = it_bytes / (ms_step * 1e-3) / 1e9
 
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "LED-updates/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC if args.config == 2 else "LED sub-image updates/sec (K x iters/s); % HBM roofline",
+        "value": round(value, 1), "unit": "LED-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "single FOV, FP32: 512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, "
-                               "Zernike pupil, noise + salt-and-pepper + vignetting + LED jitter",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": workload,
                    "K": K, "n_lo": plan.n_lo, "n_hi": plan.n_hi, "support_px": S, "learn_pupil": True},
         "roofline": roof,
         "iteration_roofline": {"algorithmic_bytes": it_bytes, "achieved_GBs": round(it_gbs, 1),

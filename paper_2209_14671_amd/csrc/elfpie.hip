@@ -13,6 +13,7 @@
 
 #include "elfpie.h"
 #include "kernels.hpp"
+#include "big_led.hpp"
 
 using namespace elfpie;
 
@@ -53,6 +54,8 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 struct Tables {
   int n_lo = 0, n_hi = 0, K = 0, S = 0, prec = 0;
   int mux = 1, nimg = 0;           // LEDs per image; images (K / mux)
+  bool big = false;                // n_lo = 256: the per-LED branch through HBM scratch
+  int nfid = 0;                    // fidelity loss partials per evaluation
   int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
   int kc = 0;                      // LED nearest the optical axis
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
@@ -66,7 +69,7 @@ struct Tables {
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
-  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0;
+  size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0, o_bigA = 0, o_bigB = 0;
   size_t total = 0;
 };
 
@@ -84,8 +87,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   if (!p->led_k) return fail(ELFPIE_E_INVALID, "led_k is NULL");
   if (p->n_lo < 2 || p->upsample < 1) return fail(ELFPIE_E_INVALID, "n_lo must be >= 2 and upsample >= 1");
   const bool f32 = p->precision == ELFPIE_F32;
-  if (!is_pow2(p->n_lo) || p->n_lo < 32 || p->n_lo > (f32 ? 128 : 64))
-    return fail(ELFPIE_E_UNSUPPORTED, f32 ? "n_lo must be 32, 64 or 128 in F32" : "n_lo must be 32 or 64 in F64");
+  if (!is_pow2(p->n_lo) || p->n_lo < 32 || p->n_lo > (f32 ? 256 : 64))
+    return fail(ELFPIE_E_UNSUPPORTED, f32 ? "n_lo must be 32, 64, 128 or 256 in F32" : "n_lo must be 32 or 64 in F64");
   const long long nh = (long long)p->n_lo * p->upsample;
   if (!is_pow2((int)std::min<long long>(nh, 1 << 30)) || nh < 128 || nh > 1024)
     return fail(ELFPIE_E_UNSUPPORTED, "n_hi = n_lo * upsample must be 128, 256, 512 or 1024");
@@ -111,12 +114,16 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
     return fail(ELFPIE_E_INVALID, "optimizer must be one of ELFPIE_OPT_*");
   if (p->mux < 1 || p->mux > 64 || p->K % p->mux != 0)
     return fail(ELFPIE_E_INVALID, "mux must lie in 1..64 and divide K");
+  if (p->n_lo == 256 && p->mux != 1)
+    return fail(ELFPIE_E_UNSUPPORTED, "multiplexed illumination needs n_lo <= 128");
 
   tb->n_lo = p->n_lo;
   tb->n_hi = (int)nh;
   tb->K = p->K;
   tb->mux = p->mux;
   tb->nimg = p->K / p->mux;
+  tb->big = p->n_lo == 256;
+  tb->nfid = tb->big ? p->K * (256 / BigLed<256>::W) : tb->nimg;
   tb->prec = p->precision;
   tb->elem = f32 ? 4 : 8;
   const int n = tb->n_lo;
@@ -231,13 +238,17 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_gP = take((size_t)n * n * cxb);
   tb->o_part = take((size_t)tb->nch * S * cxb);
   tb->o_Pf = take((size_t)n * n * cxb);
-  tb->o_fid = take(tb->K * sizeof(double));
+  tb->o_fid = take((size_t)std::max(tb->K, tb->nfid) * sizeof(double));
   tb->o_hess = take((size_t)2 * std::max(tb->nhp, ntiles) * sizeof(double));
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
   // multiplexed plans keep every LED's field between the two passes of the image
   tb->o_mux = tb->mux > 1 ? take((size_t)tb->K * n * n * cxb) : 0;
+  // the large tile keeps the band rows of each LED's row transforms between launches
+  const size_t band = tb->big ? (size_t)(tb->y_max - tb->y_min + 1) : 0;
+  tb->o_bigA = tb->big ? take((size_t)tb->K * band * n * cxb) : 0;
+  tb->o_bigB = tb->big ? take((size_t)tb->K * band * n * cxb) : 0;
   tb->total = off;
   return ELFPIE_OK;
 }
@@ -309,6 +320,29 @@ struct Ops {
     else k_led<T, N, false, false><<<K, NT, 0, s>>>(a);
   }
 
+  // n_lo = 256: rows (inverse) -> column strips -> rows (forward), through HBM scratch.
+  static elfpie_status led_big(elfpie_plan* pl, const LedArgs& a, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) {
+      const Tables& tb = pl->tb;
+      using Sh = BigLed<256>;
+      C* A = pl->at<C>(tb.o_bigA);
+      C* B = pl->at<C>(tb.o_bigB);
+      const int nband = tb.y_max - tb.y_min + 1;
+      const dim3 rows((nband + Sh::RB - 1) / Sh::RB, tb.K), cols(256 / Sh::W, tb.K);
+      const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
+      if (!(a.mode & LED_STORED)) k_big_rows_inv<T, 256><<<rows, Sh::RNT, 0, s>>>(a, A);
+      if (scaled) k_big_cols<T, 256, true><<<cols, Sh::CNT, 0, s>>>(a, A, B);
+      else k_big_cols<T, 256, false><<<cols, Sh::CNT, 0, s>>>(a, A, B);
+      if (a.mode & LED_GRAD) k_big_rows_fwd<T, 256><<<rows, Sh::RNT, 0, s>>>(a, B);
+      LAUNCH_CHECK(pl, "k_big");
+      return ELFPIE_OK;
+    } else {
+      (void)a;
+      (void)s;
+      return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_lo = 256 needs F32");
+    }
+  }
+
   static elfpie_status led(elfpie_plan* pl, int mode, const void* psi, const void* P, const void* meas,
                            void* fields, void* intens, hipStream_t s, int64_t* t_bump = nullptr) {
     const Tables& tb = pl->tb;
@@ -341,6 +375,7 @@ struct Ops {
     a.fidelity = pl->prob.fidelity;
     a.fid_gamma = pl->prob.fid_gamma;
     a.norm = pl->prob.norm;
+    if (tb.big) return led_big(pl, a, s);
     switch (tb.n_lo) {
       case 32: launch_led<32>(a, tb.K, s); break;
       case 64: launch_led<64>(a, tb.K, s); break;
@@ -544,7 +579,7 @@ struct Ops {
     const Tables& tb = pl->tb;
     FinArgs a{};
     a.fid_partial = pl->at<double>(tb.o_fid);
-    a.K = tb.nimg;
+    a.K = tb.nfid;
     a.hess_partial = pl->at<double>(tb.o_hess);
     a.ntiles = tb.nhp;
     a.alpha = pl->prob.alpha;
@@ -694,6 +729,18 @@ struct Ops {
     const int* xlo = pl->at<int>(tb.o_xlo);
     const int* xhi = pl->at<int>(tb.o_xhi);
     const C* tw = pl->at<C>(tb.o_twlo);
+    if (tb.big) {
+      if constexpr (sizeof(T) == 4) {
+        const int nb = (tb.n_lo * tb.n_lo + 255) / 256;
+        C* work = pl->at<C>(tb.o_T1);
+        k_init_big_prep<T><<<nb, 256, 0, s>>>(mc, work, tb.n_lo);
+        launch_lines<256, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+        launch_lines<256, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+        k_init_big_place<T><<<nb, 256, 0, s>>>(work, psi, y0, x0, tb.n_hi, tb.n_lo, sc, xlo, xhi);
+        LAUNCH_CHECK(pl, "k_init_big");
+        return ELFPIE_OK;
+      }
+    }
     switch (tb.n_lo) {
       case 32: k_init_window<T, 32><<<1, LedShape<32>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;
       case 64: k_init_window<T, 64><<<1, LedShape<64>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;

@@ -248,9 +248,9 @@ def test_init_state_matches_oracle():
         assert np.allclose(host(st.delta_psi), pair.oprob.lr ** 2)
 
 
-def _config2_pair(l1_eps):
+def _config2_pair(l1_eps, config=2):
     import synth
-    case = synth.config_case(2)
+    case = synth.config_case(config)
     o = case.optics
     flags = orc.LEARN_PUPIL | orc.PUPIL_SUPPORT | orc.PUPIL_FILTER
     oprob = orc.problem_from_optics(o, case.led_k, flags=flags, l1_eps=l1_eps)
@@ -353,3 +353,74 @@ def test_multiplexed_full_tile_gradient_matches_oracle():
     print(f"mux=2 n_lo=128: g_psi {eg:.2e} g_P {egp:.2e}")
     assert eg < TOL[True]["grad"] and egp < TOL[True]["grad"]
     assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < TOL[True]["loss"])
+
+
+
+# --- the 256^2 tile (per-LED branch through HBM scratch) ---
+
+BIG_CASES = [(2, orc.FID_INTENSITY, orc.NORM_ANISO, 0.5), (4, orc.FID_AMPLITUDE, orc.NORM_ISO, 0.5),
+             (2, orc.FID_GAMMA, orc.NORM_ANISO, 0.375)]
+
+
+@pytest.mark.parametrize("up,fidelity,norm,gamma", BIG_CASES)
+def test_large_tile_matches_oracle(up, fidelity, norm, gamma):
+    """n_lo = 256 (FP32): forward fields, images and loss, gradients, stored fields, one step."""
+    pair = make_pair(256, up, 3, f32=True, fidelity=fidelity, norm=norm, fid_gamma=gamma)
+    plan = make_plan(pair, True)
+    psi, P, meas = dev(pair.psi, True), dev(pair.P, True), dev(pair.meas, True)
+    out = plan.forward(psi, P, meas, fields=True, intens=True, loss=True)
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    ef = rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob))
+    ei = rel_l2(host(out["intens"]), orc.intensities(pair.psi, pair.P, pair.oprob))
+    el = np.abs(host(out["loss4"]) - rl4) / np.abs(rl4)
+    l4, g, gP = plan.grad(psi, P, meas)
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    _, g2, gP2 = plan.grad(psi, P, meas, fields=out["fields"])
+    st = gpu_state(plan, pair, True)
+    plan.step(st, meas)
+    torch.cuda.synchronize()
+    ref, _ = orc.step(pair.state, pair.meas, pair.oprob)
+    es = rel_l2(host(st.psi), ref.psi)
+    print(f"n_lo=256 up={up} fid={fidelity}: fields {ef:.2e} intens {ei:.2e} g_psi {eg:.2e} g_P {egp:.2e} "
+          f"step {es:.2e}")
+    assert ef < 1e-5 and ei < 1e-5 and np.all(el < 1e-5)
+    assert eg < 1e-4 and egp < 1e-4
+    assert torch.equal(g, g2) and torch.equal(gP, gP2)
+    assert es < 1e-5 and rel_l2(host(st.P), ref.P) < 1e-5
+
+
+def test_large_tile_init_state_matches_oracle():
+    pair = make_pair(256, 4, 3, f32=True, warm_steps=0)
+    plan = make_plan(pair, True)
+    st = plan.init_state(dev(pair.meas, True))
+    ref = orc.init_state(pair.meas, pair.oprob)
+    assert rel_l2(host(st.psi), ref.psi) < 1e-6
+    assert np.array_equal(host(st.P), ref.P)
+
+
+def test_config5_full_size_step():
+    """1024^2 high-res, K = 225, 256^2 low-res, FP32, noise-free with LED jitter: one step
+    from an identical state, every element."""
+    pair = _config2_pair(1e-3, config=5)
+    plan = make_plan(pair, True)
+    assert (plan.K, plan.n_lo, plan.n_hi) == (225, 256, 1024)
+    st = gpu_state(plan, pair, True)
+    hist = plan.run(st, dev(pair.meas, True), 1)
+    torch.cuda.synchronize()
+    ref, rl4 = orc.step(pair.state, pair.meas, pair.oprob)
+    e_psi, e_P = rel_l2(host(st.psi), ref.psi), rel_l2(host(st.P), ref.P)
+    el = np.abs(host(hist)[0] - rl4) / np.abs(rl4)
+    print(f"config5: psi {e_psi:.2e} P {e_P:.2e} loss {el}")
+    assert e_psi < 1e-5 and e_P < 1e-5
+    assert np.all(el < 1e-5)
+
+
+def test_large_tile_forward_without_measurements():
+    """The forward model alone (no stack given) at n_lo = 256: images and fields only.
+    Regression: the column kernel once read the stack in this mode."""
+    pair = make_pair(256, 2, 3, f32=True, warm_steps=0)
+    plan = make_plan(pair, True)
+    out = plan.forward(dev(pair.psi, True), dev(pair.P, True), fields=True, intens=True)
+    torch.cuda.synchronize()
+    assert rel_l2(host(out["intens"]), orc.intensities(pair.psi, pair.P, pair.oprob)) < 1e-5
+    assert rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob)) < 1e-5
