@@ -135,7 +135,7 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
       const T dxm = (x > 0) ? e - E(l - 1, y) : T(0);
       const T dym = (y > 0) ? e - E(l, y - 1) : T(0);
       q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
-      lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+      lsum += double(rho(dx0, eps) + rho(dy0, eps));
     } else {
       const T s0 = dx0 * dx0 + dy0 * dy0;
       q = -(dx0 + dy0) * inv_norm(s0, eps);
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
         const T gx = (x < N - 1) ? E(l + 1, y - 1) - eu : T(0);
         q += gy * inv_norm(gx * gx + gy * gy, eps);
       }
-      lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+      lsum += eps > T(0) ? double(sqrt_t(s0 + eps * eps) - eps) : double(sqrt_t(s0));
     }
     buf[l * PITCH + y] = fid_wirtinger<SCALED>(a.fidelity, buf[l * PITCH + y], q, gam);
   }

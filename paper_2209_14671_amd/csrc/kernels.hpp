@@ -36,14 +36,26 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* NT/64 *
   return s;  // valid in thread 0
 }
 
+// sqrt(x), 1 / sqrt(x) and 1 / x: the hardware instructions (about 1 ulp) in FP32,
+// correctly rounded in FP64.
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+
 // L1 term rho(d) = sqrt(d^2 + eps^2) - eps (eps > 0) or |d| and its derivative.
+// Per pixel these are a multiply-add and one reciprocal square root in FP32 (no IEEE
+// division or square-root expansion); the exact sign of eps = 0 is kept.
 template <class T>
 __device__ __forceinline__ T rho(T d, T eps) {
-  return eps > T(0) ? sqrt(d * d + eps * eps) - eps : fabs(d);
+  if (eps > T(0)) return sqrt_t(d * d + eps * eps) - eps;
+  return fabs(d);
 }
 template <class T>
 __device__ __forceinline__ T omega(T d, T eps) {
-  if (eps > T(0)) return d / sqrt(d * d + eps * eps);
+  if (eps > T(0)) return d * rsqrt_t(d * d + eps * eps);
   return T((d > T(0)) - (d < T(0)));
 }
 // 1 / ||c|| for the isotropic normaliser (0 at the origin when eps = 0).
@@ -59,7 +71,7 @@ __device__ __forceinline__ double log1p_t(double x) { return log1p(x); }
 template <bool SCALED, class T>
 __device__ __forceinline__ T fid_residual(int fid, T i2, T m, T gam) {
   const T mp = m > T(0) ? m : T(0);
-  if (fid == 0) return sqrt(i2) - sqrt(mp);
+  if (fid == 0) return sqrt_t(i2) - sqrt_t(mp);
   if constexpr (SCALED) {
     if (fid == 2) return pow_t(i2, gam) - pow_t(mp, gam);
     if (fid == 3) return log1p_t(i2) - log1p_t(mp);
@@ -71,10 +83,7 @@ __device__ __forceinline__ T fid_residual(int fid, T i2, T m, T gam) {
 template <bool SCALED, class T>
 __device__ __forceinline__ cx<T> fid_wirtinger(int fid, cx<T> ov, T q, T gam) {
   const T i2 = norm2(ov);
-  if (fid == 0) {
-    const T am = sqrt(i2);
-    return am > T(0) ? scale(ov, q / (T(2) * am)) : czero<T>();
-  }
+  if (fid == 0) return i2 > T(0) ? scale(ov, T(0.5) * q * rsqrt_t(i2)) : czero<T>();
   if constexpr (SCALED) {
     if (fid == 2) return i2 > T(0) ? scale(ov, q * gam * pow_t(i2, gam - T(1))) : czero<T>();
     if (fid == 3) return scale(ov, q / (T(1) + i2));
@@ -84,8 +93,8 @@ __device__ __forceinline__ cx<T> fid_wirtinger(int fid, cx<T> ov, T q, T gam) {
 
 template <class T>
 __device__ __forceinline__ T inv_norm(T s2, T eps) {
-  if (eps > T(0)) return T(1) / sqrt(s2 + eps * eps);
-  return s2 > T(0) ? T(1) / sqrt(s2) : T(0);
+  if (eps > T(0)) return rsqrt_t(s2 + eps * eps);
+  return s2 > T(0) ? rsqrt_t(s2) : T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
         const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
         q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
-        lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+        lsum += double(rho(dx0, eps) + rho(dy0, eps));
       } else {
         const T s0 = dx0 * dx0 + dy0 * dy0;
         const T inv0 = inv_norm(s0, eps);
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
           const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
           q += gy * inv_norm(gx * gx + gy * gy, eps);
         }
-        lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+        lsum += eps > T(0) ? double(sqrt_t(s0 + eps * eps) - eps) : double(sqrt_t(s0));
       }
       o[i][r] = fid_wirtinger<SCALED>(a.fidelity, o[i][r], q, gam);
     }
@@ -346,7 +355,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 // f = q g'(S) with S the image's summed intensity (g'(0) taken as 0 for the powers).
 template <bool SCALED, class T>
 __device__ __forceinline__ T fid_slope(int fid, T S, T q, T gam) {
-  if (fid == 0) return S > T(0) ? q / (T(2) * sqrt(S)) : T(0);
+  if (fid == 0) return S > T(0) ? T(0.5) * q * rsqrt_t(S) : T(0);
   if constexpr (SCALED) {
     if (fid == 2) return S > T(0) ? q * gam * pow_t(S, gam - T(1)) : T(0);
     if (fid == 3) return q / (T(1) + S);
@@ -500,7 +509,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
         const T dxm = (x > 0) ? e - E(y, x - 1) : T(0);
         const T dym = (y > 0) ? e - E(y - 1, x) : T(0);
         q = omega(dxm, eps) - omega(dx0, eps) + omega(dym, eps) - omega(dy0, eps);
-        lsum += double(rho(dx0, eps)) + double(rho(dy0, eps));
+        lsum += double(rho(dx0, eps) + rho(dy0, eps));
       } else {
         const T s0 = dx0 * dx0 + dy0 * dy0;
         q = -(dx0 + dy0) * inv_norm(s0, eps);
@@ -516,7 +525,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
           const T gx = (x < N - 1) ? E(y - 1, x + 1) - eu : T(0);
           q += gy * inv_norm(gx * gx + gy * gy, eps);
         }
-        lsum += eps > T(0) ? double(sqrt(s0 + eps * eps) - eps) : double(sqrt(s0));
+        lsum += eps > T(0) ? double(sqrt_t(s0 + eps * eps) - eps) : double(sqrt_t(s0));
       }
       S[i][r] = fid_slope<SCALED>(a.fidelity, S[i][r], q, gam);  // S now holds f
     }
@@ -748,7 +757,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   for (int p = tid; p < NL * N; p += NT) {
     const int l = p / N, y = p % N, c = c0 - 2 + l;
     const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
-    sa[p] = sqrt(norm2(O));
+    sa[p] = sqrt_t(norm2(O));
     sp[p] = atan2(O.y, O.x);
   }
   __syncthreads();
@@ -791,7 +800,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
             lv = double(rho(hxx, eps)) + double(rho(hyy, eps)) + double(rho(hxy, eps));
           } else {
             const T s2 = hxx * hxx + hyy * hyy + hxy * hxy;
-            lv = eps > T(0) ? double(sqrt(s2 + eps * eps) - eps) : double(sqrt(s2));
+            lv = eps > T(0) ? double(sqrt_t(s2 + eps * eps) - eps) : double(sqrt_t(s2));
           }
           if (f == 0) la += lv;
           else lp += lv;
@@ -816,11 +825,10 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
         const T sgn = ((c + y) & 1) ? -inv_n : inv_n;
         const cx<T> O = scale(buf[l * PITCH + y], sgn);
         const T a2 = norm2(O);
-        const T am = sqrt(a2);
         cx<T> G = czero<T>();
-        if (am > T(0)) G = scale(O, T(a.alpha) * q[0] / (T(2) * am));
+        if (a2 > T(0)) G = scale(O, T(0.5) * T(a.alpha) * q[0] * rsqrt_t(a2));
         const T den = a2 + T(a.eta_h);
-        if (den > T(0)) G = G + scale(mul_i(O), T(a.beta) * q[1] / (T(2) * den));
+        if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(a.beta) * q[1] * rcp_t(den));
         buf[l * PITCH + y] = scale(G, sgn);
       }
     }
@@ -885,7 +893,7 @@ __global__ __launch_bounds__(256) void k_hessian(HessArgs a) {
     T am = T(0), ph = T(0);
     if (gy >= 0 && gy < n && gx >= 0 && gx < n) {
       cx<T> O = scale(Ot[(size_t)gy * n + gx], ((gx + gy) & 1) ? -inv_n : inv_n);
-      am = sqrt(norm2(O));
+      am = sqrt_t(norm2(O));
       ph = atan2(O.y, O.x);
     }
     sa[ly][lx] = am;
@@ -922,7 +930,7 @@ __global__ __launch_bounds__(256) void k_hessian(HessArgs a) {
         wxx = hxx * inv;
         wyy = hyy * inv;
         wxy = hxy * inv;
-        l = eps > T(0) ? double(sqrt(s2 + eps * eps) - eps) : double(sqrt(s2));
+        l = eps > T(0) ? double(sqrt_t(s2 + eps * eps) - eps) : double(sqrt_t(s2));
       }
       om[3 * f + 0][ly][lx] = wxx;
       om[3 * f + 1][ly][lx] = wyy;
@@ -950,7 +958,7 @@ __global__ __launch_bounds__(256) void k_hessian(HessArgs a) {
     const T sgn = ((gx + gy) & 1) ? -inv_n : inv_n;
     const cx<T> O = scale(Ot[(size_t)gy * n + gx], sgn);
     const T a2 = norm2(O);
-    const T am = sqrt(a2);
+    const T am = sqrt_t(a2);
     cx<T> G = czero<T>();
     if (am > T(0)) G = scale(O, T(a.alpha) * q[0] / (T(2) * am));
     const T den = a2 + T(a.eta_h);
