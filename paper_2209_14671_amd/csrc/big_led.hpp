@@ -25,6 +25,9 @@ template <> struct BigLed<256> {
   static constexpr int W = 16;    // own columns per block of the column kernel
   static constexpr int CNT = 512; // threads of the column kernel
 };
+template <> struct BigLed<192> {
+  static constexpr int RB = 8, RNT = 256, W = 16, CNT = 512;
+};
 
 // A: K x nband x N (band row yb = y - y_min), unnormalised inverse DFT of the rows.
 template <class T, int N>

@@ -108,13 +108,62 @@ __host__ __device__ __forceinline__ void dft16(cx<T>* v) {
   }
 }
 
+// DFT3: X0 = a + b + c; X1, X2 = a - (b + c)/2 -/+ i s (b - c) with s = sin(2 pi / 3)
+// (signs of the i term swapped for the inverse).
+template <class T, bool INV>
+__host__ __device__ __forceinline__ void dft3(cx<T>* v) {
+  const T s3 = T(0.86602540378443864676);
+  const cx<T> t1 = v[1] + v[2];
+  const cx<T> t2 = v[0] - scale(t1, T(0.5));
+  cx<T> t3 = scale(v[1] - v[2], s3);
+  t3 = INV ? mul_i(t3) : mul_mi(t3);
+  v[0] = v[0] + t1;
+  v[1] = t2 + t3;
+  v[2] = t2 - t3;
+}
+
+// Prime-factor (Good-Thomas) DFT of length P Q with coprime P (a power of two) and
+// Q = 3: input n = (Q n1 + P n2) mod PQ, output k with k = k1 (mod P), k = k2 (mod Q);
+// W_PQ^(nk) = W_P^(n1 k1) W_Q^(n2 k2), so no twiddles between the two stages.
+template <class T, int P, bool INV>
+__host__ __device__ __forceinline__ void dft_pfa3(cx<T>* v) {
+  constexpr int N = 3 * P;
+  cx<T> a[P][3];
+#pragma unroll
+  for (int n1 = 0; n1 < P; ++n1) {
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) a[n1][n2] = v[(3 * n1 + P * n2) % N];
+    dft3<T, INV>(a[n1]);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 3; ++k2) {
+    cx<T> t[P];
+#pragma unroll
+    for (int n1 = 0; n1 < P; ++n1) t[n1] = a[n1][k2];
+    if constexpr (P == 2) dft2<T, INV>(t);
+    else if constexpr (P == 4) dft4<T, INV>(t);
+    else dft8<T, INV>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      // the k in [0, N) with k = k1 (mod P) and k = k2 (mod 3)
+      int k = k1;
+      while (k % 3 != k2) k += P;
+      v[k] = t[k1];
+    }
+  }
+}
+
 template <class T, int R, bool INV>
 __host__ __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 2) dft2<T, INV>(v);
+  else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
+  else if constexpr (R == 6) dft_pfa3<T, 2, INV>(v);
   else if constexpr (R == 8) dft8<T, INV>(v);
+  else if constexpr (R == 12) dft_pfa3<T, 4, INV>(v);
   else if constexpr (R == 16) dft16<T, INV>(v);
-  else static_assert(R == 2 || R == 4 || R == 8 || R == 16, "unsupported radix");
+  else if constexpr (R == 24) dft_pfa3<T, 8, INV>(v);
+  else static_assert(R == 2, "unsupported radix");
 }
 
 }  // namespace elfpie

@@ -87,11 +87,15 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   if (!p->led_k) return fail(ELFPIE_E_INVALID, "led_k is NULL");
   if (p->n_lo < 2 || p->upsample < 1) return fail(ELFPIE_E_INVALID, "n_lo must be >= 2 and upsample >= 1");
   const bool f32 = p->precision == ELFPIE_F32;
-  if (!is_pow2(p->n_lo) || p->n_lo < 32 || p->n_lo > (f32 ? 256 : 64))
-    return fail(ELFPIE_E_UNSUPPORTED, f32 ? "n_lo must be 32, 64, 128 or 256 in F32" : "n_lo must be 32 or 64 in F64");
+  const int nl = p->n_lo;
+  const bool lo_ok = f32 ? (nl == 32 || nl == 64 || nl == 96 || nl == 128 || nl == 192 || nl == 256)
+                         : (nl == 32 || nl == 64);
+  if (!lo_ok)
+    return fail(ELFPIE_E_UNSUPPORTED, f32 ? "n_lo must be 32, 64, 96, 128, 192 or 256 in F32"
+                                          : "n_lo must be 32 or 64 in F64");
   const long long nh = (long long)p->n_lo * p->upsample;
-  if (!is_pow2((int)std::min<long long>(nh, 1 << 30)) || nh < 128 || nh > 1024)
-    return fail(ELFPIE_E_UNSUPPORTED, "n_hi = n_lo * upsample must be 128, 256, 512 or 1024");
+  if (!(nh == 128 || nh == 256 || nh == 384 || nh == 512 || nh == 768 || nh == 1024))
+    return fail(ELFPIE_E_UNSUPPORTED, "n_hi = n_lo * upsample must be 128, 256, 384, 512, 768 or 1024");
   auto finite_pos = [](double v) { return std::isfinite(v) && v > 0; };
   if (!finite_pos(p->wavelength_um) || !finite_pos(p->na) || !finite_pos(p->dx_lo_um))
     return fail(ELFPIE_E_INVALID, "wavelength, NA and pixel size must be finite and > 0");
@@ -114,7 +118,7 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
     return fail(ELFPIE_E_INVALID, "optimizer must be one of ELFPIE_OPT_*");
   if (p->mux < 1 || p->mux > 64 || p->K % p->mux != 0)
     return fail(ELFPIE_E_INVALID, "mux must lie in 1..64 and divide K");
-  if (p->n_lo == 256 && p->mux != 1)
+  if (p->n_lo > 128 && p->mux != 1)
     return fail(ELFPIE_E_UNSUPPORTED, "multiplexed illumination needs n_lo <= 128");
 
   tb->n_lo = p->n_lo;
@@ -122,8 +126,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->K = p->K;
   tb->mux = p->mux;
   tb->nimg = p->K / p->mux;
-  tb->big = p->n_lo == 256;
-  tb->nfid = tb->big ? p->K * (256 / BigLed<256>::W) : tb->nimg;
+  tb->big = p->n_lo > 128;  // 192 and 256: the per-LED branch through HBM scratch
+  tb->nfid = tb->big ? p->K * (p->n_lo / BigLed<256>::W) : tb->nimg;
   tb->prec = p->precision;
   tb->elem = f32 ? 4 : 8;
   const int n = tb->n_lo;
@@ -320,26 +324,32 @@ struct Ops {
     else k_led<T, N, false, false><<<K, NT, 0, s>>>(a);
   }
 
-  // n_lo = 256: rows (inverse) -> column strips -> rows (forward), through HBM scratch.
+  // n_lo = 192, 256: rows (inverse) -> column strips -> rows (forward), through HBM scratch.
+  template <int N>
+  static void launch_big(const Tables& tb, const LedArgs& a, C* A, C* B, hipStream_t s) {
+    using Sh = BigLed<N>;
+    const int nband = tb.y_max - tb.y_min + 1;
+    const dim3 rows((nband + Sh::RB - 1) / Sh::RB, tb.K), cols(N / Sh::W, tb.K);
+    const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
+    if (!(a.mode & LED_STORED)) k_big_rows_inv<T, N><<<rows, Sh::RNT, 0, s>>>(a, A);
+    if (scaled) k_big_cols<T, N, true><<<cols, Sh::CNT, 0, s>>>(a, A, B);
+    else k_big_cols<T, N, false><<<cols, Sh::CNT, 0, s>>>(a, A, B);
+    if (a.mode & LED_GRAD) k_big_rows_fwd<T, N><<<rows, Sh::RNT, 0, s>>>(a, B);
+  }
+
   static elfpie_status led_big(elfpie_plan* pl, const LedArgs& a, hipStream_t s) {
     if constexpr (sizeof(T) == 4) {
       const Tables& tb = pl->tb;
-      using Sh = BigLed<256>;
       C* A = pl->at<C>(tb.o_bigA);
       C* B = pl->at<C>(tb.o_bigB);
-      const int nband = tb.y_max - tb.y_min + 1;
-      const dim3 rows((nband + Sh::RB - 1) / Sh::RB, tb.K), cols(256 / Sh::W, tb.K);
-      const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
-      if (!(a.mode & LED_STORED)) k_big_rows_inv<T, 256><<<rows, Sh::RNT, 0, s>>>(a, A);
-      if (scaled) k_big_cols<T, 256, true><<<cols, Sh::CNT, 0, s>>>(a, A, B);
-      else k_big_cols<T, 256, false><<<cols, Sh::CNT, 0, s>>>(a, A, B);
-      if (a.mode & LED_GRAD) k_big_rows_fwd<T, 256><<<rows, Sh::RNT, 0, s>>>(a, B);
+      if (tb.n_lo == 192) launch_big<192>(tb, a, A, B, s);
+      else launch_big<256>(tb, a, A, B, s);
       LAUNCH_CHECK(pl, "k_big");
       return ELFPIE_OK;
     } else {
       (void)a;
       (void)s;
-      return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_lo = 256 needs F32");
+      return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_lo above 128 needs F32");
     }
   }
 
@@ -379,6 +389,12 @@ struct Ops {
     switch (tb.n_lo) {
       case 32: launch_led<32>(a, tb.K, s); break;
       case 64: launch_led<64>(a, tb.K, s); break;
+      case 96:
+        if constexpr (sizeof(T) == 4) {
+          launch_led<96>(a, tb.K, s);
+          break;
+        }
+        [[fallthrough]];
       case 128:
         if constexpr (sizeof(T) == 4) {
           launch_led<128>(a, tb.K, s);
@@ -414,7 +430,9 @@ struct Ops {
     switch (tb.n_hi) {
       case 128: launch_lines<128, INV, COLS>(i, o, tw, tail, s); break;
       case 256: launch_lines<256, INV, COLS>(i, o, tw, tail, s); break;
+      case 384: launch_lines<384, INV, COLS>(i, o, tw, tail, s); break;
       case 512: launch_lines<512, INV, COLS>(i, o, tw, tail, s); break;
+      case 768: launch_lines<768, INV, COLS>(i, o, tw, tail, s); break;
       case 1024: launch_lines<1024, INV, COLS>(i, o, tw, tail, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
@@ -486,7 +504,9 @@ struct Ops {
     switch (tb.n_hi) {
       case 128: launch_strip<128>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
       case 256: launch_strip<256>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 384: launch_strip<384>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
       case 512: launch_strip<512>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 768: launch_strip<768>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
       case 1024: launch_strip<1024>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
@@ -734,8 +754,13 @@ struct Ops {
         const int nb = (tb.n_lo * tb.n_lo + 255) / 256;
         C* work = pl->at<C>(tb.o_T1);
         k_init_big_prep<T><<<nb, 256, 0, s>>>(mc, work, tb.n_lo);
-        launch_lines<256, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
-        launch_lines<256, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+        if (tb.n_lo == 192) {
+          launch_lines<192, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+          launch_lines<192, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+        } else {
+          launch_lines<256, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+          launch_lines<256, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+        }
         k_init_big_place<T><<<nb, 256, 0, s>>>(work, psi, y0, x0, tb.n_hi, tb.n_lo, sc, xlo, xhi);
         LAUNCH_CHECK(pl, "k_init_big");
         return ELFPIE_OK;
@@ -744,6 +769,12 @@ struct Ops {
     switch (tb.n_lo) {
       case 32: k_init_window<T, 32><<<1, LedShape<32>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;
       case 64: k_init_window<T, 64><<<1, LedShape<64>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw); break;
+      case 96:
+        if constexpr (sizeof(T) == 4) {
+          k_init_window<T, 96><<<1, LedShape<96>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw);
+          break;
+        }
+        [[fallthrough]];
       case 128:
         if constexpr (sizeof(T) == 4) {
           k_init_window<T, 128><<<1, LedShape<128>::NT, 0, s>>>(mc, psi, y0, x0, tb.n_hi, sc, xlo, xhi, tw);

@@ -101,8 +101,15 @@ __device__ __forceinline__ T inv_norm(T s2, T eps) {
 // Per-LED fused kernel: one workgroup per LED, the n_lo x n_lo tile in LDS.
 // ---------------------------------------------------------------------------
 
+// Loads kept in flight per batch of a gather of ppt pixels per thread: the largest of
+// 8, 6, 4, 3, 2, 1 that divides ppt, so the batches cover exactly ppt pixels.
+constexpr int gather_batch(int ppt) {
+  return ppt % 8 == 0 ? 8 : ppt % 6 == 0 ? 6 : ppt % 4 == 0 ? 4 : ppt % 3 == 0 ? 3 : ppt % 2 == 0 ? 2 : 1;
+}
+
 template <int N> struct LedShape;
 template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 8, R2 = 4; };
+template <> struct LedShape<96> { static constexpr int NT = 512, R1 = 16, R2 = 6; };
 template <> struct LedShape<64> { static constexpr int NT = 256, R1 = 8, R2 = 8; };
 #ifndef ELFPIE_LED128_NT
 #define ELFPIE_LED128_NT 1024
@@ -135,7 +142,8 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   constexpr int MB2 = ceil_div(N * (N / R2), NT);
   static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
   constexpr int PPT = N * N / NT;        // pixels per thread in the gather
-  constexpr int GB = PPT < 8 ? PPT : 8;  // loads kept in flight per batch
+  constexpr int GB = gather_batch(PPT);  // loads kept in flight per batch
+  static_assert(PPT * NT == N * N && PPT % GB == 0, "the gather covers the tile exactly");
   // row passes (transform stride PITCH) and column passes (element stride PITCH)
   using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
   using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1>;
@@ -380,7 +388,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
   constexpr int MB2 = ceil_div(N * (N / R2), NT);
   static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
   constexpr int PPT = N * N / NT;
-  constexpr int GB = PPT < 8 ? PPT : 8;
+  constexpr int GB = gather_batch(PPT);
   using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
   using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1>;
   using P1iC = StockhamPass<T, N, R1, 1, true, NT, MB1, 1, PITCH, N>;
@@ -594,6 +602,9 @@ template <> struct BigShape<512, true> {
   static constexpr int RPB = ELFPIE_COLS512, NT = RPB * 64, R1 = 8, R2 = 8, R3 = 8;
 };
 template <bool C> struct BigShape<1024, C> { static constexpr int NT = 128, RPB = 2, R1 = 16, R2 = 8, R3 = 8; };
+template <bool C> struct BigShape<192, C> { static constexpr int NT = 128, RPB = 8, R1 = 16, R2 = 12, R3 = 1; };
+template <bool C> struct BigShape<384, C> { static constexpr int NT = 128, RPB = 2, R1 = 8, R2 = 8, R3 = 6; };
+template <bool C> struct BigShape<768, C> { static constexpr int NT = 128, RPB = 2, R1 = 16, R2 = 8, R3 = 6; };
 
 // All passes of an unnormalised DFT of the RPB lines held in buf (line m at
 // m * (N + 1)); the outputs of the last pass go to emit(m, e, value).
@@ -691,6 +702,9 @@ template <> struct LineRadix<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1
 template <> struct LineRadix<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
 template <> struct LineRadix<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
 template <> struct LineRadix<1024> { static constexpr int R1 = 16, R2 = 8, R3 = 8; };
+template <> struct LineRadix<192> { static constexpr int R1 = 16, R2 = 12, R3 = 1; };
+template <> struct LineRadix<384> { static constexpr int R1 = 8, R2 = 8, R3 = 6; };
+template <> struct LineRadix<768> { static constexpr int R1 = 16, R2 = 8, R3 = 6; };
 
 template <class T, int N, bool INV, int NT, int NL>
 __device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, int tid) {
@@ -721,7 +735,10 @@ __device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, 
 #define ELFPIE_STRIP_CH 512   // rows per Hessian chunk
 #endif
 template <int N> struct StripShape {
-  static constexpr int W = ELFPIE_STRIP_W, NT = ELFPIE_STRIP_NT, CH = ELFPIE_STRIP_CH < N ? ELFPIE_STRIP_CH : N;
+  // rows per chunk: the configured size when it divides N, else half of N (768 -> 384)
+  static constexpr int W = ELFPIE_STRIP_W, NT = ELFPIE_STRIP_NT,
+                       CH = ELFPIE_STRIP_CH >= N ? N : (N % ELFPIE_STRIP_CH == 0 ? ELFPIE_STRIP_CH : N / 2);
+  static_assert(N % CH == 0, "whole chunks");
 };
 
 template <class T, int N>

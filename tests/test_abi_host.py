@@ -98,7 +98,7 @@ def test_workspace_size_accounts_for_every_buffer(lib):
     (dict(n_lo=512), 3),                       # beyond the largest tile (256^2)
     (dict(n_lo=256, precision=0), 3),          # the 256^2 tile runs in F32 only
     (dict(n_lo=256, led_k=np.zeros((2, 2)), mux=2), 3),  # no multiplexing at 256^2
-    (dict(n_lo=48), 3),                        # not a power of two
+    (dict(n_lo=48), 3),                        # not a supported size (3 x 16)
     (dict(precision=0, n_lo=128), 3),          # F64 tile of 128^2 does not fit LDS
     (dict(upsample=64), 3),                    # n_hi beyond 1024
     (dict(precision=7), 3),

@@ -424,3 +424,31 @@ def test_large_tile_forward_without_measurements():
     torch.cuda.synchronize()
     assert rel_l2(host(out["intens"]), orc.intensities(pair.psi, pair.P, pair.oprob)) < 1e-5
     assert rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob)) < 1e-5
+
+
+# --- sizes with a factor 3 (radix-3 / 6 / 12 passes): 96 and 192 low-res, 384 and 768 high-res ---
+
+@pytest.mark.parametrize("n_lo,up,grid", [(96, 4, 5), (192, 2, 3), (192, 4, 3)])
+def test_radix3_sizes_match_oracle(n_lo, up, grid):
+    pair = make_pair(n_lo, up, grid, f32=True)
+    plan = make_plan(pair, True)
+    assert (plan.n_lo, plan.n_hi) == (n_lo, n_lo * up)
+    psi, P, meas = dev(pair.psi, True), dev(pair.P, True), dev(pair.meas, True)
+    out = plan.forward(psi, P, meas, fields=True, intens=True, loss=True)
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    ef = rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob))
+    el = np.abs(host(out["loss4"]) - rl4) / np.abs(rl4)
+    l4, g, gP = plan.grad(psi, P, meas)
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    st = gpu_state(plan, pair, True)
+    plan.step(st, meas)
+    init = plan.init_state(meas)
+    torch.cuda.synchronize()
+    ref, _ = orc.step(pair.state, pair.meas, pair.oprob)
+    es = rel_l2(host(st.psi), ref.psi)
+    ei = rel_l2(host(init.psi), orc.init_state(pair.meas, pair.oprob).psi)
+    print(f"n_lo={n_lo} n_hi={n_lo * up}: fields {ef:.2e} g_psi {eg:.2e} g_P {egp:.2e} step {es:.2e} init {ei:.2e}")
+    assert ef < 1e-5 and np.all(el < 1e-5)
+    assert eg < 1e-4 and egp < 1e-4
+    assert es < 1e-5 and rel_l2(host(st.P), ref.P) < 1e-5
+    assert ei < 1e-6
