@@ -60,10 +60,12 @@ WORKLOADS = {
     1: ("f64", "config 1, FP64: 128x128 high-res, 5x5 LEDs (K=25), 32x32 low-res, circular pupil, noise-free"),
     2: ("f32", "single FOV, FP32: 512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, "
                "Zernike pupil, noise + salt-and-pepper + vignetting + LED jitter"),
+    3: ("f32", "64 independent FOV tiles, FP32: low-res 64/96/128/192/256 (high-res 4x), K 49/121/169/225 "
+               "(centred LED sub-grids), circular pupil, noise-free; one graph replay per iteration of all tiles"),
     4: ("f32", "FP32: 256x256 high-res, 11x11 LEDs (K=121), 64x64 low-res, circular pupil, noise-free"),
     5: ("f32", "FP32: 1024x1024 high-res, 15x15 LEDs (K=225), 256x256 low-res, circular pupil, noise-free"),
 }
-LED_KERNEL = {1: "k_led<double,32>", 2: "k_led<float,128>", 4: "k_led<float,64>",
+LED_KERNEL = {1: "k_led<double,32>", 2: "k_led<float,128>", 3: "whole batch iteration", 4: "k_led<float,64>",
               5: "k_big_rows_inv + k_big_cols + k_big_rows_fwd (256^2 tile through HBM)"}
 
 
@@ -242,6 +244,86 @@ def sweep_bench(args, dev, iters=100):
                       "rows": rows}), flush=True)
 
 
+def batch_bench(args, dev):
+    """Config 3: 64 independent tiles in one batch (parallel graph branches, branch count
+    tuned on gradient evaluations), `steps` replays timed; value = sum of K over tiles x
+    steps / seconds."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    cases = synth.config3_tiles(64)
+    flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+    log(f"building {len(cases)} tiles")
+    tiles, bytes_it, k_total = [], 0, 0
+    for case in cases:
+        o = case.optics
+        meas = simulated_stack(case, dev)
+        plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=E.F32, flags=flags), device=dev)
+        tiles.append((plan, plan.init_state(meas), meas))
+        bytes_it += byte_model(plan.K, plan.S, plan.n_lo ** 2, plan.n_hi ** 2)[1]
+        k_total += plan.K
+    batch = E.Batch(tiles, n_branches=4)
+    log("tuning the branch count")
+    tune = batch.tune(3)
+    log(f"branches {batch.n_branches} ({tune})")
+    if args.warmup:
+        batch.run(args.warmup, history=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    hist = batch.run(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / max(args.steps, 1)
+    if not all(bool(torch.isfinite(h).all()) for h in hist):
+        raise RuntimeError("non-finite loss during the timed run")
+    value = k_total * args.steps / (ms / 1e3)
+    gbs = bytes_it / (ms_step * 1e-3) / 1e9
+    log(f"{ms_step * 1e3:.1f} us per batch iteration, {value:.0f} LED-updates/s")
+    out = {"metric": "LED sub-image updates/sec (sum K x iters/s over tiles); % HBM roofline",
+           "value": round(value, 1), "unit": "LED-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": WORKLOADS[3][1], "tiles": len(tiles), "K_total": k_total,
+                      "branches": batch.n_branches, "tuning_ms": tune},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": LED_KERNEL[3],
+                        "algorithmic_bytes": bytes_it},
+           "source_hash": kernel_source_hash()}
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle, bounded sample)")
+        out["cpu_baseline"] = cpu_baseline_tiles(cases, flags)
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_tiles(cases, flags, budget_s=10.0):
+    """The oracle on the tiles in order, one iteration each, until the budget is spent;
+    the rate counts the iteration time only (simulation and set-up excluded)."""
+    import oracle as orc
+    n_led, done, step_wall, step_cpu = 0, 0, 0.0, 0.0
+    t0 = time.perf_counter()
+    for case in cases:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        o = case.optics
+        sim = orc.problem_from_optics(o, case.led_k_true)
+        meas = orc.intensities(orc.spectrum_from_object(case.obj), case.pupil, sim)
+        prob = orc.problem_from_optics(o, case.led_k, flags=flags)
+        st = orc.init_state(meas, prob)
+        w0, c0 = time.perf_counter(), time.process_time()
+        orc.step(st, meas, prob)
+        step_wall += time.perf_counter() - w0
+        step_cpu += time.process_time() - c0
+        n_led += prob.K
+        done += 1
+    return {"value": n_led / step_wall, "unit": "LED-updates/s", "cores": max(1, round(step_cpu / step_wall)),
+            "kind": "oracle",
+            "sample": f"one oracle iteration on each of the first {done} tiles (NumPy FP64), {step_wall:.1f} s"}
+
+
 def cpu_baseline(case, flags, budget_s=10.0, max_iter=30):
     """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
     import oracle as orc
@@ -306,6 +388,9 @@ def main():
         return
     if args.workload == "sweep":
         sweep_bench(args, dev)
+        return
+    if args.config == 3:
+        batch_bench(args, dev)
         return
     case = synth.config_case(args.config)
     o = case.optics

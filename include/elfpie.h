@@ -231,6 +231,41 @@ elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, 
                                   int32_t n_rep, float *ms_out, void *stream);
 
 /* Text of the last error on `plan` (or of the last plan-less call when plan is NULL). */
+/* ------------------------------------------------------------------------------------
+ * Batches of independent fields of view (tiles), each with its own plan, state and
+ * measured stack (sizes and K may differ).  One HIP graph replays one iteration of
+ * every tile; the tiles are spread over n_branches parallel graph branches (longest
+ * first on the algorithmic byte model, each to the least-loaded branch) so that small
+ * tiles share the GPU.  The batch holds the pointers it is given: plans, states and
+ * stacks must outlive it and keep their addresses.  A plan may appear in one batch
+ * entry only, and must not be used by other calls while the batch runs.
+ * ------------------------------------------------------------------------------------ */
+typedef struct elfpie_batch elfpie_batch;
+
+/* plans, states, meas: HOST arrays of n_tiles entries (copied); n_branches in 1..8
+ * (reduced to n_tiles).  Errors: E_INVALID (NULL or misaligned pointers, a repeated
+ * plan, counts out of range), E_DEVICE. */
+elfpie_status elfpie_batch_create(elfpie_plan *const *plans, const elfpie_state *states, const void *const *meas,
+                                  int32_t n_tiles, int32_t n_branches, elfpie_batch **out);
+elfpie_status elfpie_batch_destroy(elfpie_batch *batch);
+
+/* n_iter iterations of Algorithm 1 on every tile, each a replay of the batch graph on
+ * `stream`.  d_loss_hist: NULL, or a HOST array of n_tiles DEVICE pointers, each
+ * n_iter x 4 doubles as in elfpie_run (NULL entries allowed).  The graph is captured
+ * on the first call and again whenever the history pointers or the branch count
+ * change.  Results per tile equal those of elfpie_run on that tile alone. */
+elfpie_status elfpie_batch_run(elfpie_batch *batch, int32_t n_iter, double *const *d_loss_hist, void *stream);
+
+/* Branch-count tuning: for 1, 2, 4 and 8 branches (at most n_tiles) the batch graph
+ * of one gradient evaluation per tile (which leaves the states unchanged) is timed over
+ * n_rep replays; ms_out (HOST, 4 floats) receives the mean ms per replay (0 for a
+ * skipped count) and the fastest count is kept and returned in *n_branches_out.
+ * Synchronous. */
+elfpie_status elfpie_batch_tune(elfpie_batch *batch, int32_t n_rep, float *ms_out, int32_t *n_branches_out,
+                                void *stream);
+
+const char *elfpie_batch_last_error(const elfpie_batch *batch);
+
 const char *elfpie_last_error(const elfpie_plan *plan);
 
 #ifdef __cplusplus

@@ -56,6 +56,13 @@ FUNCTIONS = {
     "elfpie_init_state": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(StateC), c_void_p]),
     "elfpie_stage_timing": (c_int32, [c_void_p, ctypes.POINTER(StateC), c_void_p, c_int32,
                                       ctypes.POINTER(c_float), c_void_p]),
+    "elfpie_batch_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(StateC), ctypes.POINTER(c_void_p),
+                                      c_int32, c_int32, ctypes.POINTER(c_void_p)]),
+    "elfpie_batch_destroy": (c_int32, [c_void_p]),
+    "elfpie_batch_run": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), c_void_p]),
+    "elfpie_batch_tune": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float), ctypes.POINTER(c_int32),
+                                    c_void_p]),
+    "elfpie_batch_last_error": (ctypes.c_char_p, [c_void_p]),
     "elfpie_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 

@@ -1182,3 +1182,237 @@ const char* elfpie_last_error(const elfpie_plan* pl) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent fields of view (tiles): one HIP graph replays one iteration
+// of every tile, the tiles spread over parallel graph branches so that small tiles
+// share the GPU.  Tiles go to branches longest-first on the algorithmic byte model
+// (each to the branch with the least work so far); the branch count can be tuned by
+// timing gradient evaluations, which leave the states untouched.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMaxBranch = 8;
+
+double tile_cost(const Tables& tb) {
+  const double c = 2.0 * tb.elem, r = tb.elem;
+  const double A = (double)tb.n_hi * tb.n_hi, B = (double)tb.n_lo * tb.n_lo;
+  return tb.K * (5 * c * tb.S + r * B) + (11 * c + 16 + 2 * r) * A;
+}
+}  // namespace
+
+struct elfpie_batch {
+  std::vector<elfpie_plan*> plans;
+  std::vector<elfpie_state> states;
+  std::vector<const void*> meas;
+  std::vector<double> cost;
+  std::vector<int> branch;  // tile -> branch
+  int nbranch = 1;
+  hipStream_t streams[kMaxBranch] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxBranch] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int exec_mode = -1;  // 0: update steps, 1: gradients (tuning)
+  int exec_branches = 0;
+  std::vector<double*> exec_hist;
+  std::string err;
+};
+
+namespace {
+
+elfpie_status batch_err(elfpie_batch* b, elfpie_status s, const std::string& m) {
+  if (b) b->err = m;
+  g_last_error = m;
+  return s;
+}
+
+#define BATCH_TRY(b, expr)                                                              \
+  do {                                                                                  \
+    const hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                               \
+      return batch_err((b), ELFPIE_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_assign(elfpie_batch* b, int nb) {
+  const int n = (int)b->plans.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+  std::vector<double> load(nb, 0.0);
+  b->branch.assign(n, 0);
+  for (int t : order) {
+    int best = 0;
+    for (int j = 1; j < nb; ++j)
+      if (load[j] < load[best]) best = j;
+    b->branch[t] = best;
+    load[best] += b->cost[t];
+  }
+  b->nbranch = nb;
+}
+
+void batch_drop_graph(elfpie_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->exec_mode = -1;
+}
+
+// Capture one iteration (mode 0) or one gradient evaluation (mode 1) of every tile.
+elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
+  batch_drop_graph(b);
+  hipStream_t origin = b->streams[0];
+  BATCH_TRY(b, hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+  elfpie_status r = ELFPIE_OK;
+  hipError_t e = hipEventRecord(b->fork, origin);
+  for (int j = 1; j < b->nbranch && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->streams[j], b->fork, 0);
+  for (size_t t = 0; t < b->plans.size() && r == ELFPIE_OK && e == hipSuccess; ++t) {
+    elfpie_plan* pl = b->plans[t];
+    const elfpie_state* st = &b->states[t];
+    hipStream_t s = b->streams[b->branch[t]];
+    r = dispatch(pl, [&](auto ops) {
+      using O = decltype(ops);
+      if (mode == 0) return O::iterations(pl, st, b->meas[t], 1, hist ? hist[t] : nullptr, s);
+      return O::iteration(pl, st->psi, st->P, b->meas[t], nullptr, pl->template at<void>(pl->tb.o_G),
+                          pl->template at<void>(pl->tb.o_gP), pl->template at<double>(pl->tb.o_loss), nullptr, s);
+    });
+    if (r != ELFPIE_OK) b->err = pl->err;
+  }
+  for (int j = 1; j < b->nbranch && e == hipSuccess; ++j) {
+    e = hipEventRecord(b->join[j], b->streams[j]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->join[j], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(origin, &g);
+  if (r != ELFPIE_OK || e != hipSuccess || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (r != ELFPIE_OK) return batch_err(b, r, b->err);
+    return batch_err(b, ELFPIE_E_DEVICE, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : ec));
+  }
+  b->graph = g;
+  BATCH_TRY(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->exec_mode = mode;
+  b->exec_branches = b->nbranch;
+  b->exec_hist.assign(b->plans.size(), nullptr);
+  if (hist)
+    for (size_t t = 0; t < b->plans.size(); ++t) b->exec_hist[t] = hist[t];
+  return ELFPIE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+elfpie_status elfpie_batch_create(elfpie_plan* const* plans, const elfpie_state* states, const void* const* meas,
+                                  int32_t n_tiles, int32_t n_branches, elfpie_batch** out) {
+  if (!out) return batch_err(nullptr, ELFPIE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!plans || !states || !meas || n_tiles < 1)
+    return batch_err(nullptr, ELFPIE_E_INVALID, "plans, states and meas must be given for n_tiles >= 1");
+  if (n_branches < 1 || n_branches > kMaxBranch)
+    return batch_err(nullptr, ELFPIE_E_INVALID, "n_branches must lie in 1..8");
+  for (int t = 0; t < n_tiles; ++t) {
+    if (!plans[t]) return batch_err(nullptr, ELFPIE_E_INVALID, "a plan is NULL");
+    elfpie_status s = check_state(plans[t], &states[t]);
+    if (s == ELFPIE_OK) s = check_ptr(plans[t], meas[t], "meas", false);
+    if (s != ELFPIE_OK) return batch_err(nullptr, s, "tile " + std::to_string(t) + ": " + plans[t]->err);
+    for (int u = 0; u < t; ++u)
+      if (plans[u] == plans[t]) return batch_err(nullptr, ELFPIE_E_INVALID, "a plan appears twice in the batch");
+  }
+  auto* b = new elfpie_batch();
+  b->plans.assign(plans, plans + n_tiles);
+  b->states.assign(states, states + n_tiles);
+  b->meas.assign(meas, meas + n_tiles);
+  for (int t = 0; t < n_tiles; ++t) b->cost.push_back(tile_cost(plans[t]->tb));
+  auto fail = [&](const char* what) {
+    elfpie_batch_destroy(b);
+    return batch_err(nullptr, ELFPIE_E_DEVICE, what);
+  };
+  for (int j = 0; j < kMaxBranch; ++j) {
+    if (hipStreamCreateWithFlags(&b->streams[j], hipStreamNonBlocking) != hipSuccess) return fail("stream creation");
+    if (hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) != hipSuccess) return fail("event creation");
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail("event creation");
+  batch_assign(b, std::min<int>(n_branches, n_tiles));
+  *out = b;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_batch_destroy(elfpie_batch* b) {
+  if (!b) return ELFPIE_E_INVALID;
+  batch_drop_graph(b);
+  for (int j = 0; j < kMaxBranch; ++j) {
+    if (b->streams[j]) (void)hipStreamDestroy(b->streams[j]);
+    if (b->join[j]) (void)hipEventDestroy(b->join[j]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_batch_run(elfpie_batch* b, int32_t n_iter, double* const* d_loss_hist, void* stream) {
+  if (!b) return ELFPIE_E_INVALID;
+  if (n_iter < 0) return batch_err(b, ELFPIE_E_INVALID, "n_iter must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool same = b->exec && b->exec_mode == 0 && b->exec_branches == b->nbranch;
+  for (size_t t = 0; same && t < b->plans.size(); ++t)
+    same = b->exec_hist[t] == (d_loss_hist ? d_loss_hist[t] : nullptr);
+  // the graph is captured on the batch's own streams and launched on `stream`
+  for (elfpie_plan* pl : b->plans) {  // history slot counters and non-finite flags
+    k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_ctr), 0, 1);
+    k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_flag), 0, 1);
+  }
+  BATCH_TRY(b, hipGetLastError());
+  if (!same) {
+    const elfpie_status r = batch_capture(b, 0, d_loss_hist);
+    if (r != ELFPIE_OK) return r;
+  }
+  for (int i = 0; i < n_iter; ++i) BATCH_TRY(b, hipGraphLaunch(b->exec, s));
+  return ELFPIE_OK;
+}
+
+elfpie_status elfpie_batch_tune(elfpie_batch* b, int32_t n_rep, float* ms_out, int32_t* n_branches_out, void* stream) {
+  if (!b) return ELFPIE_E_INVALID;
+  if (n_rep < 1 || !ms_out || !n_branches_out) return batch_err(b, ELFPIE_E_INVALID, "n_rep >= 1 and outputs required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BATCH_TRY(b, hipEventCreate(&e0));
+  BATCH_TRY(b, hipEventCreate(&e1));
+  int best = 1;
+  float best_ms = 0.f;
+  elfpie_status r = ELFPIE_OK;
+  for (int j = 0; j < 4; ++j) ms_out[j] = 0.f;
+  const int cand[4] = {1, 2, 4, 8};
+  for (int c = 0; c < 4 && r == ELFPIE_OK; ++c) {
+    const int nb = cand[c];
+    if (nb > (int)b->plans.size()) break;
+    batch_assign(b, nb);
+    if ((r = batch_capture(b, 1, nullptr)) != ELFPIE_OK) break;
+    hipError_t e = hipGraphLaunch(b->exec, s);  // warm
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int i = 0; i < n_rep && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      r = batch_err(b, ELFPIE_E_DEVICE, std::string("batch tuning: ") + hipGetErrorString(e));
+      break;
+    }
+    ms_out[c] = ms / n_rep;
+    if (c == 0 || ms_out[c] < best_ms) {
+      best_ms = ms_out[c];
+      best = nb;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  batch_drop_graph(b);
+  batch_assign(b, best);
+  *n_branches_out = best;
+  return r;
+}
+
+const char* elfpie_batch_last_error(const elfpie_batch* b) { return b ? b->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

@@ -314,6 +314,63 @@ class Plan:
         return {n: float(ms[i]) for i, n in enumerate(names)}
 
 
+class Batch:
+    """Independent fields of view (tiles) run together: one replay of the batch graph is
+    one iteration of every tile, the tiles spread over parallel graph branches.
+    `tiles` is a list of (Plan, State, measured stack); all of them must stay alive and
+    in place while the batch exists (the batch keeps references)."""
+
+    def __init__(self, tiles, n_branches: int = 4):
+        self.lib = _lib.load()
+        self.tiles = list(tiles)
+        n = len(self.tiles)
+        for plan, st, meas in self.tiles:
+            plan._need(meas, plan.stack_shape, plan.rdtype, "meas")
+        self._plans = (ctypes.c_void_p * n)(*[plan.handle.value for plan, _, _ in self.tiles])
+        self._states = (_lib.StateC * n)(*[plan._state_c(st) for plan, st, _ in self.tiles])
+        self._meas = (ctypes.c_void_p * n)(*[m.data_ptr() for _, _, m in self.tiles])
+        handle = ctypes.c_void_p(0)
+        st = self.lib.elfpie_batch_create(self._plans, self._states, self._meas, n, int(n_branches),
+                                          ctypes.byref(handle))
+        self._check(st, None)
+        self.handle = handle
+        self.n_branches = min(int(n_branches), n)
+
+    def _check(self, status, handle=True):
+        if status != _lib.OK:
+            h = self.handle if handle else None
+            msg = self.lib.elfpie_batch_last_error(h)
+            raise ElfpieError(status, msg.decode() if msg else "")
+
+    def tune(self, n_rep: int = 5):
+        """Time 1, 2, 4 and 8 branches on gradient evaluations; keep the fastest.
+        Returns {branches: ms per replay}."""
+        ms = (ctypes.c_float * 4)()
+        nb = ctypes.c_int32(0)
+        self._check(self.lib.elfpie_batch_tune(self.handle, int(n_rep), ms, ctypes.byref(nb), _stream()))
+        self.n_branches = int(nb.value)
+        return {c: float(ms[i]) for i, c in enumerate((1, 2, 4, 8)) if ms[i] > 0}
+
+    def run(self, n_iter: int, history: bool = True):
+        """n_iter iterations of every tile; returns the per-tile loss histories."""
+        hist = [torch.empty((max(n_iter, 1), 4), dtype=torch.float64, device=p.device) if history else None
+                for p, _, _ in self.tiles]
+        arr = (ctypes.c_void_p * len(hist))(*[h.data_ptr() if h is not None else None for h in hist])
+        self._check(self.lib.elfpie_batch_run(self.handle, int(n_iter), arr if history else None, _stream()))
+        return [h[:n_iter] for h in hist] if history else None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.elfpie_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class ElfpieLoss(torch.autograd.Function):
     """L(psi, P) of Eq. (8) as an autograd function whose backward is the library's
     closed-form gradient (Eq. 15, 18).  With store_fields=False the backward

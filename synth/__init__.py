@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "Optics", "Degradation", "Case", "smooth_field", "make_object", "led_grid_positions",
-    "led_wavevectors", "true_pupil", "degrade", "make_case", "config_case", "centre_subgrid",
+    "led_wavevectors", "true_pupil", "degrade", "make_case", "config_case", "config3_tiles", "centre_subgrid",
 ]
 
 
@@ -202,6 +202,25 @@ _CONFIG_OPTICS = {
 }
 
 CONFIG_ITERS = {1: 50, 2: 100, 3: 100, 4: 1, 5: 100}
+
+
+# Batched-tile preset: low-res sizes and LED sub-grids drawn per tile.
+CONFIG3_SIZES = (64, 96, 128, 192, 256)
+CONFIG3_SUBGRIDS = (7, 11, 13, 15)  # K = 49, 121, 169, 225: centred blocks of the 15 x 15 array
+
+
+def config3_tiles(n_tiles: int = 64) -> list:
+    """Independent seeded tiles of the batched workload: n_lo drawn uniformly from
+    CONFIG3_SIZES (n_hi = 4 n_lo), the LEDs a centred sub-grid drawn from CONFIG3_SUBGRIDS,
+    circular pupil, noise-free, each with its own object."""
+    rng = np.random.default_rng(np.random.SeedSequence([3]))
+    sizes = rng.choice(CONFIG3_SIZES, size=n_tiles)
+    subs = rng.choice(CONFIG3_SUBGRIDS, size=n_tiles)
+    tiles = []
+    for t in range(n_tiles):
+        optics = Optics(n_lo=int(sizes[t]), upsample=4, led_grid=15)
+        tiles.append(make_case(optics, [3, t], led_subset=centre_subgrid(15, int(subs[t]))))
+    return tiles
 
 
 def config_case(config_id: int, tile_id: int = 0) -> Case:
