@@ -180,6 +180,19 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   int mm[MB2], jj[MB2];
   bool lv[MB2];
   cx<T> o[MB2][R2];
+  const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
+  const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
+  T mv[MB2][R2];
+  auto load_meas = [&]() {
+    if (need_e) {
+#pragma unroll
+      for (int i = 0; i < MB2; ++i) {
+        const int j = jj[i], x = mm[i];
+#pragma unroll
+        for (int r = 0; r < R2; ++r) mv[i][r] = meas[(size_t)(j + r * R1) * N + x];
+      }
+    }
+  };
   if constexpr (stored) {
     P2iC::coords(N, tid, mm, jj, lv);
     // o from the fields of a forward call, in the kernel's (-1)^(x+y) frame
@@ -193,24 +206,31 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         o[i][r] = ((x + y) & 1) ? cx<T>{-f.x, -f.y} : f;
       }
     }
+    load_meas();
   } else {
-    // gather X = P * window, zeros off the support.  Every address of the window is
-    // valid, so the loads are unconditional and a batch of them is in flight at once.
+    // gather X = P * window, zeros off the support: only lanes on the support load, a
+    // batch of GB loads in flight at once.
 #pragma unroll
     for (int i0 = 0; i0 < PPT; i0 += GB) {
       cx<T> pv[GB], wv[GB];
+      bool in[GB];
 #pragma unroll
       for (int i = 0; i < GB; ++i) {
         const int p = tid + (i0 + i) * NT;
-        pv[i] = P[p];
-        wv[i] = win[(size_t)(p / N) * a.n_hi + p % N];
+        const int y = p / N, x = p % N;
+        in[i] = x >= sxlo[y] && x <= sxhi[y];
+        pv[i] = czero<T>();
+        wv[i] = czero<T>();
+        if (in[i]) {
+          pv[i] = P[p];
+          wv[i] = win[(size_t)y * a.n_hi + x];
+        }
       }
 #pragma unroll
       for (int i = 0; i < GB; ++i) {
         const int p = tid + (i0 + i) * NT;
         const int y = p / N, x = p % N;
-        const bool in = x >= sxlo[y] && x <= sxhi[y];
-        img[y * PITCH + x] = in ? pv[i] * wv[i] : czero<T>();
+        img[y * PITCH + x] = in[i] ? pv[i] * wv[i] : czero<T>();
       }
     }
     __syncthreads();
@@ -221,6 +241,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     P2iR::run(img, a.y_min, nband, twl, tid);
     P1iC::run(img, 0, N, twl, tid);
     P2iC::coords(N, tid, mm, jj, lv);
+    load_meas();  // in flight during the last pass's loads
     P2iC::load(img, 0, mm, jj, lv, twl, o);
   }
   __syncthreads();
@@ -229,18 +250,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const T osc = stored ? T(1) : sc;  // stored fields are scaled already
   const T eps = T(a.eps);
   const T gam = T(a.fid_gamma);
-  const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
-  const T* meas = static_cast<const T*>(a.meas) + (size_t)k * N * N;
   T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
-  T mv[MB2][R2];
-  if (need_e) {
-#pragma unroll
-    for (int i = 0; i < MB2; ++i) {
-      const int j = jj[i], x = mm[i];
-#pragma unroll
-      for (int r = 0; r < R2; ++r) mv[i][r] = meas[(size_t)(j + r * R1) * N + x];
-    }
-  }
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
     const int j = jj[i], x = mm[i];
