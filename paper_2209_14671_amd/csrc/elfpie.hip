@@ -31,11 +31,16 @@ constexpr bool kFusePupil = ELFPIE_FUSE_PUPIL != 0;  // pupil partial sums ride 
 #define ELFPIE_STRIP 1
 #endif
 constexpr bool kUseStrip = ELFPIE_STRIP != 0;  // column-strip fusion of the object branch
+#ifndef ELFPIE_ROW_UPDATE
+#define ELFPIE_ROW_UPDATE 1
+#endif
+constexpr bool kRowUpdate = ELFPIE_ROW_UPDATE != 0;  // update on whole rows, row transforms folded in
 
 // The tail of an iteration (pupil update, loss) waiting to be launched, either alone
 // or as extra blocks of the next iteration's first transform launch.
 struct TailReq {
   bool pupil = false;  // Eq. 19 on P (state) or the pupil gradient
+  bool fin = true;     // the loss reduction (false: already done in the update launch)
   TailArgs a{};
 };
 
@@ -43,7 +48,8 @@ struct TailReq {
 inline TailArgs shape_tail(const TailReq& r, int nt) {
   TailArgs a = r.a;
   a.pupil_blocks = r.pupil ? (a.pa.n_lo * a.pa.n_lo + nt - 1) / nt : 0;
-  a.fin_block = 1;
+  a.fin_block = r.fin ? 1 : 0;
+  a.pupil_ppb = 0;
   return a;
 }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -60,14 +66,19 @@ struct Tables {
   int kc = 0;                      // LED nearest the optical axis
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
   bool strip = false;              // object branch on column strips (k_obj_strip)
+  bool rowupd = false;             // spectrum update on whole rows (k_update_rows)
   int nhp = 0;                     // Hessian loss partial pairs written per evaluation
+  size_t hess_pairs = 0;           // pairs per Hessian partial buffer (two, by iteration parity)
+  int nseg = 0;                    // 64-column segments per spectrum row
   int nch = 0, chunk = kPupilChunk;  // pupil reduction chunks
   std::vector<int> win;            // K x 2 (y0, x0)
   std::vector<int> xlo, xhi, rowoff;
   std::vector<int> tile_ptr, tile_led;
+  std::vector<int> seg_ptr, seg_ent;  // (row, segment) -> LED runs, 4 ints per entry
   size_t elem = 0;                 // bytes of one real in the plan precision
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
+  size_t o_sptr = 0, o_sent = 0;
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
   size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0, o_bigA = 0, o_bigB = 0;
   size_t total = 0;
@@ -216,6 +227,40 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   // the fused column-strip object kernel keeps W + 4 columns, |O| and angle(O) in LDS
   tb->strip = kUseStrip && (f32 || tb->n_hi <= 256);
   tb->nhp = tb->strip ? tb->n_hi / ELFPIE_STRIP_W : ntiles;
+  tb->hess_pairs = (size_t)std::max(tb->nhp, ntiles);
+
+  // row-form update lists: per spectrum row and 64-column segment, the runs of the
+  // LED supports that meet it, in ascending LED order, with the contribution index
+  // of each pixel as base + column
+  tb->rowupd = kRowUpdate && tb->strip && (long long)tb->K * S < (1LL << 30);
+  if (tb->rowupd) {
+    tb->nseg = tb->n_hi / 64;
+    const int nreg = tb->n_hi * tb->nseg;
+    std::vector<std::vector<int>> seg(nreg);
+    for (int k = 0; k < tb->K; ++k) {
+      const int y0 = tb->win[2 * k], x0 = tb->win[2 * k + 1];
+      for (int dy = 0; dy < n; ++dy) {
+        if (tb->xlo[dy] > tb->xhi[dy]) continue;
+        const int uy = y0 + dy, xa = x0 + tb->xlo[dy], xb = x0 + tb->xhi[dy];
+        const int base = k * S + tb->rowoff[dy] - xa;
+        for (int g = xa / 64; g <= xb / 64; ++g) {
+          std::vector<int>& e = seg[uy * tb->nseg + g];
+          e.push_back(base);
+          e.push_back(std::max(xa, g * 64));
+          e.push_back(std::min(xb, g * 64 + 63));
+          e.push_back(k);
+        }
+      }
+    }
+    tb->seg_ptr.assign(nreg + 1, 0);
+    tb->seg_ent.clear();
+    for (int r = 0; r < nreg; ++r) {
+      tb->seg_ptr[r] = (int)(tb->seg_ent.size() / 4);
+      tb->seg_ent.insert(tb->seg_ent.end(), seg[r].begin(), seg[r].end());
+    }
+    tb->seg_ptr[nreg] = (int)(tb->seg_ent.size() / 4);
+    if (tb->seg_ent.empty()) tb->seg_ent.assign(4, 0);
+  }
 
   // workspace layout
   const size_t cxb = 2 * tb->elem;
@@ -231,6 +276,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_roff = take(n * sizeof(int));
   tb->o_tptr = take(tb->tile_ptr.size() * sizeof(int));
   tb->o_tled = take(tb->tile_led.size() * sizeof(int));
+  tb->o_sptr = take(tb->seg_ptr.size() * sizeof(int));
+  tb->o_sent = take(tb->seg_ent.size() * sizeof(int));
   tb->o_twlo = take(n * cxb);
   tb->o_twhi = take(tb->n_hi * cxb);
   const size_t A = (size_t)tb->n_hi * tb->n_hi;
@@ -243,7 +290,7 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_part = take((size_t)tb->nch * S * cxb);
   tb->o_Pf = take((size_t)n * n * cxb);
   tb->o_fid = take((size_t)std::max(tb->K, tb->nfid) * sizeof(double));
-  tb->o_hess = take((size_t)2 * std::max(tb->nhp, ntiles) * sizeof(double));
+  tb->o_hess = take(2 * 2 * tb->hess_pairs * sizeof(double));
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
@@ -455,12 +502,18 @@ struct Ops {
     return lines<false, false>(pl, out, out, s);
   }
 
-  static HessArgs hess_args(elfpie_plan* pl, bool grad, const void* Ot, void* Gt) {
+  // Hessian loss partials: two buffers, by iteration parity, so that an iteration's
+  // tail can reduce one while the next object branch writes the other.
+  static double* hess_partials(elfpie_plan* pl, int par) {
+    return pl->at<double>(pl->tb.o_hess) + (size_t)(par & 1) * 2 * pl->tb.hess_pairs;
+  }
+
+  static HessArgs hess_args(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, int par = 0) {
     const Tables& tb = pl->tb;
     HessArgs a{};
     a.Ot = Ot;
     a.Gt = Gt;
-    a.partial = pl->at<double>(tb.o_hess);
+    a.partial = hess_partials(pl, par);
     a.n = tb.n_hi;
     a.inv_n = 1.0 / tb.n_hi;
     a.alpha = pl->prob.alpha;
@@ -472,52 +525,87 @@ struct Ops {
     return a;
   }
 
-  static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s) {
+  static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s, int par) {
     const Tables& tb = pl->tb;
     dim3 grid(tb.n_hi / 16, tb.n_hi / 16);
-    k_hessian<T><<<grid, 256, 0, s>>>(hess_args(pl, grad, Ot, Gt));
+    k_hessian<T><<<grid, 256, 0, s>>>(hess_args(pl, grad, Ot, Gt, par));
     LAUNCH_CHECK(pl, "k_hessian");
     return ELFPIE_OK;
   }
 
+  // A pupil-only tail rides as a slice of pupil pixels in every strip block.
   template <int N>
-  static void launch_strip(const HessArgs& a, const C* T1, C* T2, const C* tw, hipStream_t s) {
-    if constexpr (sizeof(T) == 4 || N <= 256)
-      k_obj_strip<T, N><<<N / StripShape<N>::W, StripShape<N>::NT, 0, s>>>(a, T1, T2, tw);
+  static void launch_strip(const HessArgs& a, const C* T1, C* T2, const C* tw, const TailReq* tail, hipStream_t s) {
+    if constexpr (sizeof(T) == 4 || N <= 256) {
+      using Sh = StripShape<N>;
+      constexpr int nb = N / Sh::W;
+      TailArgs ta{};
+      if (tail && tail->pupil) {
+        ta = shape_tail(*tail, Sh::NT);
+        const int npx = ta.pa.n_lo * ta.pa.n_lo;
+        ta.pupil_ppb = (npx + nb - 1) / nb;
+        ta.pupil_blocks = 0;
+        ta.fin_block = 0;
+      }
+      k_obj_strip<T, N><<<nb, Sh::NT, 0, s>>>(a, T1, T2, tw, ta);
+    }
   }
 
-  // Object branch from psi: O's penalties (loss partials) and, with grad, the
-  // gradient of the Hessian terms in out (forward DFT complete).  T1 is scratch.
-  // A pending tail of the previous iteration rides in the first launch.
+  // Object branch from psi: O's penalties (loss partials, buffer par) and, with grad,
+  // the gradient of the Hessian terms in out.  T1 is scratch; with t1_ready it already
+  // holds the inverse row transforms of psi (left there by the row-form update), and
+  // the strip launch comes first.  A pending tail of the previous iteration rides in
+  // the first launch.  Without rows_fwd the forward row transforms of out are left to
+  // the row-form update.
   static elfpie_status object_branch(elfpie_plan* pl, const void* psi, bool grad, void* T1, void* out,
-                                     hipStream_t s, const TailReq* tail = nullptr) {
+                                     hipStream_t s, const TailReq* tail = nullptr, bool t1_ready = false,
+                                     bool rows_fwd = true, int par = 0) {
     const Tables& tb = pl->tb;
     elfpie_status r;
     if (!tb.strip) {
       if ((r = obj_inverse(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
-      if ((r = hessian(pl, grad, T1, out, s)) != ELFPIE_OK) return r;
+      if ((r = hessian(pl, grad, T1, out, s, par)) != ELFPIE_OK) return r;
       return grad ? obj_forward(pl, out, out, s) : ELFPIE_OK;
     }
-    if ((r = lines<true, false>(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
-    const HessArgs a = hess_args(pl, grad, T1, out);
+    if (!t1_ready && (r = lines<true, false>(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
+    const TailReq* strip_tail = t1_ready ? tail : nullptr;
+    if (strip_tail && (strip_tail->fin || (size_t)strip_tail->a.pa.n_lo * strip_tail->a.pa.n_lo >
+                                              (size_t)(tb.n_hi / ELFPIE_STRIP_W) * ELFPIE_STRIP_NT)) {
+      // only a pupil update that fits one slice per strip block rides there
+      if ((r = Ops::tail(pl, *strip_tail, s)) != ELFPIE_OK) return r;
+      strip_tail = nullptr;
+    }
+    const HessArgs a = hess_args(pl, grad, T1, out, par);
     const C* tw = pl->at<C>(tb.o_twhi);
+    C* t1 = static_cast<C*>(T1);
+    C* o = static_cast<C*>(out);
     switch (tb.n_hi) {
-      case 128: launch_strip<128>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
-      case 256: launch_strip<256>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
-      case 384: launch_strip<384>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
-      case 512: launch_strip<512>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
-      case 768: launch_strip<768>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
-      case 1024: launch_strip<1024>(a, static_cast<C*>(T1), static_cast<C*>(out), tw, s); break;
+      case 128: launch_strip<128>(a, t1, o, tw, strip_tail, s); break;
+      case 256: launch_strip<256>(a, t1, o, tw, strip_tail, s); break;
+      case 384: launch_strip<384>(a, t1, o, tw, strip_tail, s); break;
+      case 512: launch_strip<512>(a, t1, o, tw, strip_tail, s); break;
+      case 768: launch_strip<768>(a, t1, o, tw, strip_tail, s); break;
+      case 1024: launch_strip<1024>(a, t1, o, tw, strip_tail, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
     LAUNCH_CHECK(pl, "k_obj_strip");
-    return grad ? lines<false, false>(pl, out, out, s) : ELFPIE_OK;
+    return grad && rows_fwd ? lines<false, false>(pl, out, out, s) : ELFPIE_OK;
   }
 
   // LED gather + (gradient | Eq. 19 update) on 16 x 16 tiles, with the pupil partial
   // sums (and pre-filter) as trailing blocks of the launch.
+  template <int N>
+  static void launch_update_rows(const UpdArgs& a, const PupilArgs& pa, const FinArgs* fin, hipStream_t s) {
+    const FinArgs fa = fin ? *fin : FinArgs{};
+    k_update_rows<T, N><<<N / UpdRows<N>::RB + a.pupil_blocks + (fin ? 1 : 0), UpdRows<N>::NT, 0, s>>>(a, pa, fa);
+  }
+
+  // With the row form (tb.rowupd), gH is the Hessian-term gradient before its forward
+  // row transforms, and inv asks for the inverse row transforms of psi (as the launch
+  // leaves it) in T1.
   static elfpie_status update(elfpie_plan* pl, const elfpie_state* st, void* g_out, const void* gH,
-                              const void* P, bool pupil, bool prefilter, hipStream_t s) {
+                              const void* P, bool pupil, bool prefilter, hipStream_t s, bool inv = false,
+                              const void* psi = nullptr, const FinArgs* fin = nullptr) {
     const Tables& tb = pl->tb;
     UpdArgs a{};
     if (st) {
@@ -555,6 +643,27 @@ struct Ops {
       if (prefilter) pblocks += (tb.n_lo * tb.n_lo + 255) / 256;
     }
     a.pupil_blocks = pblocks;
+    if (tb.rowupd) {
+      a.tw = pl->at<void>(tb.o_twhi);
+      a.T1 = pl->at<void>(tb.o_T1);
+      a.seg_ptr = pl->at<int>(tb.o_sptr);
+      a.seg_ent = pl->at<int>(tb.o_sent);
+      a.nseg = tb.nseg;
+      a.inv = inv ? 1 : 0;
+      if (!st) a.x = const_cast<void*>(psi);  // read for the inverse transforms only
+      if (inv && !a.x) return set_err(pl, ELFPIE_E_INVALID, "row-form update without psi");
+      switch (tb.n_hi) {
+        case 128: launch_update_rows<128>(a, pa, fin, s); break;
+        case 256: launch_update_rows<256>(a, pa, fin, s); break;
+        case 384: launch_update_rows<384>(a, pa, fin, s); break;
+        case 512: launch_update_rows<512>(a, pa, fin, s); break;
+        case 768: launch_update_rows<768>(a, pa, fin, s); break;
+        case 1024: launch_update_rows<1024>(a, pa, fin, s); break;
+        default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
+      }
+      LAUNCH_CHECK(pl, "k_update_rows");
+      return ELFPIE_OK;
+    }
     if (kFusePupil) {
       k_update<T><<<a.ntiles + pblocks, 256, 0, s>>>(a, pa);
     } else {
@@ -595,12 +704,12 @@ struct Ops {
     return a;
   }
 
-  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist) {
+  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist, int par) {
     const Tables& tb = pl->tb;
     FinArgs a{};
     a.fid_partial = pl->at<double>(tb.o_fid);
     a.K = tb.nfid;
-    a.hess_partial = pl->at<double>(tb.o_hess);
+    a.hess_partial = hess_partials(pl, par);
     a.ntiles = tb.nhp;
     a.alpha = pl->prob.alpha;
     a.beta = pl->prob.beta;
@@ -614,7 +723,7 @@ struct Ops {
   // The tail of an iteration: Eq. 19 on P (st != NULL) or the pupil gradient into
   // g_out (when pupil), and the loss terms into loss4 / the history.
   static TailReq tail_req(elfpie_plan* pl, bool pupil, const void* P, const elfpie_state* st, void* g_out,
-                          double* loss4, double* hist) {
+                          double* loss4, double* hist, int par = 0) {
     TailReq r;
     r.pupil = pupil;
     PupilArgs& a = r.a.pa;
@@ -628,12 +737,13 @@ struct Ops {
       a.t = reinterpret_cast<const long long*>(st->t);
       a.step = 1;
     }
-    r.a.fin = fin_args(pl, loss4, hist);
+    r.a.fin = fin_args(pl, loss4, hist, par);
     return r;
   }
 
   static elfpie_status tail(elfpie_plan* pl, const TailReq& r, hipStream_t s) {
     const TailArgs a = shape_tail(r, 256);
+    if (a.pupil_blocks + a.fin_block == 0) return ELFPIE_OK;
     k_tail<T><<<a.pupil_blocks + a.fin_block, 256, 0, s>>>(a);
     LAUNCH_CHECK(pl, "k_tail");
     return ELFPIE_OK;
@@ -647,23 +757,35 @@ struct Ops {
   // iteration's tail is returned there instead of launched.
   // Kernels on one queue dispatch back to back; a join across queues costs more
   // than the overlap it buys (the per-LED kernel fills every CU).
+  // With the row-form update, the forward row transforms of the object branch and the
+  // inverse row transforms of the next one ride in the update launch: t1_ready says
+  // that T1 already holds the latter (the previous iteration of the same call left it),
+  // and par picks the Hessian loss partial buffer, alternating between iterations.
   static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
                                  const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
                                  hipStream_t s, const TailReq* prev = nullptr, TailReq* defer = nullptr,
-                                 const void* stored_fields = nullptr) {
+                                 const void* stored_fields = nullptr, bool t1_ready = false, int par = 0) {
     const Tables& tb = pl->tb;
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
-    if ((r = object_branch(pl, psi, true, T1, T2, s, prev)) != ELFPIE_OK) return r;
+    if ((r = object_branch(pl, psi, true, T1, T2, s, prev, t1_ready && tb.rowupd, !tb.rowupd, par)) != ELFPIE_OK)
+      return r;
     const int mode = stored_fields ? LED_GRAD | LED_STORED : LED_GRAD;
     if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr)) !=
         ELFPIE_OK)
       return r;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
-    if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s)) != ELFPIE_OK) return r;
-    const TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist);
+    // a deferred tail leaves its loss reduction to this update launch, so that only
+    // the pupil update rides in the next strip launch
+    const bool split = tb.rowupd && defer;
+    const FinArgs fa = fin_args(pl, loss4, hist, par);
+    if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s, st != nullptr, nullptr, split ? &fa : nullptr)) !=
+        ELFPIE_OK)
+      return r;
+    TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist, par);
+    if (split) mine.fin = false;
     if (defer) {
       *defer = mine;
       return ELFPIE_OK;
@@ -678,7 +800,8 @@ struct Ops {
     elfpie_status r = ELFPIE_OK;
     for (int it = 0; it < n_iter && r == ELFPIE_OK; ++it) {
       TailReq next;
-      r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, it ? &pend : nullptr, &next);
+      r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, it ? &pend : nullptr, &next,
+                    nullptr, it > 0, it & 1);
       pend = next;
     }
     if (r != ELFPIE_OK || n_iter == 0) return r;
@@ -824,8 +947,9 @@ struct Ops {
         }
         switch (stage) {
           case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s); break;
-          case 1: r = object_branch(pl, st->psi, true, T1, T2, s); break;
-          case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s); break;
+          // with the row form, the update stage carries both row transforms, as in a run
+          case 1: r = object_branch(pl, st->psi, true, T1, T2, s, nullptr, false, !tb.rowupd); break;
+          case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s, tb.rowupd, st->psi); break;
           case 3: r = tail(pl, tq, s); break;
         }
       }
@@ -973,6 +1097,8 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
       (st = put(t.o_roff, t.rowoff.data(), t.rowoff.size() * sizeof(int))) != ELFPIE_OK ||
       (st = put(t.o_tptr, t.tile_ptr.data(), t.tile_ptr.size() * sizeof(int))) != ELFPIE_OK ||
       (st = put(t.o_tled, t.tile_led.data(), t.tile_led.size() * sizeof(int))) != ELFPIE_OK ||
+      (t.rowupd && (st = put(t.o_sptr, t.seg_ptr.data(), t.seg_ptr.size() * sizeof(int))) != ELFPIE_OK) ||
+      (t.rowupd && (st = put(t.o_sent, t.seg_ent.data(), t.seg_ent.size() * sizeof(int))) != ELFPIE_OK) ||
       (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
     return cleanup(st);
   const int zero = 0;

@@ -659,6 +659,11 @@ __device__ __forceinline__ void fft_lines_lds(cx<T>* buf, const cx<T>* twl, int 
 
 template <class T, int NT>
 __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, double* sbc, double (*red)[4]);
+__device__ __forceinline__ void bias_corrections(double g1, double g2, double t, double* bc);
+template <class T>
+__device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p);
+template <int NT>
+__device__ __forceinline__ void finalize_block(const FinArgs& a, int tid, double (*red)[4]);
 
 // Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
 // (COLS = true) of an N x N complex array; in may equal out.  Blocks past the
@@ -739,6 +744,8 @@ __device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, 
 //   q = H^T omega, the loss terms and G = alpha q_a O / (2|O|) + beta q_phi i O / (2(|O|^2 + eta)),
 //   stored as (-1)^(x+y) G / n over O.
 // Finally the forward DFT along the W own columns, written to T2 (rows still to go).
+// The previous iteration's pupil update can ride along, a slice of pixels per block
+// (every block has room for it; extra blocks would wait for a free compute unit).
 #ifndef ELFPIE_STRIP_W
 #define ELFPIE_STRIP_W 2      // output columns per block
 #define ELFPIE_STRIP_NT 1024  // threads per block
@@ -753,7 +760,7 @@ template <int N> struct StripShape {
 
 template <class T, int N>
 __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, const cx<T>* T1, cx<T>* T2,
-                                                                  const cx<T>* tw) {
+                                                                  const cx<T>* tw, TailArgs ta) {
   using Sh = StripShape<N>;
   constexpr int W = Sh::W, NT = Sh::NT, CH = Sh::CH, NL = W + 4, PITCH = N + 1, OW = W + 2, OH = CH + 2;
   __shared__ cx<T> buf[NL * PITCH];     // line l = column c0 - 2 + l
@@ -762,6 +769,14 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   __shared__ cx<T> twl[N];
   __shared__ double red[NT / 64][2];
   const int tid = threadIdx.x;
+  if (tid < ta.pupil_ppb) {  // the previous iteration's pupil update, a slice per block
+    const int p = blockIdx.x * ta.pupil_ppb + tid;
+    if (p < ta.pa.n_lo * ta.pa.n_lo) {
+      double bc[3] = {1.0, 1.0, 1.0};
+      if (ta.pa.step) bias_corrections(ta.pa.g1, ta.pa.g2, double(*ta.pa.t), bc);
+      pupil_update_body<T>(ta.pa, bc, p);
+    }
+  }
   const int c0 = blockIdx.x * W;
   const T inv_n = T(a.inv_n), eps = T(a.eps);
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
@@ -1202,6 +1217,121 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   static_cast<cx<T>*>(a.mu)[u] = mu;
   a.v[u] = v;
   static_cast<T*>(a.delta)[u] = d;
+}
+
+// The same update on whole rows of the spectrum, with the row transforms on either
+// side folded in, so that neither needs a launch of its own:
+//   the rows of T2 (the Hessian-term gradient after its column transforms) get their
+//   forward row DFT in LDS, which completes gH;
+//   g = gH + the LED contributions covering each pixel, summed in ascending LED order
+//   (the same terms in the same order as k_update) from per-(row, 64-column segment)
+//   lists; a wave's 64 pixels share one segment, so its list reads are scalar;
+//   step mode applies the plan's rule (Eq. 19) and writes the state, gradient mode
+//   writes g;
+//   with inv, the rows of psi as they leave this launch get their inverse row DFT
+//   into T1, the first step of the next iteration's object branch.
+// Blocks past the rows run the pupil partial sums and pre-filter, as in k_update, and
+// a last block may reduce this iteration's loss (its partials are all written).
+#ifndef ELFPIE_UPDROWS_RB
+#define ELFPIE_UPDROWS_RB 1  // rows per block where 256 threads cover whole rows
+#endif
+template <int N> struct UpdRows {
+  static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB, NT = 256;
+};
+
+template <class T, int N>
+__global__ __launch_bounds__(256) void k_update_rows(UpdArgs a, PupilArgs pa, FinArgs fa) {
+  constexpr int RB = UpdRows<N>::RB, NT = UpdRows<N>::NT, PITCH = N + 1;
+  constexpr int PPT = RB * N / NT;  // pixels per thread
+  static_assert(PPT * NT == RB * N && N % 64 == 0, "whole pixels per thread, whole segments per wave");
+  constexpr int GB = ELFPIE_UPD_GB;
+  using cint = const __attribute__((address_space(4))) int;  // wave-uniform reads go scalar
+  __shared__ cx<T> buf[RB * PITCH];
+  __shared__ cx<T> twl[N];
+  __shared__ double sbc[3];
+  __shared__ double fred[3][4];
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= N / RB + a.pupil_blocks) {  // this iteration's loss
+    finalize_block<256>(fa, tid, fred);
+    return;
+  }
+  if ((int)blockIdx.x >= N / RB) {
+    pupil_block<T, 256>(pa, blockIdx.x - N / RB, tid);
+    return;
+  }
+  const int r0 = blockIdx.x * RB;
+  const bool step = a.step != 0, keep_x = step || a.inv;
+  for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
+  if (step && tid == 0) bias_corrections(a.g1, a.g2, double(*a.t), sbc);
+  const cx<T>* Hc = static_cast<const cx<T>*>(a.gH) + (size_t)r0 * N;
+  cx<T> x[PPT], mu[PPT];
+  double v[PPT];
+  T d[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int p = tid + i * NT;
+    buf[(p / N) * PITCH + p % N] = Hc[p];
+    const size_t u = (size_t)r0 * N + p;
+    x[i] = keep_x ? static_cast<const cx<T>*>(a.x)[u] : czero<T>();
+    mu[i] = czero<T>();
+    v[i] = 0.0;
+    d[i] = T(0);
+    if (step) {
+      mu[i] = static_cast<const cx<T>*>(a.mu)[u];
+      v[i] = a.v[u];
+      d[i] = static_cast<const T*>(a.delta)[u];
+    }
+  }
+  __syncthreads();
+  fft_lines_inplace<T, N, false, NT, RB>(buf, twl, tid);  // gH; ends with a barrier
+
+  const cx<T>* C = static_cast<const cx<T>*>(a.C);
+  cint* sp = (cint*)a.seg_ptr;
+  cint* se = (cint*)a.seg_ent;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int p = tid + i * NT;
+    const int ux = p % N;
+    cx<T>& slot = buf[(p / N) * PITCH + ux];
+    cx<T> g = slot;
+    const int seg = __builtin_amdgcn_readfirstlane((r0 + p / N) * a.nseg + ux / 64);
+    const int b0 = sp[seg], b1 = sp[seg + 1];
+    for (int l0 = b0; l0 < b1; l0 += GB) {
+      int idx[GB];
+      bool ok[GB];
+#pragma unroll
+      for (int j = 0; j < GB; ++j) {
+        const int l = min(l0 + j, b1 - 1);  // wave-uniform list entry
+        ok[j] = l0 + j < b1 && ux >= se[4 * l + 1] && ux <= se[4 * l + 2];
+        idx[j] = se[4 * l] + ux;
+      }
+      cx<T> cv[GB];
+#pragma unroll
+      for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
+#pragma unroll
+      for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
+    }
+    const size_t u = (size_t)r0 * N + p;
+    if (step) {
+      optimizer_elem(a.opt, x[i], g, mu[i], v[i], d[i], a.g1, a.g2, a.eta, a.lr, sbc);
+      static_cast<cx<T>*>(a.x)[u] = x[i];
+      static_cast<cx<T>*>(a.mu)[u] = mu[i];
+      a.v[u] = v[i];
+      static_cast<T*>(a.delta)[u] = d[i];
+    } else {
+      static_cast<cx<T>*>(a.g_out)[u] = g;
+    }
+    slot = x[i];
+  }
+  if (!a.inv) return;
+  __syncthreads();
+  fft_lines_inplace<T, N, true, NT, RB>(buf, twl, tid);
+  cx<T>* T1 = static_cast<cx<T>*>(a.T1) + (size_t)r0 * N;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int p = tid + i * NT;
+    T1[p] = buf[(p / N) * PITCH + p % N];
+  }
 }
 
 // ---------------------------------------------------------------------------

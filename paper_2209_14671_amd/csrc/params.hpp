@@ -73,6 +73,14 @@ struct UpdArgs {
   int opt;              // ELFPIE_OPT_*
   int step;             // 0: write g_out; 1: update with the plan's rule
   int pupil_blocks;     // trailing blocks that run the pupil partial sums / pre-filter
+  // the row form (k_update_rows): whole rows per block, row transforms folded in
+  const void* tw;       // n_hi forward twiddles
+  void* T1;             // out (inv): unnormalised inverse row DFT of psi after this call
+  const int* seg_ptr;   // CSR over (row, 64-column segment) of the spectrum
+  const int* seg_ent;   // entries of 4 ints: C index base (index = base + column), first
+                        // column, last column, unused; ascending LED order per segment
+  int nseg;             // segments per row (n_hi / 64)
+  int inv;              // 1: write T1
 };
 
 struct FinArgs {
@@ -120,6 +128,7 @@ struct TailArgs {
   FinArgs fin;
   int pupil_blocks;     // blocks of the pupil update (0: none)
   int fin_block;        // 1: one more block reduces the loss
+  int pupil_ppb;        // riding in the strip launch: pupil pixels per strip block (0: none)
 };
 
 
