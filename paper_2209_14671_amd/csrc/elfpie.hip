@@ -595,9 +595,16 @@ struct Ops {
   // LED gather + (gradient | Eq. 19 update) on 16 x 16 tiles, with the pupil partial
   // sums (and pre-filter) as trailing blocks of the launch.
   template <int N>
-  static void launch_update_rows(const UpdArgs& a, const PupilArgs& pa, const FinArgs* fin, hipStream_t s) {
+  static void launch_update_rows(UpdArgs a, const PupilArgs& pa, const FinArgs* fin, bool pupil, bool prefilter,
+                                 const Tables& tb, hipStream_t s) {
+    constexpr int NT = UpdRows<N>::NT;
+    a.pupil_blocks = 0;  // pupil partial sums and pre-filter, in blocks of NT threads
+    if (pupil) {
+      a.pupil_blocks = ((tb.S + NT - 1) / NT) * tb.nch;
+      if (prefilter) a.pupil_blocks += (tb.n_lo * tb.n_lo + NT - 1) / NT;
+    }
     const FinArgs fa = fin ? *fin : FinArgs{};
-    k_update_rows<T, N><<<N / UpdRows<N>::RB + a.pupil_blocks + (fin ? 1 : 0), UpdRows<N>::NT, 0, s>>>(a, pa, fa);
+    k_update_rows<T, N><<<N / UpdRows<N>::RB + a.pupil_blocks + (fin ? 1 : 0), NT, 0, s>>>(a, pa, fa);
   }
 
   // With the row form (tb.rowupd), gH is the Hessian-term gradient before its forward
@@ -653,12 +660,12 @@ struct Ops {
       if (!st) a.x = const_cast<void*>(psi);  // read for the inverse transforms only
       if (inv && !a.x) return set_err(pl, ELFPIE_E_INVALID, "row-form update without psi");
       switch (tb.n_hi) {
-        case 128: launch_update_rows<128>(a, pa, fin, s); break;
-        case 256: launch_update_rows<256>(a, pa, fin, s); break;
-        case 384: launch_update_rows<384>(a, pa, fin, s); break;
-        case 512: launch_update_rows<512>(a, pa, fin, s); break;
-        case 768: launch_update_rows<768>(a, pa, fin, s); break;
-        case 1024: launch_update_rows<1024>(a, pa, fin, s); break;
+        case 128: launch_update_rows<128>(a, pa, fin, pupil, prefilter, tb, s); break;
+        case 256: launch_update_rows<256>(a, pa, fin, pupil, prefilter, tb, s); break;
+        case 384: launch_update_rows<384>(a, pa, fin, pupil, prefilter, tb, s); break;
+        case 512: launch_update_rows<512>(a, pa, fin, pupil, prefilter, tb, s); break;
+        case 768: launch_update_rows<768>(a, pa, fin, pupil, prefilter, tb, s); break;
+        case 1024: launch_update_rows<1024>(a, pa, fin, pupil, prefilter, tb, s); break;
         default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
       }
       LAUNCH_CHECK(pl, "k_update_rows");

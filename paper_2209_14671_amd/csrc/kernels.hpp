@@ -1232,19 +1232,27 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 //   into T1, the first step of the next iteration's object branch.
 // Blocks past the rows run the pupil partial sums and pre-filter, as in k_update, and
 // a last block may reduce this iteration's loss (its partials are all written).
+#ifndef ELFPIE_UPDR_GB
+#define ELFPIE_UPDR_GB 16  // contribution loads in flight per pixel (row form)
+#endif
+#ifndef ELFPIE_UPDROWS_NT
+#define ELFPIE_UPDROWS_NT 512  // threads per block (at most one per pixel of the block's rows)
+#endif
 #ifndef ELFPIE_UPDROWS_RB
 #define ELFPIE_UPDROWS_RB 1  // rows per block where 256 threads cover whole rows
 #endif
 template <int N> struct UpdRows {
-  static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB, NT = 256;
+  static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
+  static constexpr int NT0 = ELFPIE_UPDROWS_NT < RB * N ? ELFPIE_UPDROWS_NT : RB * N;
+  static constexpr int NT = (RB * N) % NT0 == 0 ? NT0 : 256;
 };
 
 template <class T, int N>
-__global__ __launch_bounds__(256) void k_update_rows(UpdArgs a, PupilArgs pa, FinArgs fa) {
+__global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, PupilArgs pa, FinArgs fa) {
   constexpr int RB = UpdRows<N>::RB, NT = UpdRows<N>::NT, PITCH = N + 1;
   constexpr int PPT = RB * N / NT;  // pixels per thread
   static_assert(PPT * NT == RB * N && N % 64 == 0, "whole pixels per thread, whole segments per wave");
-  constexpr int GB = ELFPIE_UPD_GB;
+  constexpr int GB = ELFPIE_UPDR_GB;
   using cint = const __attribute__((address_space(4))) int;  // wave-uniform reads go scalar
   __shared__ cx<T> buf[RB * PITCH];
   __shared__ cx<T> twl[N];
@@ -1252,11 +1260,11 @@ __global__ __launch_bounds__(256) void k_update_rows(UpdArgs a, PupilArgs pa, Fi
   __shared__ double fred[3][4];
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= N / RB + a.pupil_blocks) {  // this iteration's loss
-    finalize_block<256>(fa, tid, fred);
+    finalize_block<NT>(fa, tid, fred);
     return;
   }
   if ((int)blockIdx.x >= N / RB) {
-    pupil_block<T, 256>(pa, blockIdx.x - N / RB, tid);
+    pupil_block<T, NT>(pa, blockIdx.x - N / RB, tid);
     return;
   }
   const int r0 = blockIdx.x * RB;
