@@ -78,7 +78,8 @@ struct Tables {
   size_t elem = 0;                 // bytes of one real in the plan precision
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
-  size_t o_sptr = 0, o_sent = 0;
+  size_t o_sptr = 0, o_sent = 0, o_s2p = 0;
+  std::vector<int> s2p;            // support index -> pupil pixel index
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
   size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0, o_bigA = 0, o_bigB = 0;
   size_t total = 0;
@@ -174,6 +175,9 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   }
   if (S == 0) return fail(ELFPIE_E_INVALID, "the pupil support is empty (NA * FOV / lambda too small)");
   tb->S = S;
+  tb->s2p.clear();
+  for (int y = 0; y < n; ++y)
+    for (int x = tb->xlo[y]; x <= tb->xhi[y]; ++x) tb->s2p.push_back(y * n + x);
 
   // LED windows
   tb->win.resize(2 * (size_t)tb->K);
@@ -287,7 +291,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_T2 = take(A * cxb);
   tb->o_G = take(A * cxb);
   tb->o_gP = take((size_t)n * n * cxb);
-  tb->o_part = take((size_t)tb->nch * S * cxb);
+  tb->o_part = take((size_t)tb->nch * n * n * cxb);  // zero off the support, for good
+  tb->o_s2p = take((size_t)S * sizeof(int));
   tb->o_Pf = take((size_t)n * n * cxb);
   tb->o_fid = take((size_t)std::max(tb->K, tb->nfid) * sizeof(double));
   tb->o_hess = take(2 * 2 * tb->hess_pairs * sizeof(double));
@@ -638,6 +643,8 @@ struct Ops {
     a.ntiles = tb.ntiles_x * tb.ntiles_x;
     a.g1 = pl->prob.gamma1;
     a.g2 = pl->prob.gamma2;
+    a.lg1 = std::log2(pl->prob.gamma1);
+    a.lg2 = std::log2(pl->prob.gamma2);
     a.eta = pl->prob.eta_opt;
     a.lr = pl->prob.lr;
     a.opt = pl->prob.optimizer;
@@ -689,6 +696,7 @@ struct Ops {
     a.Pf_out = pl->at<void>(tb.o_Pf);
     a.D = pl->at<void>(tb.o_D);
     a.part = pl->at<void>(tb.o_part);
+    a.s2p = pl->at<int>(tb.o_s2p);
     a.xlo = pl->at<int>(tb.o_xlo);
     a.xhi = pl->at<int>(tb.o_xhi);
     a.rowoff = pl->at<int>(tb.o_roff);
@@ -703,6 +711,8 @@ struct Ops {
     a.w_k = e2 / z;
     a.g1 = pl->prob.gamma1;
     a.g2 = pl->prob.gamma2;
+    a.lg1 = std::log2(pl->prob.gamma1);
+    a.lg2 = std::log2(pl->prob.gamma2);
     a.eta = pl->prob.eta_opt;
     a.lr = pl->prob.lr;
     a.opt = pl->prob.optimizer;
@@ -1104,12 +1114,17 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
       (st = put(t.o_roff, t.rowoff.data(), t.rowoff.size() * sizeof(int))) != ELFPIE_OK ||
       (st = put(t.o_tptr, t.tile_ptr.data(), t.tile_ptr.size() * sizeof(int))) != ELFPIE_OK ||
       (st = put(t.o_tled, t.tile_led.data(), t.tile_led.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_s2p, t.s2p.data(), t.s2p.size() * sizeof(int))) != ELFPIE_OK ||
       (t.rowupd && (st = put(t.o_sptr, t.seg_ptr.data(), t.seg_ptr.size() * sizeof(int))) != ELFPIE_OK) ||
       (t.rowupd && (st = put(t.o_sent, t.seg_ent.data(), t.seg_ent.size() * sizeof(int))) != ELFPIE_OK) ||
       (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
     return cleanup(st);
   const int zero = 0;
   if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
+    return cleanup(st);
+  // the pupil partial sums are written on the support only; the rest stays zero
+  const size_t part_bytes = (size_t)t.nch * t.n_lo * t.n_lo * 2 * t.elem;
+  if ((st = hip_check(pl, hipMemset(pl->ws + t.o_part, 0, part_bytes), "hipMemset(pupil partials)")) != ELFPIE_OK)
     return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));

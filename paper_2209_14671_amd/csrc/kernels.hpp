@@ -659,11 +659,28 @@ __device__ __forceinline__ void fft_lines_lds(cx<T>* buf, const cx<T>* twl, int 
 
 template <class T, int NT>
 __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, double* sbc, double (*red)[4]);
-__device__ __forceinline__ void bias_corrections(double g1, double g2, double t, double* bc);
+__device__ __forceinline__ void bias_corrections(double lg1, double lg2, double t, double* bc);
 template <class T>
 __device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p);
 template <int NT>
 __device__ __forceinline__ void finalize_block(const FinArgs& a, int tid, double (*red)[4]);
+
+// Eq. 19 on one pupil pixel p, in two halves so that a caller can issue every load
+// early and finish late: the gradient is the sum of the chunk partial sums in chunk
+// order (zero off the support).
+template <class T>
+struct PupilPre {
+  static constexpr int MC = 16;  // chunks held in registers; more are read at the finish
+  cx<T> part[MC];
+  cx<T> xv, mu;
+  double v;
+  T d;
+  int lo, hi;
+};
+template <class T>
+__device__ __forceinline__ void pupil_prefetch(const PupilArgs& a, int p, PupilPre<T>& f);
+template <class T>
+__device__ __forceinline__ void pupil_finish(const PupilArgs& a, const double* sbc, int p, PupilPre<T>& f);
 
 // Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
 // (COLS = true) of an N x N complex array; in may equal out.  Blocks past the
@@ -769,14 +786,15 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   __shared__ cx<T> twl[N];
   __shared__ double red[NT / 64][2];
   const int tid = threadIdx.x;
-  if (tid < ta.pupil_ppb) {  // the previous iteration's pupil update, a slice per block
-    const int p = blockIdx.x * ta.pupil_ppb + tid;
-    if (p < ta.pa.n_lo * ta.pa.n_lo) {
-      double bc[3] = {1.0, 1.0, 1.0};
-      if (ta.pa.step) bias_corrections(ta.pa.g1, ta.pa.g2, double(*ta.pa.t), bc);
-      pupil_update_body<T>(ta.pa, bc, p);
-    }
-  }
+  // the previous iteration's pupil update, a slice of pixels per block: loads issued
+  // here, the update at the end, so that their latency hides behind the strip's work
+  const int pp = blockIdx.x * ta.pupil_ppb + tid;
+  const bool pslice = tid < ta.pupil_ppb && pp < ta.pa.n_lo * ta.pa.n_lo;
+  constexpr bool early = sizeof(T) == 4;  // FP64 has no registers to spare across the strip
+  PupilPre<T> pf;
+  if (early && pslice) pupil_prefetch<T>(ta.pa, pp, pf);
+  __shared__ double pbc[3];
+  if (tid == 0 && ta.pupil_ppb && ta.pa.step) bias_corrections(ta.pa.lg1, ta.pa.lg2, double(*ta.pa.t), pbc);
   const int c0 = blockIdx.x * W;
   const T inv_n = T(a.inv_n), eps = T(a.eps);
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
@@ -896,16 +914,19 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
     a.partial[2 * blockIdx.x + 0] = s0;
     a.partial[2 * blockIdx.x + 1] = s1;
   }
-  if (!a.want_grad) return;
-  // forward DFT along the own columns (lines 2 .. W + 1), then store
-  fft_lines_inplace<T, N, false, NT, W>(buf + 2 * PITCH, twl, tid);
-  {
+  if (a.want_grad) {
+    // forward DFT along the own columns (lines 2 .. W + 1), then store
+    fft_lines_inplace<T, N, false, NT, W>(buf + 2 * PITCH, twl, tid);
     constexpr int EPT = ceil_div(W * N, NT);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int p = tid + i * NT, l = p % W, y = p / W;
       if (p < W * N) T2[(size_t)y * N + c0 + l] = buf[(l + 2) * PITCH + y];
     }
+  }
+  if (pslice) {
+    if (!early) pupil_prefetch<T>(ta.pa, pp, pf);
+    pupil_finish<T>(ta.pa, pbc, pp, pf);  // pbc: written before the first barrier
   }
 }
 
@@ -1048,11 +1069,12 @@ __device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, dou
   v = vn;
 }
 
-// 1 - g1^t, 1 - g2^t and 1 - g1^(t+1) for step t.
-__device__ __forceinline__ void bias_corrections(double g1, double g2, double t, double* bc) {
-  bc[0] = 1.0 - pow(g1, t);
-  bc[1] = 1.0 - pow(g2, t);
-  bc[2] = 1.0 - pow(g1, t + 1.0);
+// 1 - g1^t, 1 - g2^t and 1 - g1^(t+1) for step t >= 1, from lg = log2(g) (computed
+// once on the host; -inf for g = 0): g^t = 2^(t lg), a fraction of the cost of pow.
+__device__ __forceinline__ void bias_corrections(double lg1, double lg2, double t, double* bc) {
+  bc[0] = 1.0 - exp2(t * lg1);
+  bc[1] = 1.0 - exp2(t * lg2);
+  bc[2] = 1.0 - exp2((t + 1.0) * lg1);
 }
 
 // The update rule of the plan (ELFPIE_OPT_*) for one element: Eq. 19, or for the
@@ -1139,7 +1161,7 @@ __device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid)
 #pragma unroll
   for (int j = 0; j < kPupilChunk; ++j)
     if (k0 + j < a.K) acc = acc + v[j];
-  static_cast<cx<T>*>(a.part)[(size_t)ch * a.S + s] = acc;
+  static_cast<cx<T>*>(a.part)[(size_t)ch * a.n_lo * a.n_lo + a.s2p[s]] = acc;
 }
 
 // Spectrum gradient gather (the segmented sum of the LED contributions that cover
@@ -1171,7 +1193,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   for (int i = tid; i < a.n_lo; i += 256) stab[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   if (a.step && tid == 0) {
     const double t = double(*a.t);
-    bias_corrections(a.g1, a.g2, t, sbc);
+    bias_corrections(a.lg1, a.lg2, t, sbc);
   }
   // state loads go out first; they do not depend on the gather
   cx<T> g = static_cast<const cx<T>*>(a.gH)[u];
@@ -1270,7 +1292,7 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
   const int r0 = blockIdx.x * RB;
   const bool step = a.step != 0, keep_x = step || a.inv;
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
-  if (step && tid == 0) bias_corrections(a.g1, a.g2, double(*a.t), sbc);
+  if (step && tid == 0) bias_corrections(a.lg1, a.lg2, double(*a.t), sbc);
   const cx<T>* Hc = static_cast<const cx<T>*>(a.gH) + (size_t)r0 * N;
   cx<T> x[PPT], mu[PPT];
   double v[PPT];
@@ -1416,7 +1438,7 @@ __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, 
     const PupilArgs& a = ta.pa;
     if (a.step && tid == 0) {
       const double t = double(*a.t);
-      bias_corrections(a.g1, a.g2, t, sbc);
+      bias_corrections(a.lg1, a.lg2, t, sbc);
     }
     __syncthreads();
     const int p = vb * NT + tid;
@@ -1434,44 +1456,57 @@ __global__ __launch_bounds__(256) void k_tail(TailArgs ta) {
   tail_block<T, 256>(ta, blockIdx.x, threadIdx.x, sbc, red);
 }
 
+// Eq. 19 on one pupil pixel p, in two halves (declared above).
+
 template <class T>
-__device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p) {
-  constexpr int GB = 8;
-  const int n = a.n_lo;
-  const int y = p / n, x = p % n;
-  const int lo = a.xlo[y];
-  const bool in = x >= lo && x <= a.xhi[y];
-  const int s = in ? a.rowoff[y] + x - lo : 0;
-  cx<T> xv = czero<T>(), mu = czero<T>();
-  double v = 0.0;
-  T d = T(0);
-  if (a.step) {
-    xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
-    mu = static_cast<cx<T>*>(a.mu)[p];
-    v = a.v[p];
-    d = static_cast<T*>(a.delta)[p];
-  }
-  cx<T> g = czero<T>();
+__device__ __forceinline__ void pupil_prefetch(const PupilArgs& a, int p, PupilPre<T>& f) {
+  const int n = a.n_lo, y = p / n;
+  const size_t A = (size_t)n * n;
   const cx<T>* part = static_cast<const cx<T>*>(a.part);
-  for (int c0 = 0; c0 < a.nch; c0 += GB) {
-    cx<T> pv[GB];
+  f.lo = a.xlo[y];
+  f.hi = a.xhi[y];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) pv[j] = part[(size_t)(c0 + j < a.nch ? c0 + j : c0) * a.S + s];
-#pragma unroll
-    for (int j = 0; j < GB; ++j)
-      if (c0 + j < a.nch) g = g + pv[j];
+  for (int c = 0; c < PupilPre<T>::MC; ++c) f.part[c] = c < a.nch ? part[c * A + p] : czero<T>();
+  f.xv = czero<T>();
+  f.mu = czero<T>();
+  f.v = 0.0;
+  f.d = T(0);
+  if (a.step) {
+    f.xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
+    f.mu = static_cast<const cx<T>*>(a.mu)[p];
+    f.v = a.v[p];
+    f.d = static_cast<const T*>(a.delta)[p];
   }
+}
+
+template <class T>
+__device__ __forceinline__ void pupil_finish(const PupilArgs& a, const double* sbc, int p, PupilPre<T>& f) {
+  const int n = a.n_lo, x = p % n;
+  const size_t A = (size_t)n * n;
+  cx<T> g = czero<T>();
+#pragma unroll
+  for (int c = 0; c < PupilPre<T>::MC; ++c)
+    if (c < a.nch) g = g + f.part[c];
+  for (int c = PupilPre<T>::MC; c < a.nch; ++c) g = g + static_cast<const cx<T>*>(a.part)[c * A + p];
+  const bool in = x >= f.lo && x <= f.hi;
   if (!in) g = czero<T>();
   if (!a.step) {
     static_cast<cx<T>*>(a.g_out)[p] = g;
     return;
   }
-  optimizer_elem(a.opt, xv, g, mu, v, d, a.g1, a.g2, a.eta, a.lr, sbc);
-  if (a.support && !in) xv = czero<T>();
-  static_cast<cx<T>*>(a.P_out)[p] = xv;
-  static_cast<cx<T>*>(a.mu)[p] = mu;
-  a.v[p] = v;
-  static_cast<T*>(a.delta)[p] = d;
+  optimizer_elem(a.opt, f.xv, g, f.mu, f.v, f.d, a.g1, a.g2, a.eta, a.lr, sbc);
+  if (a.support && !in) f.xv = czero<T>();
+  static_cast<cx<T>*>(a.P_out)[p] = f.xv;
+  static_cast<cx<T>*>(a.mu)[p] = f.mu;
+  a.v[p] = f.v;
+  static_cast<T*>(a.delta)[p] = f.d;
+}
+
+template <class T>
+__device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const double* sbc, int p) {
+  PupilPre<T> f;
+  pupil_prefetch<T>(a, p, f);
+  pupil_finish<T>(a, sbc, p, f);
 }
 
 // ---------------------------------------------------------------------------

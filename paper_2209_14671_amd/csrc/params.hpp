@@ -69,6 +69,7 @@ struct UpdArgs {
   const long long* t;   // step counter, already advanced for this iteration
   int n_hi, n_lo, S, ntiles_x, ntiles;
   double g1, g2, eta;
+  double lg1, lg2;      // log2(g1), log2(g2) (-inf for 0): the bias corrections
   double lr;            // step size of the moment methods and SGD
   int opt;              // ELFPIE_OPT_*
   int step;             // 0: write g_out; 1: update with the plan's rule
@@ -101,7 +102,8 @@ struct PupilArgs {
   const void* Pf;       // pre-filtered pupil (workspace)
   void* Pf_out;
   const void* D;        // K x S
-  void* part;           // nch x S complex partial sums
+  void* part;           // nch x n_lo^2 complex partial sums on the pupil grid (zero off the support)
+  const int* s2p;       // support index -> pupil pixel index
   void* g_out;          // gradient output (gradient mode)
   void* mu;
   double* v;
@@ -113,6 +115,7 @@ struct PupilArgs {
   int n_lo, S, K, chunk, nch;
   double w_c, w_e, w_k;  // Gaussian weights: centre, edge, corner
   double g1, g2, eta;
+  double lg1, lg2;      // log2(g1), log2(g2) (-inf for 0)
   double lr;
   int opt;
   int step;
