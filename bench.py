@@ -324,7 +324,7 @@ def cpu_baseline_tiles(cases, flags, budget_s=10.0):
             "sample": f"one oracle iteration on each of the first {done} tiles (NumPy FP64), {step_wall:.1f} s"}
 
 
-def cpu_baseline(case, flags, budget_s=12.0, max_iter=400):
+def cpu_baseline(case, flags, budget_s=12.0, max_iter=100000):
     """The FP64 oracle (unchanged) on the same workload for a bounded number of iterations."""
     import oracle as orc
     import synth
