@@ -64,10 +64,11 @@ __global__ __launch_bounds__(BigLed<N>::RNT) void k_big_rows_inv(LedArgs a, cx<T
 template <class T, int N, bool SCALED>
 __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx<T>* A, cx<T>* B) {
   using Sh = BigLed<N>;
-  constexpr int W = Sh::W, NT = Sh::CNT, NL = W + 2, PITCH = N + 1;
+  constexpr int W = Sh::W, NT = Sh::CNT, NL = W + 2, PITCH = N + 1, EP = NL + 1;
   constexpr int NSTRIP = N / W;
   __shared__ cx<T> buf[NL * PITCH];  // line l at l * PITCH, element = row y
-  __shared__ T eb[NL * N];           // residual, line-major
+  __shared__ T eb[N * EP];           // residual, row-major (row y at y * EP): the loops below
+                                     // give consecutive lanes consecutive lines
   __shared__ cx<T> twl[N];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
@@ -101,9 +102,7 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
       buf[l * PITCH + y] = v;
     }
     __syncthreads();
-    fft_lines_inplace<T, N, true, NT, NL>(buf, twl, tid);
-    for (int p = tid; p < NL * N; p += NT) buf[(p / N) * PITCH + p % N] = scale(buf[(p / N) * PITCH + p % N], sc);
-    __syncthreads();
+    fft_lines_inplace<T, N, true, NT, NL>(buf, twl, tid);  // scaled by sc below
   }
   const T gam = T(a.fid_gamma), eps = T(a.eps);
   // the measured stack is read only when the loss or its gradient is wanted: the
@@ -112,7 +111,11 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
   const T* meas = need_e ? static_cast<const T*>(a.meas) + (size_t)k * N * N : nullptr;
   for (int p = tid; p < NL * N; p += NT) {
     const int y = p / NL, l = p % NL, c = c0 - 1 + l;
-    const cx<T> ov = buf[l * PITCH + y];
+    cx<T> ov = buf[l * PITCH + y];
+    if (!stored) {
+      ov = scale(ov, sc);
+      buf[l * PITCH + y] = ov;  // o itself, for the Wirtinger factor below
+    }
     const T i2 = norm2(ov);
     const bool in = c >= 0 && c < N;
     if (in && l >= 1 && l <= W) {
@@ -120,13 +123,13 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
       if (mode & LED_FIELDS) static_cast<cx<T>*>(a.fields)[pix] = ((c + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
       if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
     }
-    if (need_e) eb[l * N + y] = in ? fid_residual<SCALED>(a.fidelity, i2, meas[(size_t)y * N + c], gam) : T(0);
+    if (need_e) eb[y * EP + l] = in ? fid_residual<SCALED>(a.fidelity, i2, meas[(size_t)y * N + c], gam) : T(0);
   }
   if (!need_e) return;
   __syncthreads();
 
   // features on the own columns: q = grad^T omega needs e one column to each side
-  auto E = [&](int l, int y) -> T { return eb[l * N + y]; };
+  auto E = [&](int l, int y) -> T { return eb[y * EP + l]; };
   double lsum = 0.0;
   for (int p = tid; p < W * N; p += NT) {
     const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;
