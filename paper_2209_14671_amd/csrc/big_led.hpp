@@ -19,11 +19,17 @@
 namespace elfpie {
 
 template <int N> struct BigLed;
+#ifndef ELFPIE_BIG_RB
+#define ELFPIE_BIG_RB 8
+#define ELFPIE_BIG_RNT 256
+#define ELFPIE_BIG_W 16
+#define ELFPIE_BIG_CNT 512
+#endif
 template <> struct BigLed<256> {
-  static constexpr int RB = 8;    // rows per block of the row transforms
-  static constexpr int RNT = 256; // threads of the row transforms
-  static constexpr int W = 16;    // own columns per block of the column kernel
-  static constexpr int CNT = 512; // threads of the column kernel
+  static constexpr int RB = ELFPIE_BIG_RB;    // rows per block of the row transforms
+  static constexpr int RNT = ELFPIE_BIG_RNT;  // threads of the row transforms
+  static constexpr int W = ELFPIE_BIG_W;      // own columns per block of the column kernel
+  static constexpr int CNT = ELFPIE_BIG_CNT;  // threads of the column kernel
 };
 template <> struct BigLed<192> {
   static constexpr int RB = 8, RNT = 256, W = 16, CNT = 512;

@@ -139,7 +139,7 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->mux = p->mux;
   tb->nimg = p->K / p->mux;
   tb->big = p->n_lo > 128;  // 192 and 256: the per-LED branch through HBM scratch
-  tb->nfid = tb->big ? p->K * (p->n_lo / BigLed<256>::W) : tb->nimg;
+  tb->nfid = !tb->big ? tb->nimg : p->K * (p->n_lo == 256 ? 256 / BigLed<256>::W : 192 / BigLed<192>::W);
   tb->prec = p->precision;
   tb->elem = f32 ? 4 : 8;
   const int n = tb->n_lo;
@@ -318,8 +318,11 @@ struct elfpie_plan {
   int device = 0;
   hipStream_t cap = nullptr;  // graph capture stream (captures cannot use the legacy NULL stream)
   hipGraphExec_t gexec = nullptr;   // non-null once the graphs below exist
-  hipGraphExec_t gexecs[2] = {nullptr, nullptr};
-  hipGraph_t graphs[2] = {nullptr, nullptr};
+  // run graphs: kGraphIters and 1 iterations; with the row form also chained variants
+  // (T1 ready and a pupil update pending at the start, and left so at the end)
+  static constexpr int kGraphs = 4;
+  hipGraphExec_t gexecs[kGraphs] = {};
+  hipGraph_t graphs[kGraphs] = {};
   elfpie_state gkey{};
   const void* gkey_meas = nullptr;
   const double* gkey_hist = nullptr;
@@ -811,18 +814,36 @@ struct Ops {
   }
 
   // n_iter update steps; every tail but the last rides in the next iteration.
+  // With the row form, a sequence of calls can chain: cont says that an earlier call
+  // of the same run left T1 ready and its last pupil update pending (it rides in this
+  // call's first launch); without close this call leaves the same to the next one.
   static elfpie_status iterations(elfpie_plan* pl, const elfpie_state* st, const void* meas, int n_iter,
-                                  double* hist, hipStream_t s) {
-    TailReq pend;
+                                  double* hist, hipStream_t s, bool cont = false, bool close = true) {
+    TailReq pend = cont ? pending_pupil(pl, st, hist) : TailReq{};
     elfpie_status r = ELFPIE_OK;
     for (int it = 0; it < n_iter && r == ELFPIE_OK; ++it) {
       TailReq next;
-      r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, it ? &pend : nullptr, &next,
-                    nullptr, it > 0, it & 1);
+      const bool chained = it > 0 || cont;
+      r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, chained ? &pend : nullptr, &next,
+                    nullptr, chained, it & 1);
       pend = next;
     }
-    if (r != ELFPIE_OK || n_iter == 0) return r;
+    if (r != ELFPIE_OK || (n_iter == 0 && !cont) || !close) return r;
     return tail(pl, pend, s);
+  }
+
+  // The tail that a row-form update step defers: the pupil update alone (its loss was
+  // reduced in the update launch), as iteration() returns it.
+  static TailReq pending_pupil(elfpie_plan* pl, const elfpie_state* st, double* hist) {
+    const bool learn_p = (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0;
+    TailReq r = tail_req(pl, learn_p, st->P, st, nullptr, nullptr, hist, 1);
+    r.fin = false;
+    return r;
+  }
+
+  // Close a chained run: the last pending pupil update, launched alone.
+  static elfpie_status close_run(elfpie_plan* pl, const elfpie_state* st, double* hist, hipStream_t s) {
+    return tail(pl, pending_pupil(pl, st, hist), s);
   }
 
   static elfpie_status forward(elfpie_plan* pl, const void* psi, const void* P, const void* meas, void* fields,
@@ -1134,7 +1155,7 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
 
 elfpie_status elfpie_plan_destroy(elfpie_plan* pl) {
   if (!pl) return ELFPIE_E_INVALID;
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
     if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
     if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
   }
@@ -1227,23 +1248,27 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   k_fill<int><<<1, 64, 0, s>>>(flag, 0, 1);
   LAUNCH_CHECK(pl, "k_fill");
   if (n_iter == 0) return ELFPIE_OK;
+  const bool chain = tb.rowupd;
   // the graphs bake in every pointer of the iteration: reuse them only for the same ones
   const bool same = pl->gexec && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
                     pl->gkey_hist == d_loss_hist;
   if (!same) {
-    // (re)capture: one graph of kGraphIters iterations and one of a single iteration
-    for (int g = 0; g < 2; ++g) {
+    // (re)capture: graphs of kGraphIters iterations and of a single iteration, each a
+    // whole run; with the row form, each of them opening a chain and continuing one
+    for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
       if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
       if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
       pl->gexecs[g] = nullptr;
       pl->graphs[g] = nullptr;
     }
     pl->gexec = nullptr;
-    for (int g = 0; g < 2; ++g) {
-      const int reps = g == 0 ? kGraphIters : 1;
+    for (int g = 0; g < (chain ? 4 : 2); ++g) {
+      const int reps = g % 2 == 0 ? kGraphIters : 1;
+      const bool cont = g >= 2;
       HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-      const elfpie_status r = dispatch(
-          pl, [&](auto ops) { return decltype(ops)::iterations(pl, st, meas, reps, d_loss_hist, pl->cap); });
+      const elfpie_status r = dispatch(pl, [&](auto ops) {
+        return decltype(ops)::iterations(pl, st, meas, reps, d_loss_hist, pl->cap, cont, !chain);
+      });
       hipGraph_t gr = nullptr;
       const hipError_t ec = hipStreamEndCapture(pl->cap, &gr);
       if (r != ELFPIE_OK) {
@@ -1259,8 +1284,24 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
     pl->gkey_meas = meas;
     pl->gkey_hist = d_loss_hist;
   }
-  for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[0], s));
-  for (int i = 0; i < n_iter % kGraphIters; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[1], s));
+  if (chain) {
+    // the first replay opens the chain, the others continue it, a last launch closes it
+    bool opened = false;
+    for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) {
+      HIP_TRY(pl, hipGraphLaunch(pl->gexecs[opened ? 2 : 0], s));
+      opened = true;
+    }
+    for (int i = 0; i < n_iter % kGraphIters; ++i) {
+      HIP_TRY(pl, hipGraphLaunch(pl->gexecs[opened ? 3 : 1], s));
+      opened = true;
+    }
+    const elfpie_status r =
+        dispatch(pl, [&](auto ops) { return decltype(ops)::close_run(pl, st, d_loss_hist, s); });
+    if (r != ELFPIE_OK) return r;
+  } else {
+    for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[0], s));
+    for (int i = 0; i < n_iter % kGraphIters; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[1], s));
+  }
   if (checked) {
     HIP_TRY(pl, hipStreamSynchronize(s));
     int h = 0;

@@ -235,6 +235,24 @@ def test_run_equals_repeated_steps_bitwise_and_tracks_oracle():
     assert np.max(np.abs(host(hist) - rh) / np.abs(rh)) < 1e-11
 
 
+def test_chained_runs_equal_repeated_steps():
+    """Runs of 5 and then 19 iterations (graphs that open, continue and close a chain:
+    8 + 8 + 3 x 1) against 24 single steps, bit for bit, FP32 and FP64."""
+    for f32 in (True, False):
+        pair = make_pair(64, 4, 7, f32=f32)
+        plan = make_plan(pair, f32)
+        meas = dev(pair.meas, f32)
+        a = gpu_state(plan, pair, f32)
+        b = a.clone()
+        h1 = plan.run(a, meas, 5)
+        h2 = plan.run(a, meas, 19)
+        hs = [plan.step(b, meas) for _ in range(24)]
+        torch.cuda.synchronize()
+        for k in ("psi", "P", "mu_psi", "v_psi", "delta_psi", "mu_P", "v_P", "delta_P", "t"):
+            assert torch.equal(getattr(a, k), getattr(b, k)), (f32, k)
+        assert torch.equal(torch.cat([h1, h2]), torch.stack(hs))
+
+
 def test_init_state_matches_oracle():
     for f32 in (False, True):
         pair = make_pair(32, 4, 5, f32=f32)
