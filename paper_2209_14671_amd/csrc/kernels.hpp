@@ -278,6 +278,34 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   // features, loss and dL/d(conj o), written over the field registers
   auto E = [&](int yy, int xx) -> T { return eb[yy * PITCH + xx]; };
   double lsum = 0.0;
+  if (!SCALED && a.norm == 0 && !(eps > T(0))) {
+    // the exact anisotropic L1 (omega = sign, rho = |.|) under the intensity or amplitude
+    // fidelity, without a branch per pixel: clamped reads and selects; the same
+    // arithmetic as the general loop below
+    const bool amp = a.fidelity == 0;
+    auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+      const int j = jj[i], x = mm[i];
+      const int xr = min(x + 1, N - 1), xl = max(x - 1, 0);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = j + r * R1;
+        const int yd = min(y + 1, N - 1), yu = max(y - 1, 0);
+        const T e = E(y, x), er = E(y, xr), ed = E(yd, x), el = E(y, xl), eu = E(yu, x);
+        const T dx0 = (x < N - 1) ? er - e : T(0);
+        const T dy0 = (y < N - 1) ? ed - e : T(0);
+        const T dxm = (x > 0) ? e - el : T(0);
+        const T dym = (y > 0) ? e - eu : T(0);
+        const T q = sgn(dxm) - sgn(dx0) + sgn(dym) - sgn(dy0);
+        lsum += double(fabs(dx0) + fabs(dy0));
+        const cx<T> ov = o[i][r];
+        const T i2 = norm2(ov);
+        const T fa = i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0);
+        o[i][r] = scale(ov, amp ? fa : q);
+      }
+    }
+  } else {
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
     const int j = jj[i], x = mm[i];
@@ -313,6 +341,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       }
       o[i][r] = fid_wirtinger<SCALED>(a.fidelity, o[i][r], q, gam);
     }
+  }
   }
   __syncthreads();  // every residual read is done; the tile can be overwritten
 
