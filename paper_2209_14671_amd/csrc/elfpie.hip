@@ -1147,6 +1147,10 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
   const size_t part_bytes = (size_t)t.nch * t.n_lo * t.n_lo * 2 * t.elem;
   if ((st = hip_check(pl, hipMemset(pl->ws + t.o_part, 0, part_bytes), "hipMemset(pupil partials)")) != ELFPIE_OK)
     return cleanup(st);
+  // the memset runs on the null stream, which work on non-blocking streams does not
+  // wait for: finish it before the plan is handed out
+  if ((st = hip_check(pl, hipStreamSynchronize(nullptr), "hipStreamSynchronize(plan set-up)")) != ELFPIE_OK)
+    return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));
   *out = pl;
