@@ -852,7 +852,11 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   __syncthreads();
   double la = 0.0, lp = 0.0;
   for (int r0 = 0; r0 < N; r0 += CH) {
-    // omega on lines 1 .. W + 2 (columns c0 - 1 .. c0 + W), rows r0 - 1 .. r0 + CH
+    // omega on lines 1 .. W + 2 (columns c0 - 1 .. c0 + W), rows r0 - 1 .. r0 + CH.  The
+    // exact anisotropic L1 (the default) takes a copy of the loop with omega = sign and
+    // rho = |.| and no branch per position: the same arithmetic, selects for the rest.
+    auto omega_pass = [&](auto fast_c) {
+    constexpr bool FAST = decltype(fast_c)::value;
     for (int p = tid; p < OW * OH; p += NT) {
       const int li = p / OH, yi = p % OH;
       const int l = li + 1, y = r0 - 1 + yi, c = c0 - 2 + l;
@@ -861,10 +865,26 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
       const bool vxy = in && c <= N - 2 && y <= N - 2;
       // rows clamped into the grid: exact for valid positions, harmless for the others
       const int y0c = min(max(y, 0), N - 1), ymc = min(max(y - 1, 0), N - 1), ypc = min(max(y + 1, 0), N - 1);
+      const bool own = l >= 2 && l <= W + 1 && yi >= 1 && yi <= CH && in;
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
         const T* src = f == 0 ? sa : sp;
         const T ctr = src[l * N + y0c];
+        if constexpr (FAST) {
+          const T sl = src[(l - 1) * N + y0c], sr = src[(l + 1) * N + y0c];
+          const T su = src[l * N + ymc], sd = src[l * N + ypc], srd = src[(l + 1) * N + ypc];
+          const T hxx = vxx ? sl - T(2) * ctr + sr : T(0);
+          const T hyy = vyy ? su - T(2) * ctr + sd : T(0);
+          const T hxy = vxy ? ctr - sr - sd + srd : T(0);
+          auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+          om[3 * f + 0][p] = sgn(hxx);
+          om[3 * f + 1][p] = sgn(hyy);
+          om[3 * f + 2][p] = sgn(hxy);
+          const double lv = double(fabs(hxx)) + double(fabs(hyy)) + double(fabs(hxy));
+          if (f == 0) la += own ? lv : 0.0;
+          else lp += own ? lv : 0.0;
+          continue;
+        }
         const T hxx = vxx ? src[(l - 1) * N + y0c] - T(2) * ctr + src[(l + 1) * N + y0c] : T(0);
         const T hyy = vyy ? src[l * N + ymc] - T(2) * ctr + src[l * N + ypc] : T(0);
         const T hxy = vxy ? ctr - src[(l + 1) * N + y0c] - src[l * N + ypc] + src[(l + 1) * N + ypc] : T(0);
@@ -883,7 +903,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
         om[3 * f + 1][p] = wyy;
         om[3 * f + 2][p] = wxy;
         // loss: own pixels (lines 2 .. W + 1, rows r0 .. r0 + CH - 1), each counted once
-        if (l >= 2 && l <= W + 1 && yi >= 1 && yi <= CH && in) {
+        if (own) {
           double lv;
           if (a.norm == 0) {
             lv = double(rho(hxx, eps)) + double(rho(hyy, eps)) + double(rho(hxy, eps));
@@ -896,6 +916,9 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
         }
       }
     }
+    };
+    if (a.norm == 0 && !(eps > T(0))) omega_pass(std::true_type{});
+    else omega_pass(std::false_type{});
     __syncthreads();
     if (a.want_grad) {
       for (int p = tid; p < W * CH; p += NT) {
