@@ -1364,12 +1364,28 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
       d[i] = static_cast<const T*>(a.delta)[u];
     }
   }
-  __syncthreads();
-  fft_lines_inplace<T, N, false, NT, RB>(buf, twl, tid);  // gH; ends with a barrier
-
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
   cint* sp = (cint*)a.seg_ptr;
   cint* se = (cint*)a.seg_ent;
+  // with one pixel per thread, the first GB contribution loads go out before the row
+  // transform (the barriers there wait for LDS only), and are added after gH, in the
+  // same order as the loop below
+  constexpr bool PF = PPT == 1;
+  cx<T> pre[PF ? GB : 1];
+  if constexpr (PF) {
+    const int ux = tid % N;
+    const int seg = __builtin_amdgcn_readfirstlane((r0 + tid / N) * a.nseg + ux / 64);
+    const int b0 = sp[seg], b1 = sp[seg + 1];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) {
+      const int l = b1 > b0 ? min(b0 + j, b1 - 1) : 0;  // an entry that exists, also for an empty list
+      const bool ok = b0 + j < b1 && ux >= se[4 * l + 1] && ux <= se[4 * l + 2];
+      pre[j] = ok ? C[se[4 * l] + ux] : czero<T>();
+    }
+  }
+  __syncthreads();
+  fft_lines_inplace<T, N, false, NT, RB>(buf, twl, tid);  // gH; ends with a barrier
+
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int p = tid + i * NT;
@@ -1378,7 +1394,13 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
     cx<T> g = slot;
     const int seg = __builtin_amdgcn_readfirstlane((r0 + p / N) * a.nseg + ux / 64);
     const int b0 = sp[seg], b1 = sp[seg + 1];
-    for (int l0 = b0; l0 < b1; l0 += GB) {
+    int lstart = b0;
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < GB; ++j) g = g + pre[j];
+      lstart = b0 + GB;
+    }
+    for (int l0 = lstart; l0 < b1; l0 += GB) {
       int idx[GB];
       bool ok[GB];
 #pragma unroll
