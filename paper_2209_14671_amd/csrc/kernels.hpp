@@ -1309,6 +1309,9 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #ifndef ELFPIE_UPDR_GB
 #define ELFPIE_UPDR_GB 16  // contribution loads in flight per pixel (row form)
 #endif
+#ifndef ELFPIE_UPDR_PF
+#define ELFPIE_UPDR_PF 1  // gather batches issued before the row transform (one pixel per thread)
+#endif
 #ifndef ELFPIE_UPDROWS_NT
 #define ELFPIE_UPDROWS_NT 512  // threads per block (at most one per pixel of the block's rows)
 #endif
@@ -1371,13 +1374,14 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
   // transform (the barriers there wait for LDS only), and are added after gH, in the
   // same order as the loop below
   constexpr bool PF = PPT == 1;
-  cx<T> pre[PF ? GB : 1];
+  constexpr int PG = PF ? ELFPIE_UPDR_PF * GB : 1;  // loads issued early
+  cx<T> pre[PG];
   if constexpr (PF) {
     const int ux = tid % N;
     const int seg = __builtin_amdgcn_readfirstlane((r0 + tid / N) * a.nseg + ux / 64);
     const int b0 = sp[seg], b1 = sp[seg + 1];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) {
+    for (int j = 0; j < PG; ++j) {
       const int l = b1 > b0 ? min(b0 + j, b1 - 1) : 0;  // an entry that exists, also for an empty list
       const bool ok = b0 + j < b1 && ux >= se[4 * l + 1] && ux <= se[4 * l + 2];
       pre[j] = ok ? C[se[4 * l] + ux] : czero<T>();
@@ -1397,8 +1401,8 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
     int lstart = b0;
     if constexpr (PF) {
 #pragma unroll
-      for (int j = 0; j < GB; ++j) g = g + pre[j];
-      lstart = b0 + GB;
+      for (int j = 0; j < PG; ++j) g = g + pre[j];
+      lstart = b0 + PG;
     }
     for (int l0 = lstart; l0 < b1; l0 += GB) {
       int idx[GB];
