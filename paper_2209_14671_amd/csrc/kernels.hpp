@@ -1370,21 +1370,37 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
   cint* sp = (cint*)a.seg_ptr;
   cint* se = (cint*)a.seg_ent;
-  // with one pixel per thread, the first GB contribution loads go out before the row
+  // Each pixel's segment list: lane j of the wave holds entry j (up to 64), fetched with
+  // one vector load per field; the walk reads them back with readlane, so that only the
+  // list bounds are scalar loads on the way to the contribution loads.
+  const int lane = tid & 63;
+  int b0[PPT], nl[PPT], lb[PPT], lxs[PPT], lxe[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int p = tid + i * NT;
+    const int seg = __builtin_amdgcn_readfirstlane((r0 + p / N) * a.nseg + (p % N) / 64);
+    b0[i] = sp[seg];
+    nl[i] = sp[seg + 1] - b0[i];
+    const int li = lane < nl[i] ? b0[i] + lane : 0;  // entry 0 exists, also for an empty list
+    lb[i] = a.seg_ent[4 * li];
+    lxs[i] = a.seg_ent[4 * li + 1];
+    lxe[i] = a.seg_ent[4 * li + 2];
+  }
+  // with one pixel per thread, the first PG contribution loads go out before the row
   // transform (the barriers there wait for LDS only), and are added after gH, in the
-  // same order as the loop below
+  // same order as the walk below
   constexpr bool PF = PPT == 1;
   constexpr int PG = PF ? ELFPIE_UPDR_PF * GB : 1;  // loads issued early
+  static_assert(PG <= 64, "early loads come from the entries held in lanes");
   cx<T> pre[PG];
   if constexpr (PF) {
     const int ux = tid % N;
-    const int seg = __builtin_amdgcn_readfirstlane((r0 + tid / N) * a.nseg + ux / 64);
-    const int b0 = sp[seg], b1 = sp[seg + 1];
 #pragma unroll
     for (int j = 0; j < PG; ++j) {
-      const int l = b1 > b0 ? min(b0 + j, b1 - 1) : 0;  // an entry that exists, also for an empty list
-      const bool ok = b0 + j < b1 && ux >= se[4 * l + 1] && ux <= se[4 * l + 2];
-      pre[j] = ok ? C[se[4 * l] + ux] : czero<T>();
+      const int lu = min(j, max(nl[0] - 1, 0));  // wave-uniform
+      const int xs = __builtin_amdgcn_readlane(lxs[0], lu), xe = __builtin_amdgcn_readlane(lxe[0], lu);
+      const bool ok = j < nl[0] && ux >= xs && ux <= xe;
+      pre[j] = ok ? C[__builtin_amdgcn_readlane(lb[0], lu) + ux] : czero<T>();
     }
   }
   __syncthreads();
@@ -1396,15 +1412,32 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
     const int ux = p % N;
     cx<T>& slot = buf[(p / N) * PITCH + ux];
     cx<T> g = slot;
-    const int seg = __builtin_amdgcn_readfirstlane((r0 + p / N) * a.nseg + ux / 64);
-    const int b0 = sp[seg], b1 = sp[seg + 1];
-    int lstart = b0;
+    int lstart = 0;
     if constexpr (PF) {
 #pragma unroll
       for (int j = 0; j < PG; ++j) g = g + pre[j];
-      lstart = b0 + PG;
+      lstart = PG;
     }
-    for (int l0 = lstart; l0 < b1; l0 += GB) {
+    const int nh = min(nl[i], 64);  // entries held in lanes
+    for (int l0 = lstart; l0 < nh; l0 += GB) {
+      int idx[GB];
+      bool ok[GB];
+#pragma unroll
+      for (int j = 0; j < GB; ++j) {
+        const int lu = min(l0 + j, nh - 1);  // wave-uniform
+        const int xs = __builtin_amdgcn_readlane(lxs[i], lu), xe = __builtin_amdgcn_readlane(lxe[i], lu);
+        ok[j] = l0 + j < nh && ux >= xs && ux <= xe;
+        idx[j] = __builtin_amdgcn_readlane(lb[i], lu) + ux;
+      }
+      cx<T> cv[GB];
+#pragma unroll
+      for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
+#pragma unroll
+      for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
+    }
+    // entries past the 64 held in lanes (long lists only), through scalar loads
+    const int b1 = b0[i] + nl[i];
+    for (int l0 = b0[i] + 64; l0 < b1; l0 += GB) {
       int idx[GB];
       bool ok[GB];
 #pragma unroll
@@ -1417,7 +1450,7 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
 #pragma unroll
       for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
 #pragma unroll
-      for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
+      for (int j = 0; j < GB; ++j) g = g + cv[j];
     }
     const size_t u = (size_t)r0 * N + p;
     if (step) {
