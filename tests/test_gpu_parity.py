@@ -235,6 +235,37 @@ def test_run_equals_repeated_steps_bitwise_and_tracks_oracle():
     assert np.max(np.abs(host(hist) - rh) / np.abs(rh)) < 1e-11
 
 
+@pytest.mark.parametrize("f32", [True, False])
+def test_long_segment_lists_match_oracle(f32):
+    """121 LEDs 0.5 mm apart under a 0.3 NA: every window covers nearly the same pixels,
+    so a 64-column segment of a spectrum row meets up to 121 LED runs (more than the 64
+    that the update keeps in lanes; the rest go through its scalar walk).  Gradient and
+    one step against the oracle."""
+    pair = make_pair(32, 4, 11, f32=f32, na=0.3, pitch_mm=0.5)
+    org, sup = orc.window_origins(pair.oprob), orc.pupil_support(pair.oprob)
+    count = {}
+    for y0, x0 in org:
+        for dy in range(pair.oprob.n_lo):
+            xs = np.nonzero(sup[dy])[0]
+            if len(xs):
+                for g in range((x0 + xs[0]) // 64, (x0 + xs[-1]) // 64 + 1):
+                    count[(y0 + dy, g)] = count.get((y0 + dy, g), 0) + 1
+    assert max(count.values()) > 64
+    plan = make_plan(pair, f32)
+    psi, P, meas = dev(pair.psi, f32), dev(pair.P, f32), dev(pair.meas, f32)
+    l4, g, gP = plan.grad(psi, P, meas)
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    st = gpu_state(plan, pair, f32)
+    plan.step(st, meas)
+    torch.cuda.synchronize()
+    ref, _ = orc.step(pair.state, pair.meas, pair.oprob)
+    t = TOL[f32]
+    eg, egp, es = rel_l2(host(g), rg), rel_l2(host(gP), rgP), rel_l2(host(st.psi), ref.psi)
+    print(f"long lists ({'f32' if f32 else 'f64'}): g_psi {eg:.2e} g_P {egp:.2e} step {es:.2e}")
+    assert eg < t["grad"] and egp < t["grad"]
+    assert es < t["state"] and rel_l2(host(st.P), ref.P) < t["state"]
+
+
 def test_chained_runs_equal_repeated_steps():
     """Runs of 5 and then 19 iterations (graphs that open, continue and close a chain:
     8 + 8 + 3 x 1) against 24 single steps, bit for bit, FP32 and FP64."""
