@@ -137,6 +137,27 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
   // features on the own columns: q = grad^T omega needs e one column to each side
   auto E = [&](int l, int y) -> T { return eb[y * EP + l]; };
   double lsum = 0.0;
+  if (!SCALED && a.norm == 0 && !(eps > T(0))) {
+    // the exact anisotropic L1 (omega = sign, rho = |.|) under the intensity or amplitude
+    // fidelity, without a branch per pixel (the same arithmetic as the general loop)
+    const bool amp = a.fidelity == 0;
+    auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+    for (int p = tid; p < W * N; p += NT) {
+      const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;
+      const int yd = min(y + 1, N - 1), yu = max(y - 1, 0);
+      const T e = E(l, y), er = E(l + 1, y), ed = E(l, yd), el = E(l - 1, y), eu = E(l, yu);
+      const T dx0 = (x < N - 1) ? er - e : T(0);
+      const T dy0 = (y < N - 1) ? ed - e : T(0);
+      const T dxm = (x > 0) ? e - el : T(0);
+      const T dym = (y > 0) ? e - eu : T(0);
+      const T q = sgn(dxm) - sgn(dx0) + sgn(dym) - sgn(dy0);
+      lsum += double(fabs(dx0) + fabs(dy0));
+      const cx<T> ov = buf[l * PITCH + y];
+      const T i2 = norm2(ov);
+      const T fa = i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0);
+      buf[l * PITCH + y] = scale(ov, amp ? fa : q);
+    }
+  } else
   for (int p = tid; p < W * N; p += NT) {
     const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;
     const T e = E(l, y);

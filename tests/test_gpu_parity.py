@@ -190,16 +190,29 @@ def test_set_penalty_changes_the_loss_weights():
     assert rel_l2(host(st.psi), ref.psi) < 1e-12
 
 
-def test_exact_sign_mode_gradient_close():
-    """l1_eps = 0 (literal L1): FP32 sign decisions of near-zero differences may differ."""
-    pair = make_pair(32, 4, 5, f32=True, l1_eps=0.0)
-    plan = make_plan(pair, True)
-    l4, g, gP = plan.grad(dev(pair.psi, True), dev(pair.P, True), dev(pair.meas, True))
+EXACT_SIGN_CASES = [(32, 4, True, orc.FID_INTENSITY), (32, 4, False, orc.FID_INTENSITY),
+                    (64, 4, True, orc.FID_AMPLITUDE), (64, 4, False, orc.FID_AMPLITUDE),
+                    (128, 4, True, orc.FID_INTENSITY), (256, 2, True, orc.FID_INTENSITY),
+                    (256, 2, True, orc.FID_AMPLITUDE)]
+
+
+@pytest.mark.parametrize("n_lo,up,f32,fidelity", EXACT_SIGN_CASES)
+def test_exact_sign_mode_gradient_close(n_lo, up, f32, fidelity):
+    """l1_eps = 0 (literal L1, the kernels' branch-free feature loops, in the LDS tile and
+    in the 256^2 column kernel).  The gradient is a sum of sign(.) terms: where a
+    difference of neighbouring residuals is within rounding of zero, FP32 and the FP64
+    oracle may take opposite signs, and such pixels grow with the tile (measured rel-L2:
+    1e-7 at 32^2, 2e-5 at 64^2, 2e-3 at 128^2, 1e-3 at 256^2).  FP32 is held to 5e-3;
+    FP64, whose decisions agree, to 1e-9; the loss to the usual bounds."""
+    pair = make_pair(n_lo, up, 5 if n_lo <= 64 else 3, f32=f32, l1_eps=0.0, fidelity=fidelity)
+    plan = make_plan(pair, f32)
+    l4, g, gP = plan.grad(dev(pair.psi, f32), dev(pair.P, f32), dev(pair.meas, f32))
     rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
-    eg = rel_l2(host(g), rg)
-    print(f"exact-sign g_psi rel err {eg:.2e}")
-    assert eg < 1e-3
-    assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < 1e-5)
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    print(f"exact-sign n_lo={n_lo} f32={f32} fid={fidelity}: g_psi {eg:.2e} g_P {egp:.2e}")
+    tol = 5e-3 if f32 else 1e-9
+    assert eg < tol and egp < tol
+    assert np.all(np.abs(host(l4) - rl4) / np.abs(rl4) < (1e-5 if f32 else 1e-12))
 
 
 def test_transforms_match_oracle():
