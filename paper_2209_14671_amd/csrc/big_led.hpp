@@ -115,21 +115,42 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
   // forward model alone (fields, images) is called without one
   const bool need_e = (mode & (LED_GRAD | LED_LOSS)) != 0;
   const T* meas = need_e ? static_cast<const T*>(a.meas) + (size_t)k * N * N : nullptr;
-  for (int p = tid; p < NL * N; p += NT) {
-    const int y = p / NL, l = p % NL, c = c0 - 1 + l;
-    cx<T> ov = buf[l * PITCH + y];
-    if (!stored) {
-      ov = scale(ov, sc);
-      buf[l * PITCH + y] = ov;  // o itself, for the Wirtinger factor below
+  // the gradient and loss modes under the amplitude or intensity fidelity: the same
+  // residual with the fidelity fixed outside the loop and no output stores to test
+  auto residual_only = [&](auto amp_c) {
+    constexpr bool AMP = decltype(amp_c)::value;
+    for (int p = tid; p < NL * N; p += NT) {
+      const int y = p / NL, l = p % NL, c = c0 - 1 + l;
+      cx<T> ov = buf[l * PITCH + y];
+      if (!stored) {
+        ov = scale(ov, sc);
+        buf[l * PITCH + y] = ov;
+      }
+      const T i2 = norm2(ov);
+      const bool in = c >= 0 && c < N;
+      eb[y * EP + l] = in ? fid_residual<false>(AMP ? 0 : 1, i2, meas[(size_t)y * N + c], gam) : T(0);
     }
-    const T i2 = norm2(ov);
-    const bool in = c >= 0 && c < N;
-    if (in && l >= 1 && l <= W) {
-      const size_t pix = (size_t)k * N * N + (size_t)y * N + c;
-      if (mode & LED_FIELDS) static_cast<cx<T>*>(a.fields)[pix] = ((c + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
-      if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
+  };
+  if (!SCALED && need_e && !(mode & (LED_FIELDS | LED_INTENS))) {
+    if (a.fidelity == 0) residual_only(std::true_type{});
+    else residual_only(std::false_type{});
+  } else {
+    for (int p = tid; p < NL * N; p += NT) {
+      const int y = p / NL, l = p % NL, c = c0 - 1 + l;
+      cx<T> ov = buf[l * PITCH + y];
+      if (!stored) {
+        ov = scale(ov, sc);
+        buf[l * PITCH + y] = ov;  // o itself, for the Wirtinger factor below
+      }
+      const T i2 = norm2(ov);
+      const bool in = c >= 0 && c < N;
+      if (in && l >= 1 && l <= W) {
+        const size_t pix = (size_t)k * N * N + (size_t)y * N + c;
+        if (mode & LED_FIELDS) static_cast<cx<T>*>(a.fields)[pix] = ((c + y) & 1) ? cx<T>{-ov.x, -ov.y} : ov;
+        if (mode & LED_INTENS) static_cast<T*>(a.intens)[pix] = i2;
+      }
+      if (need_e) eb[y * EP + l] = in ? fid_residual<SCALED>(a.fidelity, i2, meas[(size_t)y * N + c], gam) : T(0);
     }
-    if (need_e) eb[y * EP + l] = in ? fid_residual<SCALED>(a.fidelity, i2, meas[(size_t)y * N + c], gam) : T(0);
   }
   if (!need_e) return;
   __syncthreads();
