@@ -6,7 +6,8 @@
  * from a Fourier-ptychographic stack of K low-resolution intensity images
  * (Sec. 3, Algorithm 1).  One iteration, for all K LEDs at once:
  *   - crops each LED's window of Psi and applies the pupil, inverse-transforms
- *     it to a low-resolution field (Sec. 3.1, Eq. 1, M = 1 LED per image);
+ *     it to a low-resolution field (Sec. 3.1, Eq. 1; M LEDs lit together per
+ *     image, M = mux, the images summing their intensities);
  *   - evaluates the L1 data fidelity on image gradients (Eq. 4 or Eq. 5 with
  *     the normaliser of Eq. 12) and the Hessian penalties on the amplitude and
  *     phase of O = F_A Psi (Eq. 6, 7, combined by Eq. 8);
@@ -84,8 +85,9 @@ enum {
 
 /* Problem statement: Algorithm 1's inputs and the optics of Sec. 4.1. */
 typedef struct {
-  int32_t n_lo;            /* low-res image side; power of two, 32..128 (F32), 32..64 (F64) */
-  int32_t upsample;        /* r = n_hi / n_lo; n_hi must be a power of two, 128..1024       */
+  int32_t n_lo;            /* low-res image side: 32, 64, 96, 128, 192 or 256 (F32);
+                              32 or 64 (F64); 192 and 256 need mux = 1                    */
+  int32_t upsample;        /* r = n_hi / n_lo; n_hi must be 128, 256, 384, 512, 768 or 1024  */
   int32_t K;               /* number of LEDs (rows of led_k), >= 1; images = K / mux         */
   double wavelength_um;    /* illumination wavelength, > 0                                  */
   double na;               /* objective numerical aperture, > 0                             */
