@@ -108,9 +108,18 @@ constexpr int gather_batch(int ppt) {
 }
 
 template <int N> struct LedShape;
-template <> struct LedShape<32> { static constexpr int NT = 128, R1 = 8, R2 = 4; };
-template <> struct LedShape<96> { static constexpr int NT = 512, R1 = 16, R2 = 6; };
-template <> struct LedShape<64> { static constexpr int NT = 256, R1 = 8, R2 = 8; };
+#ifndef ELFPIE_LED32_NT
+#define ELFPIE_LED32_NT 256
+#endif
+#ifndef ELFPIE_LED96_NT
+#define ELFPIE_LED96_NT 512
+#endif
+template <> struct LedShape<32> { static constexpr int NT = ELFPIE_LED32_NT, R1 = 8, R2 = 4; };
+template <> struct LedShape<96> { static constexpr int NT = ELFPIE_LED96_NT, R1 = 16, R2 = 6; };
+#ifndef ELFPIE_LED64_NT
+#define ELFPIE_LED64_NT 512
+#endif
+template <> struct LedShape<64> { static constexpr int NT = ELFPIE_LED64_NT, R1 = 8, R2 = 8; };
 #ifndef ELFPIE_LED128_NT
 #define ELFPIE_LED128_NT 1024
 #endif
