@@ -578,7 +578,7 @@ struct Ops {
     if (!t1_ready && (r = lines<true, false>(pl, psi, T1, s, tail)) != ELFPIE_OK) return r;
     const TailReq* strip_tail = t1_ready ? tail : nullptr;
     if (strip_tail && (strip_tail->fin || (size_t)strip_tail->a.pa.n_lo * strip_tail->a.pa.n_lo >
-                                              (size_t)(tb.n_hi / ELFPIE_STRIP_W) * ELFPIE_STRIP_NT)) {
+                                              (size_t)(tb.n_hi / ELFPIE_STRIP_W) * (tb.n_hi <= 256 ? ELFPIE_STRIP_NT_SMALL : ELFPIE_STRIP_NT))) {
       // only a pupil update that fits one slice per strip block rides there
       if ((r = Ops::tail(pl, *strip_tail, s)) != ELFPIE_OK) return r;
       strip_tail = nullptr;

@@ -806,9 +806,12 @@ __device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, 
 #define ELFPIE_STRIP_NT 1024  // threads per block
 #define ELFPIE_STRIP_CH 512   // rows per Hessian chunk
 #endif
+#ifndef ELFPIE_STRIP_NT_SMALL
+#define ELFPIE_STRIP_NT_SMALL 512  // threads per block for n_hi <= 256: 6 lines of at most 256 points
+#endif
 template <int N> struct StripShape {
   // rows per chunk: the configured size when it divides N, else half of N (768 -> 384)
-  static constexpr int W = ELFPIE_STRIP_W, NT = ELFPIE_STRIP_NT,
+  static constexpr int W = ELFPIE_STRIP_W, NT = N <= 256 ? ELFPIE_STRIP_NT_SMALL : ELFPIE_STRIP_NT,
                        CH = ELFPIE_STRIP_CH >= N ? N : (N % ELFPIE_STRIP_CH == 0 ? ELFPIE_STRIP_CH : N / 2);
   static_assert(N % CH == 0, "whole chunks");
 };
