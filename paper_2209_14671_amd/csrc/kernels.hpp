@@ -776,10 +776,10 @@ template <> struct LineRadix<192> { static constexpr int R1 = 16, R2 = 12, R3 = 
 template <> struct LineRadix<384> { static constexpr int R1 = 8, R2 = 8, R3 = 6; };
 template <> struct LineRadix<768> { static constexpr int R1 = 16, R2 = 8, R3 = 6; };
 
-template <class T, int N, bool INV, int NT, int NL>
+template <class T, int N, bool INV, int NT, int NL, int PITCH = N + 1>
 __device__ __forceinline__ void fft_lines_inplace(cx<T>* buf, const cx<T>* twl, int tid) {
   using Rd = LineRadix<N>;
-  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3, PITCH = N + 1;
+  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3;
   StockhamPass<T, N, R1, 1, INV, NT, ceil_div(NL * (N / R1), NT), PITCH, 1, NL>::run(buf, 0, NL, twl, tid);
   StockhamPass<T, N, R2, R1, INV, NT, ceil_div(NL * (N / R2), NT), PITCH, 1, NL>::run(buf, 0, NL, twl, tid);
   if constexpr (R3 > 1)
@@ -815,12 +815,27 @@ template <int N> struct StripShape {
                        CH = ELFPIE_STRIP_CH >= N ? N : (N % ELFPIE_STRIP_CH == 0 ? ELFPIE_STRIP_CH : N / 2);
   static_assert(N % CH == 0, "whole chunks");
 };
+#ifndef ELFPIE_STRIP_PAD
+#define ELFPIE_STRIP_PAD 1
+#endif
+// Line pitch (elements) of the strip's LDS lines.  Lanes of a pass walk the lines fastest
+// (line m, butterfly j = b / NL), so with a pitch of N + 1 lines m and m + 1 start one
+// element apart and the few lines of a strip share banks with the butterflies next to
+// them; these pitches (an exhaustive search of the bank load of every pass, 64 banks of
+// 4 bytes) spread them over the banks.
+constexpr int strip_pitch(int n, int elem_bytes) {
+  if (!ELFPIE_STRIP_PAD) return n + 1;
+  if (elem_bytes == 8)
+    return n == 128 ? 137 : n == 256 ? 261 : n == 384 ? 395 : n == 512 ? 523 : n == 768 ? 795 : n == 1024 ? 1051 : n + 1;
+  return n == 128 ? 131 : n == 256 ? 259 : n + 1;
+}
 
 template <class T, int N>
 __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, const cx<T>* T1, cx<T>* T2,
                                                                   const cx<T>* tw, TailArgs ta) {
   using Sh = StripShape<N>;
-  constexpr int W = Sh::W, NT = Sh::NT, CH = Sh::CH, NL = W + 4, PITCH = N + 1, OW = W + 2, OH = CH + 2;
+  constexpr int W = Sh::W, NT = Sh::NT, CH = Sh::CH, NL = W + 4, OW = W + 2, OH = CH + 2;
+  constexpr int PITCH = strip_pitch(N, sizeof(cx<T>));
   __shared__ cx<T> buf[NL * PITCH];     // line l = column c0 - 2 + l
   __shared__ T sa[NL * N], sp[NL * N];  // |O| and angle(O), line-major
   __shared__ T om[6][OW * OH];          // omega: 3 components of |O|, then of angle(O)
@@ -854,7 +869,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
     }
   }
   __syncthreads();
-  fft_lines_inplace<T, N, true, NT, NL>(buf, twl, tid);
+  fft_lines_inplace<T, N, true, NT, NL, PITCH>(buf, twl, tid);
   for (int p = tid; p < NL * N; p += NT) {
     const int l = p / N, y = p % N, c = c0 - 2 + l;
     const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
@@ -980,7 +995,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   }
   if (a.want_grad) {
     // forward DFT along the own columns (lines 2 .. W + 1), then store
-    fft_lines_inplace<T, N, false, NT, W>(buf + 2 * PITCH, twl, tid);
+    fft_lines_inplace<T, N, false, NT, W, PITCH>(buf + 2 * PITCH, twl, tid);
     constexpr int EPT = ceil_div(W * N, NT);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
