@@ -34,6 +34,9 @@ template <> struct BigLed<256> {
 template <> struct BigLed<192> {
   static constexpr int RB = 8, RNT = 256, W = 16, CNT = 512;
 };
+#ifndef ELFPIE_BIG_XCD
+#define ELFPIE_BIG_XCD 1  // XCD-aware workgroup order in the column kernel
+#endif
 
 // A: K x nband x N (band row yb = y - y_min), unnormalised inverse DFT of the rows.
 template <class T, int N>
@@ -78,7 +81,14 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
   __shared__ cx<T> twl[N];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
-  const int s = blockIdx.x, k = blockIdx.y;
+  // Workgroups go to the 8 XCDs in turn (linear id modulo 8), so workgroup b is
+  // renumbered so that each XCD runs whole LEDs: the neighbouring strips of an LED read
+  // overlapping column segments of A and the measured image, which then share that
+  // XCD's L2 instead of being fetched once per XCD.
+  int b = blockIdx.y * NSTRIP + blockIdx.x;
+  const int nblk = gridDim.y * NSTRIP;
+  if (ELFPIE_BIG_XCD && nblk % 8 == 0) b = (b % 8) * (nblk / 8) + b / 8;
+  const int s = b % NSTRIP, k = b / NSTRIP;
   const int c0 = s * W;
   const int nband = a.y_max - a.y_min + 1;
   const int mode = a.mode;
