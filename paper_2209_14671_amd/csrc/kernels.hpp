@@ -139,6 +139,17 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
   if (a.t_bump && k == 0 && tid == 0) *a.t_bump = *a.t_bump + 1;
 }
 
+#ifndef ELFPIE_LED_XCD
+#define ELFPIE_LED_XCD 1
+#endif
+// Workgroup b of a launch of n runs on XCD b mod 8.  Renumbering b so that each XCD takes
+// a run of consecutive LEDs (neighbours in the LED grid, whose spectrum windows overlap)
+// lets their window reads share that XCD's L2.  A bijection of 0 .. n - 1 for any n.
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  const int q = n / 8, r = n % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
 // Every pass of each 2-D transform is spread over the whole block (StockhamPass).
 // SCALED: compiled with the Sec. 6.3 fidelity scalings (used only for them).
 // STORED: the LED_STORED mode (fields read, not recomputed), in its own instantiation.
@@ -169,7 +180,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
-  const int k = blockIdx.x;
+  const int k = ELFPIE_LED_XCD ? xcd_order(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   led_bump_step(a, k, tid);
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
