@@ -22,7 +22,10 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr size_t kAlign = 256;
-constexpr int kGraphIters = 8;  // iterations per replayed graph
+// Iterations per replayed graph, largest first: a run of n iterations replays n / 32
+// graphs of 32, then graphs of 8, then of 1 (each replay adds a launch gap of a few us).
+constexpr int kGraphSizes[] = {32, 8, 1};
+constexpr int kGraphLevels = sizeof kGraphSizes / sizeof kGraphSizes[0];
 #ifndef ELFPIE_FUSE_PUPIL
 #define ELFPIE_FUSE_PUPIL 1
 #endif
@@ -317,10 +320,11 @@ struct elfpie_plan {
   char* ws = nullptr;
   int device = 0;
   hipStream_t cap = nullptr;  // graph capture stream (captures cannot use the legacy NULL stream)
-  hipGraphExec_t gexec = nullptr;   // non-null once the graphs below exist
-  // run graphs: kGraphIters and 1 iterations; with the row form also chained variants
-  // (T1 ready and a pupil update pending at the start, and left so at the end)
-  static constexpr int kGraphs = 4;
+  bool gvalid = false;  // the graphs below belong to gkey; a null one is captured on first use
+  // run graphs [level][cont] of kGraphSizes[level] iterations; cont (row form only): a
+  // replay that continues a chain (T1 ready and a pupil update pending at the start, and
+  // left so at the end)
+  static constexpr int kGraphs = 2 * kGraphLevels;
   hipGraphExec_t gexecs[kGraphs] = {};
   hipGraph_t graphs[kGraphs] = {};
   elfpie_state gkey{};
@@ -1254,24 +1258,30 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   if (n_iter == 0) return ELFPIE_OK;
   const bool chain = tb.rowupd;
   // the graphs bake in every pointer of the iteration: reuse them only for the same ones
-  const bool same = pl->gexec && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
+  const bool same = pl->gvalid && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
                     pl->gkey_hist == d_loss_hist;
   if (!same) {
-    // (re)capture: graphs of kGraphIters iterations and of a single iteration, each a
-    // whole run; with the row form, each of them opening a chain and continuing one
     for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
       if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
       if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
       pl->gexecs[g] = nullptr;
       pl->graphs[g] = nullptr;
     }
-    pl->gexec = nullptr;
-    for (int g = 0; g < (chain ? 4 : 2); ++g) {
-      const int reps = g % 2 == 0 ? kGraphIters : 1;
-      const bool cont = g >= 2;
+    pl->gkey = *st;
+    pl->gkey_meas = meas;
+    pl->gkey_hist = d_loss_hist;
+    pl->gvalid = true;
+  }
+  // one replay of graph (level, cont), captured on first use: each graph is a whole run
+  // of its iterations; with the row form it opens a chain (cont false) or continues one
+  auto replay = [&](int level, bool cont) -> elfpie_status {
+    const int g = 2 * level + (cont ? 1 : 0);
+    if (!pl->gexecs[g]) {
+      if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
+      pl->graphs[g] = nullptr;
       HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
       const elfpie_status r = dispatch(pl, [&](auto ops) {
-        return decltype(ops)::iterations(pl, st, meas, reps, d_loss_hist, pl->cap, cont, !chain);
+        return decltype(ops)::iterations(pl, st, meas, kGraphSizes[level], d_loss_hist, pl->cap, cont, !chain);
       });
       hipGraph_t gr = nullptr;
       const hipError_t ec = hipStreamEndCapture(pl->cap, &gr);
@@ -1283,28 +1293,21 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
       pl->graphs[g] = gr;
       HIP_TRY(pl, hipGraphInstantiate(&pl->gexecs[g], gr, nullptr, nullptr, 0));
     }
-    pl->gexec = pl->gexecs[0];
-    pl->gkey = *st;
-    pl->gkey_meas = meas;
-    pl->gkey_hist = d_loss_hist;
-  }
+    HIP_TRY(pl, hipGraphLaunch(pl->gexecs[g], s));
+    return ELFPIE_OK;
+  };
+  // the first replay opens the chain, the others continue it, a last launch closes it
+  int left = n_iter;
+  bool opened = false;
+  for (int level = 0; level < kGraphLevels; ++level)
+    for (; left >= kGraphSizes[level]; left -= kGraphSizes[level]) {
+      CHECK(replay(level, chain && opened));
+      opened = true;
+    }
   if (chain) {
-    // the first replay opens the chain, the others continue it, a last launch closes it
-    bool opened = false;
-    for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) {
-      HIP_TRY(pl, hipGraphLaunch(pl->gexecs[opened ? 2 : 0], s));
-      opened = true;
-    }
-    for (int i = 0; i < n_iter % kGraphIters; ++i) {
-      HIP_TRY(pl, hipGraphLaunch(pl->gexecs[opened ? 3 : 1], s));
-      opened = true;
-    }
     const elfpie_status r =
         dispatch(pl, [&](auto ops) { return decltype(ops)::close_run(pl, st, d_loss_hist, s); });
     if (r != ELFPIE_OK) return r;
-  } else {
-    for (int i = 0; i + kGraphIters <= n_iter; i += kGraphIters) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[0], s));
-    for (int i = 0; i < n_iter % kGraphIters; ++i) HIP_TRY(pl, hipGraphLaunch(pl->gexecs[1], s));
   }
   if (checked) {
     HIP_TRY(pl, hipStreamSynchronize(s));
@@ -1355,7 +1358,7 @@ elfpie_status elfpie_plan_set_penalty(elfpie_plan* pl, double alpha, double beta
     return set_err(pl, ELFPIE_E_INVALID, "alpha and beta must be finite and >= 0");
   pl->prob.alpha = alpha;
   pl->prob.beta = beta;
-  pl->gexec = nullptr;  // captured graphs hold the old weights in their launch arguments
+  pl->gvalid = false;  // captured graphs hold the old weights in their launch arguments
   return ELFPIE_OK;
 }
 

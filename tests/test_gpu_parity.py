@@ -280,21 +280,21 @@ def test_long_segment_lists_match_oracle(f32):
 
 
 def test_chained_runs_equal_repeated_steps():
-    """Runs of 5 and then 19 iterations (graphs that open, continue and close a chain:
-    8 + 8 + 3 x 1) against 24 single steps, bit for bit, FP32 and FP64."""
+    """Runs of 5, 19 and 45 iterations (graphs of 32, 8 and 1 iterations that open,
+    continue and close a chain: 5 x 1, 8 + 8 + 3 x 1, 32 + 8 + 5 x 1) against 69 single
+    steps, bit for bit, FP32 and FP64."""
     for f32 in (True, False):
         pair = make_pair(64, 4, 7, f32=f32)
         plan = make_plan(pair, f32)
         meas = dev(pair.meas, f32)
         a = gpu_state(plan, pair, f32)
         b = a.clone()
-        h1 = plan.run(a, meas, 5)
-        h2 = plan.run(a, meas, 19)
-        hs = [plan.step(b, meas) for _ in range(24)]
+        h = [plan.run(a, meas, n) for n in (5, 19, 45)]
+        hs = [plan.step(b, meas) for _ in range(69)]
         torch.cuda.synchronize()
         for k in ("psi", "P", "mu_psi", "v_psi", "delta_psi", "mu_P", "v_P", "delta_P", "t"):
             assert torch.equal(getattr(a, k), getattr(b, k)), (f32, k)
-        assert torch.equal(torch.cat([h1, h2]), torch.stack(hs))
+        assert torch.equal(torch.cat(h), torch.stack(hs))
 
 
 def test_init_state_matches_oracle():
