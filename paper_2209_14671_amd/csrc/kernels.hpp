@@ -142,6 +142,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_XCD
 #define ELFPIE_LED_XCD 1
 #endif
+#ifndef ELFPIE_STRIP_XCD
+#define ELFPIE_STRIP_XCD 1
+#endif
 // Workgroup b of a launch of n runs on XCD b mod 8.  Renumbering b so that each XCD takes
 // a run of consecutive LEDs (neighbours in the LED grid, whose spectrum windows overlap)
 // lets their window reads share that XCD's L2.  A bijection of 0 .. n - 1 for any n.
@@ -862,7 +865,9 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   if (early && pslice) pupil_prefetch<T>(ta.pa, pp, pf);
   __shared__ double pbc[3];
   if (tid == 0 && ta.pupil_ppb && ta.pa.step) bias_corrections(ta.pa.lg1, ta.pa.lg2, double(*ta.pa.t), pbc);
-  const int c0 = blockIdx.x * W;
+  // runs of neighbouring strips per XCD: their column segments share cache lines
+  const int sidx = ELFPIE_STRIP_XCD ? xcd_order(blockIdx.x, N / W) : (int)blockIdx.x;
+  const int c0 = sidx * W;
   const T inv_n = T(a.inv_n), eps = T(a.eps);
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
   {
@@ -1001,8 +1006,8 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
       s0 += red[w][0];
       s1 += red[w][1];
     }
-    a.partial[2 * blockIdx.x + 0] = s0;
-    a.partial[2 * blockIdx.x + 1] = s1;
+    a.partial[2 * sidx + 0] = s0;
+    a.partial[2 * sidx + 1] = s1;
   }
   if (a.want_grad) {
     // forward DFT along the own columns (lines 2 .. W + 1), then store
