@@ -145,6 +145,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_STRIP_XCD
 #define ELFPIE_STRIP_XCD 1
 #endif
+#ifndef ELFPIE_UPD_PAIR
+#define ELFPIE_UPD_PAIR 2  // neighbouring update rows per XCD run
+#endif
 // Workgroup b of a launch of n runs on XCD b mod 8.  Renumbering b so that each XCD takes
 // a run of consecutive LEDs (neighbours in the LED grid, whose spectrum windows overlap)
 // lets their window reads share that XCD's L2.  A bijection of 0 .. n - 1 for any n.
@@ -1387,7 +1390,12 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
     pupil_block<T, NT>(pa, blockIdx.x - N / RB, tid);
     return;
   }
-  const int r0 = blockIdx.x * RB;
+  // runs of G neighbouring rows per XCD (their contribution segments meet in cache lines
+  // of C), the runs still spread over the XCDs in turn
+  constexpr int G = ELFPIE_UPD_PAIR;
+  int rb = blockIdx.x;
+  if (G > 1 && (N / RB) % (8 * G) == 0) rb = (rb / (8 * G)) * 8 * G + (rb % 8) * G + (rb / 8) % G;
+  const int r0 = rb * RB;
   const bool step = a.step != 0, keep_x = step || a.inv;
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
   if (step && tid == 0) bias_corrections(a.lg1, a.lg2, double(*a.t), sbc);
