@@ -24,6 +24,7 @@ thread_local std::string g_last_error;
 constexpr size_t kAlign = 256;
 // Iterations per replayed graph, largest first: a run of n iterations replays n / 32
 // graphs of 32, then graphs of 8, then of 1 (each replay adds a launch gap of a few us).
+// All are captured on the first run with a given state, stack and history.
 constexpr int kGraphSizes[] = {32, 8, 1};
 constexpr int kGraphLevels = sizeof kGraphSizes / sizeof kGraphSizes[0];
 #ifndef ELFPIE_FUSE_PUPIL
@@ -320,7 +321,7 @@ struct elfpie_plan {
   char* ws = nullptr;
   int device = 0;
   hipStream_t cap = nullptr;  // graph capture stream (captures cannot use the legacy NULL stream)
-  bool gvalid = false;  // the graphs below belong to gkey; a null one is captured on first use
+  bool gvalid = false;  // the graphs below exist and belong to gkey
   // run graphs [level][cont] of kGraphSizes[level] iterations; cont (row form only): a
   // replay that continues a chain (T1 ready and a pupil update pending at the start, and
   // left so at the end)
@@ -1261,24 +1262,20 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   const bool same = pl->gvalid && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
                     pl->gkey_hist == d_loss_hist;
   if (!same) {
+    // (re)capture every graph now, so that later calls with these pointers only replay:
+    // each graph is a whole run of its iterations; with the row form it opens a chain
+    // (cont false) or continues one
+    pl->gvalid = false;
     for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
       if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
       if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
       pl->gexecs[g] = nullptr;
       pl->graphs[g] = nullptr;
     }
-    pl->gkey = *st;
-    pl->gkey_meas = meas;
-    pl->gkey_hist = d_loss_hist;
-    pl->gvalid = true;
-  }
-  // one replay of graph (level, cont), captured on first use: each graph is a whole run
-  // of its iterations; with the row form it opens a chain (cont false) or continues one
-  auto replay = [&](int level, bool cont) -> elfpie_status {
-    const int g = 2 * level + (cont ? 1 : 0);
-    if (!pl->gexecs[g]) {
-      if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
-      pl->graphs[g] = nullptr;
+    for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
+      const int level = g / 2;
+      const bool cont = g % 2 == 1;
+      if (cont && !chain) continue;
       HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
       const elfpie_status r = dispatch(pl, [&](auto ops) {
         return decltype(ops)::iterations(pl, st, meas, kGraphSizes[level], d_loss_hist, pl->cap, cont, !chain);
@@ -1293,7 +1290,13 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
       pl->graphs[g] = gr;
       HIP_TRY(pl, hipGraphInstantiate(&pl->gexecs[g], gr, nullptr, nullptr, 0));
     }
-    HIP_TRY(pl, hipGraphLaunch(pl->gexecs[g], s));
+    pl->gkey = *st;
+    pl->gkey_meas = meas;
+    pl->gkey_hist = d_loss_hist;
+    pl->gvalid = true;
+  }
+  auto replay = [&](int level, bool cont) -> elfpie_status {
+    HIP_TRY(pl, hipGraphLaunch(pl->gexecs[2 * level + (cont ? 1 : 0)], s));
     return ELFPIE_OK;
   };
   // the first replay opens the chain, the others continue it, a last launch closes it
