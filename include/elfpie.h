@@ -200,8 +200,10 @@ elfpie_status elfpie_grad_fields(elfpie_plan *plan, const void *psi, const void 
 elfpie_status elfpie_step(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                           double *d_loss4, void *stream);
 
-/* n_iter iterations (elfpie_step repeated), replayed from a HIP graph captured
- * on first use for these pointers.  d_loss_hist (optional, device, n_iter x 4
+/* n_iter iterations (elfpie_step repeated), replayed from HIP graphs of 32, 8 and
+ * 1 iterations (largest first), all captured by the first call with these state,
+ * stack and history pointers; later calls with the same pointers only replay, so the
+ * first call carries the capture cost.  d_loss_hist (optional, device, n_iter x 4
  * doubles) receives each iteration's loss terms.  checked = 1 waits for the
  * stream at the end and returns ELFPIE_E_NONFINITE if any loss was NaN / Inf;
  * checked = 0 returns at once. */
