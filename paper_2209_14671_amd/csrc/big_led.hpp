@@ -37,6 +37,9 @@ template <> struct BigLed<192> {
 #ifndef ELFPIE_BIG_XCD
 #define ELFPIE_BIG_XCD 1  // XCD-aware workgroup order in the column kernel
 #endif
+#ifndef ELFPIE_BIGROW_XCD
+#define ELFPIE_BIGROW_XCD 1  // and in the row kernels
+#endif
 
 // A: K x nband x N (band row yb = y - y_min), unnormalised inverse DFT of the rows.
 template <class T, int N>
@@ -46,9 +49,12 @@ __global__ __launch_bounds__(BigLed<N>::RNT) void k_big_rows_inv(LedArgs a, cx<T
   __shared__ cx<T> buf[RB * PITCH];
   __shared__ cx<T> twl[N];
   const int tid = threadIdx.x;
-  const int k = blockIdx.y;
+  // runs of neighbouring LEDs per XCD (overlapping spectrum windows share its L2)
+  const int L = ELFPIE_BIGROW_XCD ? xcd_order(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y)
+                               : (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int k = L / gridDim.x;
   const int nband = a.y_max - a.y_min + 1;
-  const int yb0 = blockIdx.x * RB;
+  const int yb0 = (L % gridDim.x) * RB;
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
   const cx<T>* win = static_cast<const cx<T>*>(a.psi) + (size_t)a.win[2 * k] * a.n_hi + a.win[2 * k + 1];
@@ -239,9 +245,12 @@ __global__ __launch_bounds__(BigLed<N>::RNT) void k_big_rows_fwd(LedArgs a, cons
   __shared__ cx<T> buf[RB * PITCH];
   __shared__ cx<T> twl[N];
   const int tid = threadIdx.x;
-  const int k = blockIdx.y;
+  // runs of neighbouring LEDs per XCD (overlapping spectrum windows share its L2)
+  const int L = ELFPIE_BIGROW_XCD ? xcd_order(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y)
+                               : (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int k = L / gridDim.x;
   const int nband = a.y_max - a.y_min + 1;
-  const int yb0 = blockIdx.x * RB;
+  const int yb0 = (L % gridDim.x) * RB;
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
   const cx<T>* Bk = B + (size_t)k * nband * N;
   for (int p = tid; p < RB * N; p += NT) {
