@@ -178,7 +178,7 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
     // the exact anisotropic L1 (omega = sign, rho = |.|) under the intensity or amplitude
     // fidelity, without a branch per pixel (the same arithmetic as the general loop)
     const bool amp = a.fidelity == 0;
-    auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+    auto sgn = [](T d) { return sign_unit(d); };
     for (int p = tid; p < W * N; p += NT) {
       const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;
       const int yd = min(y + 1, N - 1), yu = max(y - 1, 0);

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     // fidelity, without a branch per pixel: clamped reads and selects; the same
     // arithmetic as the general loop below
     const bool amp = a.fidelity == 0;
-    auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+    auto sgn = [](T d) { return sign_unit(d); };
 #pragma unroll
     for (int i = 0; i < MB2; ++i) {
       const int j = jj[i], x = mm[i];
@@ -922,7 +922,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
           const T hxx = vxx ? sl - T(2) * ctr + sr : T(0);
           const T hyy = vyy ? su - T(2) * ctr + sd : T(0);
           const T hxy = vxy ? ctr - sr - sd + srd : T(0);
-          auto sgn = [](T d) { return T((d > T(0)) - (d < T(0))); };
+          auto sgn = [](T d) { return sign_unit(d); };
           om[3 * f + 0][p] = sgn(hxx);
           om[3 * f + 1][p] = sgn(hyy);
           om[3 * f + 2][p] = sgn(hxy);
