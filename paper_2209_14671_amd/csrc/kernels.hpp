@@ -142,6 +142,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_XCD
 #define ELFPIE_LED_XCD 1
 #endif
+#ifndef ELFPIE_LED_TSUM
+#define ELFPIE_LED_TSUM 1
+#endif
 #ifndef ELFPIE_STRIP_XCD
 #define ELFPIE_STRIP_XCD 1
 #endif
@@ -310,6 +313,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     // arithmetic as the general loop below
     const bool amp = a.fidelity == 0;
     auto sgn = [](T d) { return sign_unit(d); };
+    T lpart = T(0);  // this lane's pixels, summed in T and added to the FP64 partial once
 #pragma unroll
     for (int i = 0; i < MB2; ++i) {
       const int j = jj[i], x = mm[i];
@@ -324,13 +328,15 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         const T dxm = (x > 0) ? e - el : T(0);
         const T dym = (y > 0) ? e - eu : T(0);
         const T q = sgn(dxm) - sgn(dx0) + sgn(dym) - sgn(dy0);
-        lsum += double(fabs(dx0) + fabs(dy0));
+        if (ELFPIE_LED_TSUM) lpart += fabs(dx0) + fabs(dy0);
+        else lsum += double(fabs(dx0) + fabs(dy0));
         const cx<T> ov = o[i][r];
         const T i2 = norm2(ov);
         const T fa = i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0);
         o[i][r] = scale(ov, amp ? fa : q);
       }
     }
+    lsum += double(lpart);
   } else {
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
