@@ -40,6 +40,9 @@ template <> struct BigLed<192> {
 #ifndef ELFPIE_BIGROW_XCD
 #define ELFPIE_BIGROW_XCD 1  // and in the row kernels
 #endif
+#ifndef ELFPIE_BIG_TSUM
+#define ELFPIE_BIG_TSUM 1
+#endif
 
 // A: K x nband x N (band row yb = y - y_min), unnormalised inverse DFT of the rows.
 template <class T, int N>
@@ -179,6 +182,7 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
     // fidelity, without a branch per pixel (the same arithmetic as the general loop)
     const bool amp = a.fidelity == 0;
     auto sgn = [](T d) { return sign_unit(d); };
+    T lpart = T(0);  // this lane's pixels, summed in T and added to the FP64 partial once
     for (int p = tid; p < W * N; p += NT) {
       const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;
       const int yd = min(y + 1, N - 1), yu = max(y - 1, 0);
@@ -188,12 +192,14 @@ __global__ __launch_bounds__(BigLed<N>::CNT) void k_big_cols(LedArgs a, const cx
       const T dxm = (x > 0) ? e - el : T(0);
       const T dym = (y > 0) ? e - eu : T(0);
       const T q = sgn(dxm) - sgn(dx0) + sgn(dym) - sgn(dy0);
-      lsum += double(fabs(dx0) + fabs(dy0));
+      if (ELFPIE_BIG_TSUM) lpart += fabs(dx0) + fabs(dy0);
+      else lsum += double(fabs(dx0) + fabs(dy0));
       const cx<T> ov = buf[l * PITCH + y];
       const T i2 = norm2(ov);
       const T fa = i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0);
       buf[l * PITCH + y] = scale(ov, amp ? fa : q);
     }
+    lsum += double(lpart);
   } else
   for (int p = tid; p < W * N; p += NT) {
     const int y = p / W, l = 1 + p % W, x = c0 - 1 + l;

@@ -145,6 +145,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_TSUM
 #define ELFPIE_LED_TSUM 1
 #endif
+#ifndef ELFPIE_STRIP_TSUM
+#define ELFPIE_STRIP_TSUM 1
+#endif
 #ifndef ELFPIE_STRIP_XCD
 #define ELFPIE_STRIP_XCD 1
 #endif
@@ -909,6 +912,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
     // rho = |.| and no branch per position: the same arithmetic, selects for the rest.
     auto omega_pass = [&](auto fast_c) {
     constexpr bool FAST = decltype(fast_c)::value;
+    T ta_ = T(0), tp_ = T(0);
     for (int p = tid; p < OW * OH; p += NT) {
       const int li = p / OH, yi = p % OH;
       const int l = li + 1, y = r0 - 1 + yi, c = c0 - 2 + l;
@@ -932,9 +936,15 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
           om[3 * f + 0][p] = sgn(hxx);
           om[3 * f + 1][p] = sgn(hyy);
           om[3 * f + 2][p] = sgn(hxy);
-          const double lv = double(fabs(hxx)) + double(fabs(hyy)) + double(fabs(hxy));
-          if (f == 0) la += own ? lv : 0.0;
-          else lp += own ? lv : 0.0;
+          if (ELFPIE_STRIP_TSUM) {  // this lane's positions summed in T, added to FP64 per pass
+            const T lv = fabs(hxx) + fabs(hyy) + fabs(hxy);
+            if (f == 0) ta_ += own ? lv : T(0);
+            else tp_ += own ? lv : T(0);
+          } else {
+            const double lv = double(fabs(hxx)) + double(fabs(hyy)) + double(fabs(hxy));
+            if (f == 0) la += own ? lv : 0.0;
+            else lp += own ? lv : 0.0;
+          }
           continue;
         }
         const T hxx = vxx ? src[(l - 1) * N + y0c] - T(2) * ctr + src[(l + 1) * N + y0c] : T(0);
@@ -968,6 +978,8 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
         }
       }
     }
+    la += double(ta_);
+    lp += double(tp_);
     };
     if (a.norm == 0 && !(eps > T(0))) omega_pass(std::true_type{});
     else omega_pass(std::false_type{});
