@@ -762,7 +762,7 @@ __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<
   static_assert(EPT * NT == RPB * N, "whole elements per thread");
   __shared__ cx<T> buf[RPB * PITCH];
   __shared__ cx<T> twl[N];
-  __shared__ double tail_sbc[3];
+  __shared__ double tail_sbc[6];
   __shared__ double tail_red[3][4];
   const int tid = threadIdx.x;
   if (blockIdx.x >= N / RPB) {
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
   constexpr bool early = sizeof(T) == 4;  // FP64 has no registers to spare across the strip
   PupilPre<T> pf;
   if (early && pslice) pupil_prefetch<T>(ta.pa, pp, pf);
-  __shared__ double pbc[3];
+  __shared__ double pbc[6];
   if (tid == 0 && ta.pupil_ppb && ta.pa.step) bias_corrections(ta.pa.lg1, ta.pa.lg2, double(*ta.pa.t), pbc);
   // runs of neighbouring strips per XCD: their column segments share cache lines
   const int sidx = ELFPIE_STRIP_XCD ? xcd_order(blockIdx.x, N / W) : (int)blockIdx.x;
@@ -1169,15 +1169,16 @@ __global__ __launch_bounds__(256) void k_hessian(HessArgs a) {
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, double& v, T& delta, double g1,
-                                               double g2, double eta, double bc1, double bc2) {
+                                               double g2, double eta, double ibc1, double ibc2) {
   const T tg1 = T(g1);
   const cx<T> m = {tg1 * mu.x + (T(1) - tg1) * g.x, tg1 * mu.y + (T(1) - tg1) * g.y};
   const double dxr = double(m.x) - double(g.x), dxi = double(m.y) - double(g.y);
   const double vn = g2 * v + (1.0 - g2) * (dxr * dxr + dxi * dxi);
-  const double ratio = (sqrt(double(delta)) + eta) / (sqrt(vn / bc2) + eta);
-  // gamma1 * mu_hat + (1 - gamma1) g
-  const double sx = g1 * double(m.x) / bc1 + (1.0 - g1) * double(g.x);
-  const double sy = g1 * double(m.y) / bc1 + (1.0 - g1) * double(g.y);
+  const double ratio = (sqrt(double(delta)) + eta) / (sqrt(vn * ibc2) + eta);
+  // gamma1 * mu_hat + (1 - gamma1) g, with mu_hat = m / (1 - g1^t); the fused multiply-add
+  // is written out so that every kernel that inlines this rounds it the same way
+  const double sx = __builtin_fma(g1 * double(m.x), ibc1, (1.0 - g1) * double(g.x));
+  const double sy = __builtin_fma(g1 * double(m.y), ibc1, (1.0 - g1) * double(g.y));
   const cx<T> step = {T(ratio * sx), T(ratio * sy)};
   x = x - step;
   delta = tg1 * delta + (T(1) - tg1) * norm2(step);
@@ -1187,10 +1188,14 @@ __device__ __forceinline__ void adabelief_elem(cx<T>& x, cx<T> g, cx<T>& mu, dou
 
 // 1 - g1^t, 1 - g2^t and 1 - g1^(t+1) for step t >= 1, from lg = log2(g) (computed
 // once on the host; -inf for g = 0): g^t = 2^(t lg), a fraction of the cost of pow.
+// bc[3 .. 5] are their reciprocals, so that each element multiplies instead of dividing.
 __device__ __forceinline__ void bias_corrections(double lg1, double lg2, double t, double* bc) {
   bc[0] = 1.0 - exp2(t * lg1);
   bc[1] = 1.0 - exp2(t * lg2);
   bc[2] = 1.0 - exp2((t + 1.0) * lg1);
+  bc[3] = 1.0 / bc[0];
+  bc[4] = 1.0 / bc[1];
+  bc[5] = 1.0 / bc[2];
 }
 
 // The update rule of the plan (ELFPIE_OPT_*) for one element: Eq. 19, or for the
@@ -1200,7 +1205,7 @@ template <class T>
 __device__ __forceinline__ void optimizer_elem(int opt, cx<T>& x, cx<T> g, cx<T>& mu, double& v, T& delta,
                                                double g1, double g2, double eta, double lr, const double* bc) {
   if (opt == 0) {
-    adabelief_elem(x, g, mu, v, delta, g1, g2, eta, bc[0], bc[1]);
+    adabelief_elem(x, g, mu, v, delta, g1, g2, eta, bc[3], bc[4]);
     return;
   }
   if (opt == 1) {
@@ -1212,15 +1217,15 @@ __device__ __forceinline__ void optimizer_elem(int opt, cx<T>& x, cx<T> g, cx<T>
   double sx, sy, vn;
   if (opt == 2) {  // NAdam: moments of g; look-ahead mean
     vn = g2 * v + (1.0 - g2) * (double(g.x) * double(g.x) + double(g.y) * double(g.y));
-    sx = g1 * double(m.x) / bc[2] + (1.0 - g1) * double(g.x) / bc[0];
-    sy = g1 * double(m.y) / bc[2] + (1.0 - g1) * double(g.y) / bc[0];
+    sx = __builtin_fma(g1 * double(m.x), bc[5], (1.0 - g1) * double(g.x) * bc[3]);
+    sy = __builtin_fma(g1 * double(m.y), bc[5], (1.0 - g1) * double(g.y) * bc[3]);
   } else {  // AdaBelief: belief (g - m)^2 plus eps
     const double dxr = double(g.x) - double(m.x), dxi = double(g.y) - double(m.y);
     vn = g2 * v + (1.0 - g2) * (dxr * dxr + dxi * dxi) + eta;
-    sx = double(m.x) / bc[0];
-    sy = double(m.y) / bc[0];
+    sx = double(m.x) * bc[3];
+    sy = double(m.y) * bc[3];
   }
-  const double f = lr / (sqrt(vn / bc[1]) + eta);
+  const double f = lr / (sqrt(vn * bc[4]) + eta);
   x = x - cx<T>{T(f * sx), T(f * sy)};
   mu = m;
   v = vn;
@@ -1296,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
   constexpr int GB = ELFPIE_UPD_GB;
   using cint = const __attribute__((address_space(4))) int;  // read-only: wave-uniform reads go scalar
   __shared__ int4 stab[kMaxLo];  // per support row: first column, last column, row base (rowoff - xlo)
-  __shared__ double sbc[3];
+  __shared__ double sbc[6];
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
   if (tile >= a.ntiles) {
@@ -1397,7 +1402,7 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
   using cint = const __attribute__((address_space(4))) int;  // wave-uniform reads go scalar
   __shared__ cx<T> buf[RB * PITCH];
   __shared__ cx<T> twl[N];
-  __shared__ double sbc[3];
+  __shared__ double sbc[6];
   __shared__ double fred[3][4];
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= N / RB + a.pupil_blocks) {  // this iteration's loss
@@ -1631,7 +1636,7 @@ __device__ __forceinline__ void tail_block(const TailArgs& ta, int vb, int tid, 
 // An iteration's tail as a launch of its own.
 template <class T>
 __global__ __launch_bounds__(256) void k_tail(TailArgs ta) {
-  __shared__ double sbc[3];
+  __shared__ double sbc[6];
   __shared__ double red[3][4];
   tail_block<T, 256>(ta, blockIdx.x, threadIdx.x, sbc, red);
 }
