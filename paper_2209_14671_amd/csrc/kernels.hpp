@@ -188,7 +188,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 
   __shared__ cx<T> img[N * PITCH];
   __shared__ cx<T> twl[N];
-  __shared__ int sxlo[N], sxhi[N], sroff[N];
+  __shared__ int4 srow[N];  // per row: first and last support column, offset of s - first
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
@@ -198,9 +198,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
   for (int i = tid; i < N; i += NT) {
     twl[i] = static_cast<const cx<T>*>(a.tw)[i];
-    sxlo[i] = a.xlo[i];
-    sxhi[i] = a.xhi[i];
-    sroff[i] = a.rowoff[i];
+    srow[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   }
   const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
   const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
@@ -250,7 +248,8 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       for (int i = 0; i < GB; ++i) {
         const int p = tid + (i0 + i) * NT;
         const int y = p / N, x = p % N;
-        in[i] = x >= sxlo[y] && x <= sxhi[y];
+        const int4 rw = srow[y];
+        in[i] = x >= rw.x && x <= rw.y;
         pv[i] = czero<T>();
         wv[i] = czero<T>();
         if (in[i]) {
@@ -421,9 +420,9 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int y = j + r * R1;
-        const int lo = sxlo[y];
-        if (x >= lo && x <= sxhi[y]) {
-          const int s = sroff[y] + x - lo;
+        const int4 rw = srow[y];
+        if (x >= rw.x && x <= rw.y) {
+          const int s = rw.z + x;
           const cx<T> yv = scale(Y[i][r], sc);
           C[s] = cmulc(pw[r], yv);
           D[s] = cmulc(ww[r], yv);
@@ -474,7 +473,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
 
   __shared__ cx<T> img[N * PITCH];
   __shared__ cx<T> twl[N];
-  __shared__ int sxlo[N], sxhi[N], sroff[N];
+  __shared__ int4 srow[N];  // per row: first and last support column, offset of s - first
   __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
@@ -486,9 +485,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
   cx<T>* F = static_cast<cx<T>*>(a.fields);
   for (int i = tid; i < N; i += NT) {
     twl[i] = static_cast<const cx<T>*>(a.tw)[i];
-    sxlo[i] = a.xlo[i];
-    sxhi[i] = a.xhi[i];
-    sroff[i] = a.rowoff[i];
+    srow[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
   }
   const int mode = a.mode;
   const bool stored = (mode & LED_STORED) != 0;
@@ -528,7 +525,8 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
         for (int i = 0; i < GB; ++i) {
           const int p = tid + (i0 + i) * NT;
           const int y = p / N, x = p % N;
-          img[y * PITCH + x] = (x >= sxlo[y] && x <= sxhi[y]) ? pv[i] * wv[i] : czero<T>();
+          const int4 rw = srow[y];
+          img[y * PITCH + x] = (x >= rw.x && x <= rw.y) ? pv[i] * wv[i] : czero<T>();
         }
       }
       __syncthreads();
@@ -648,9 +646,9 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led_mux(LedArgs a) {
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int y = fj[i] + r * R1;
-        const int lo = sxlo[y];
-        if (x >= lo && x <= sxhi[y]) {
-          const int s = sroff[y] + x - lo;
+        const int4 rw = srow[y];
+        if (x >= rw.x && x <= rw.y) {
+          const int s = rw.z + x;
           const cx<T> yv = scale(Y[i][r], sc);
           C[s] = cmulc(P[y * N + x], yv);
           D[s] = cmulc(win[(size_t)y * a.n_hi + x], yv);
