@@ -145,6 +145,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_TSUM
 #define ELFPIE_LED_TSUM 1
 #endif
+#ifndef ELFPIE_LED_NBR
+#define ELFPIE_LED_NBR 1
+#endif
 #ifndef ELFPIE_STRIP_TSUM
 #define ELFPIE_STRIP_TSUM 1
 #endif
@@ -281,7 +284,11 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const T osc = stored ? T(1) : sc;  // stored fields are scaled already
   const T eps = T(a.eps);
   const T gam = T(a.fid_gamma);
-  T* eb = reinterpret_cast<T*>(img);  // real residual, row pitch PITCH
+  // real residual, row pitch PITCH, one row and one element into the (now dead) tile, so
+  // that the neighbour reads of the loop below may step one row or column off the grid
+  // without leaving the array (such values are discarded by the boundary selects)
+  static_assert(2 * N * PITCH > (N + 1) * PITCH + N, "room for the shifted residual");
+  T* eb = reinterpret_cast<T*>(img) + (ELFPIE_LED_NBR ? PITCH + 1 : 0);
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
     const int j = jj[i], x = mm[i];
@@ -319,11 +326,11 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 #pragma unroll
     for (int i = 0; i < MB2; ++i) {
       const int j = jj[i], x = mm[i];
-      const int xr = min(x + 1, N - 1), xl = max(x - 1, 0);
+      const int xr = ELFPIE_LED_NBR ? x + 1 : min(x + 1, N - 1), xl = ELFPIE_LED_NBR ? x - 1 : max(x - 1, 0);
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
         const int y = j + r * R1;
-        const int yd = min(y + 1, N - 1), yu = max(y - 1, 0);
+        const int yd = ELFPIE_LED_NBR ? y + 1 : min(y + 1, N - 1), yu = ELFPIE_LED_NBR ? y - 1 : max(y - 1, 0);
         const T e = E(y, x), er = E(y, xr), ed = E(yd, x), el = E(y, xl), eu = E(yu, x);
         const T dx0 = (x < N - 1) ? er - e : T(0);
         const T dy0 = (y < N - 1) ? ed - e : T(0);
