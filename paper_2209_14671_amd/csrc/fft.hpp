@@ -24,7 +24,11 @@ namespace elfpie {
 // TS / ES are the compile-time transform and element strides, so every LDS address
 // of a butterfly is one base register plus immediate offsets.  NTR is the number of
 // transforms when known at compile time (0: the runtime value ntr).
-template <class T, int N, int R, int NS, bool INV, int NT, int MAXB, int TS, int ES, int NTR = 0>
+// TWB selects the twiddle table: false, the natural table above; true, a table laid out
+// per butterfly class, tw[(j mod NS) R + r] = exp(-2 pi i r (j mod NS) / (NS R)), so that the
+// R - 1 twiddles of a butterfly are one address plus immediate offsets.
+template <class T, int N, int R, int NS, bool INV, int NT, int MAXB, int TS, int ES, int NTR = 0,
+          bool TWB = false>
 struct StockhamPass {
   static constexpr int BPT = N / R;            // butterflies per transform
   static_assert(N % (NS * R) == 0, "radix product must divide N");
@@ -61,7 +65,7 @@ struct StockhamPass {
         if (NS > 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            cx<T> w = tw[r * jm * (N / (NS * R))];
+            cx<T> w = TWB ? tw[jm * R + r] : tw[r * jm * (N / (NS * R))];
             if (INV) w.y = -w.y;
             v[i][r] = v[i][r] * w;
           }

@@ -148,6 +148,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_NBR
 #define ELFPIE_LED_NBR 1
 #endif
+#ifndef ELFPIE_LED_TWB
+#define ELFPIE_LED_TWB 1
+#endif
 #ifndef ELFPIE_STRIP_TSUM
 #define ELFPIE_STRIP_TSUM 1
 #endif
@@ -173,6 +176,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   using Sh = LedShape<N>;
   constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
   static_assert(R1 * R2 == N, "two-pass decomposition");
+  constexpr bool TWB = ELFPIE_LED_TWB != 0;
   constexpr int MB1 = ceil_div(N * (N / R1), NT);
   constexpr int MB2 = ceil_div(N * (N / R2), NT);
   static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
@@ -181,18 +185,21 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   static_assert(PPT * NT == N * N && PPT % GB == 0, "the gather covers the tile exactly");
   // row passes (transform stride PITCH) and column passes (element stride PITCH)
   using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
-  using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1>;
+  using P2iR = StockhamPass<T, N, R2, R1, true, NT, MB2, PITCH, 1, 0, TWB>;
   using P1iC = StockhamPass<T, N, R1, 1, true, NT, MB1, 1, PITCH, N>;
-  using P2iC = StockhamPass<T, N, R2, R1, true, NT, MB2, 1, PITCH, N>;
+  using P2iC = StockhamPass<T, N, R2, R1, true, NT, MB2, 1, PITCH, N, TWB>;
   using P1fR = StockhamPass<T, N, R1, 1, false, NT, MB1, PITCH, 1, N>;
-  using P2fR = StockhamPass<T, N, R2, R1, false, NT, MB2, PITCH, 1, N>;
+  using P2fR = StockhamPass<T, N, R2, R1, false, NT, MB2, PITCH, 1, N, TWB>;
   using P1fC = StockhamPass<T, N, R1, 1, false, NT, MB1, 1, PITCH>;
-  using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH>;
+  using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH, 0, TWB>;
 
   __shared__ cx<T> img[N * PITCH];
   __shared__ cx<T> twl[N];
   __shared__ int4 srow[N];  // per row: first and last support column, offset of s - first
   __shared__ double red[NT / 64];
+  // the second passes' twiddles per butterfly class (R1 classes of R2 entries)
+  __shared__ cx<T> twb_s[TWB ? N : 1];
+  const cx<T>* twb = TWB ? twb_s : twl;
 
   const int tid = threadIdx.x;
   const int k = ELFPIE_LED_XCD ? xcd_order(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -202,6 +209,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   for (int i = tid; i < N; i += NT) {
     twl[i] = static_cast<const cx<T>*>(a.tw)[i];
     srow[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
+    if (TWB) twb_s[i] = static_cast<const cx<T>*>(a.tw)[(i % R2) * (i / R2)];  // W_N^(r jm), N = R1 R2
   }
   const int y0 = a.win[2 * k], x0 = a.win[2 * k + 1];
   const cx<T>* win = psi + (size_t)y0 * a.n_hi + x0;
@@ -272,11 +280,11 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     // inverse DFT: rows that hold support pixels, then every column
     const int nband = a.y_max - a.y_min + 1;
     P1iR::run(img, a.y_min, nband, twl, tid);
-    P2iR::run(img, a.y_min, nband, twl, tid);
+    P2iR::run(img, a.y_min, nband, twb, tid);
     P1iC::run(img, 0, N, twl, tid);
     P2iC::coords(N, tid, mm, jj, lv);
     load_meas();  // in flight during the last pass's loads
-    P2iC::load(img, 0, mm, jj, lv, twl, o);
+    P2iC::load(img, 0, mm, jj, lv, twb, o);
   }
   __syncthreads();
 
@@ -401,12 +409,12 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 
   // forward DFT of dL/d(conj o): all rows, then only columns that hold support
   P1fR::run(img, 0, N, twl, tid);
-  P2fR::run(img, 0, N, twl, tid);
+  P2fR::run(img, 0, N, twb, tid);
   const int ncol = a.x_max - a.x_min + 1;
   P1fC::run(img, a.x_min, ncol, twl, tid);
   P2fC::coords(ncol, tid, mm, jj, lv);
   cx<T> Y[MB2][R2];
-  P2fC::load(img, a.x_min, mm, jj, lv, twl, Y);
+  P2fC::load(img, a.x_min, mm, jj, lv, twb, Y);
 
   // contributions on the support; the window and pupil loads are issued together
   cx<T>* C = static_cast<cx<T>*>(a.C) + (size_t)k * a.S;
