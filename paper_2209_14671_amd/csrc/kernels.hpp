@@ -151,6 +151,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_LED_TWB
 #define ELFPIE_LED_TWB 1
 #endif
+#ifndef ELFPIE_LED_AMPC
+#define ELFPIE_LED_AMPC 1
+#endif
 #ifndef ELFPIE_STRIP_TSUM
 #define ELFPIE_STRIP_TSUM 1
 #endif
@@ -297,6 +300,27 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   // without leaving the array (such values are discarded by the boundary selects)
   static_assert(2 * N * PITCH > (N + 1) * PITCH + N, "room for the shifted residual");
   T* eb = reinterpret_cast<T*>(img) + (ELFPIE_LED_NBR ? PITCH + 1 : 0);
+  // the gradient and loss modes under the amplitude or intensity fidelity (no field or
+  // image output): the residual with the fidelity fixed outside the pixel loop
+  const bool plain = ELFPIE_LED_AMPC && !SCALED && need_e && !(mode & (LED_FIELDS | LED_INTENS)) &&
+                     (a.fidelity == 0 || a.fidelity == 1);
+  auto residual_only = [&](auto amp_c) {
+    constexpr bool AMP = decltype(amp_c)::value;
+#pragma unroll
+    for (int i = 0; i < MB2; ++i) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int y = jj[i] + r * R1;
+        const cx<T> ov = scale(o[i][r], osc);
+        o[i][r] = ov;
+        const T i2 = norm2(ov), m = mv[i][r];
+        eb[y * PITCH + mm[i]] = AMP ? sqrt_t(i2) - sqrt_t(m > T(0) ? m : T(0)) : i2 - m;
+      }
+    }
+  };
+  if (plain && a.fidelity == 0) residual_only(std::true_type{});
+  else if (plain) residual_only(std::false_type{});
+  else
 #pragma unroll
   for (int i = 0; i < MB2; ++i) {
     const int j = jj[i], x = mm[i];
@@ -328,9 +352,10 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     // the exact anisotropic L1 (omega = sign, rho = |.|) under the intensity or amplitude
     // fidelity, without a branch per pixel: clamped reads and selects; the same
     // arithmetic as the general loop below
-    const bool amp = a.fidelity == 0;
     auto sgn = [](T d) { return sign_unit(d); };
     T lpart = T(0);  // this lane's pixels, summed in T and added to the FP64 partial once
+    auto fast_pass = [&](auto amp_c) {
+    constexpr bool AMP = decltype(amp_c)::value;
 #pragma unroll
     for (int i = 0; i < MB2; ++i) {
       const int j = jj[i], x = mm[i];
@@ -348,11 +373,17 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         if (ELFPIE_LED_TSUM) lpart += fabs(dx0) + fabs(dy0);
         else lsum += double(fabs(dx0) + fabs(dy0));
         const cx<T> ov = o[i][r];
-        const T i2 = norm2(ov);
-        const T fa = i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0);
-        o[i][r] = scale(ov, amp ? fa : q);
+        if constexpr (AMP) {
+          const T i2 = norm2(ov);
+          o[i][r] = scale(ov, i2 > T(0) ? T(0.5) * q * rsqrt_t(i2) : T(0));
+        } else {
+          o[i][r] = scale(ov, q);
+        }
       }
     }
+    };
+    if (a.fidelity == 0) fast_pass(std::true_type{});
+    else fast_pass(std::false_type{});
     lsum += double(lpart);
   } else {
 #pragma unroll
