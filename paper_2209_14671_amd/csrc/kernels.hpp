@@ -463,15 +463,23 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       ww[r] = win[(size_t)y * a.n_hi + x];
     }
     if (live) {
+      // the support tests and offsets of the column's R2 pixels first, each row entry read
+      // whole and used unconditionally (one LDS read, no chain of dependent reads), then
+      // the stores
+      int so[R2];
+      bool ok[R2];
 #pragma unroll
       for (int r = 0; r < R2; ++r) {
-        const int y = j + r * R1;
-        const int4 rw = srow[y];
-        if (x >= rw.x && x <= rw.y) {
-          const int s = rw.z + x;
+        const int4 rw = srow[j + r * R1];
+        ok[r] = (x >= rw.x) & (x <= rw.y);
+        so[r] = ok[r] ? rw.z + x : 0;
+      }
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        if (ok[r]) {
           const cx<T> yv = scale(Y[i][r], sc);
-          C[s] = cmulc(pw[r], yv);
-          D[s] = cmulc(ww[r], yv);
+          C[so[r]] = cmulc(pw[r], yv);
+          D[so[r]] = cmulc(ww[r], yv);
         }
       }
     }
