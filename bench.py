@@ -319,9 +319,24 @@ def cpu_baseline_tiles(cases, flags, budget_s=10.0):
         step_cpu += time.process_time() - c0
         n_led += prob.K
         done += 1
+    model, avail = host_cpu()
     return {"value": n_led / step_wall, "unit": "LED-updates/s", "cores": max(1, round(step_cpu / step_wall)),
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "cores_available": avail,
             "sample": f"one oracle iteration on each of the first {done} tiles (NumPy FP64), {step_wall:.1f} s"}
+
+
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
 
 def cpu_baseline(case, flags, budget_s=12.0, max_iter=100000):
@@ -343,8 +358,9 @@ def cpu_baseline(case, flags, budget_s=12.0, max_iter=100000):
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     K = prob.K
+    model, avail = host_cpu()
     return {"value": K * n / wall, "unit": "LED-updates/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "cores_available": avail,
             "sample": f"{n} oracle iterations of the same workload (NumPy FP64), {wall:.1f} s wall"}
 
 
@@ -415,20 +431,25 @@ def main():
     st = plan.init_state(meas)
     stream = torch.cuda.current_stream()
 
+    # one history buffer for the warm-up and the timed run: the run graphs are keyed on its
+    # address, so the warm-up captures them and the timed run only replays
+    hist_buf = torch.empty((max(args.warmup, args.steps, 1), 4), dtype=torch.float64, device=dev)
     log(f"warmup {args.warmup} iterations")
     if args.warmup:
-        plan.run(st, meas, args.warmup)
+        plan.run(st, meas, args.warmup, history=hist_buf)
     torch.cuda.synchronize()
+    cap0 = plan.stats()["captures"]
 
     log(f"timing {args.steps} iterations")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     ev0.record(stream)
-    hist = plan.run(st, meas, args.steps)
+    hist = plan.run(st, meas, args.steps, history=hist_buf)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    captures_timed = plan.stats()["captures"] - cap0
     ms = ev0.elapsed_time(ev1)
     ms_step = ms / max(args.steps, 1)
     value = K * args.steps / (ms / 1e3)
@@ -464,6 +485,7 @@ def main():
         "iteration_roofline": {"algorithmic_bytes": it_bytes, "achieved_GBs": round(it_gbs, 1),
                                "frac": round(it_gbs / HBM_PEAK_GBS, 4)},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "graph_captures_in_timed_run": captures_timed,
         "source_hash": src_hash,
     }
     if not args.no_cpu_baseline:

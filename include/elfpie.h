@@ -165,7 +165,8 @@ elfpie_status elfpie_plan_info(const elfpie_plan *plan, int32_t *out);
 elfpie_status elfpie_auto_penalty(elfpie_plan *plan, const void *meas, double *alpha_out, void *stream);
 
 /* Sets the plan's penalty weights (Eq. 8), e.g. to elfpie_auto_penalty's value.
- * Host-only; later calls use the new weights.  alpha, beta finite and >= 0. */
+ * Host-only; later calls use the new weights, also the replays of a batch holding
+ * the plan (its graph is captured again).  alpha, beta finite and >= 0. */
 elfpie_status elfpie_plan_set_penalty(elfpie_plan *plan, double alpha, double beta);
 
 /* Forward model, Eq. (1): for every LED, o_k = F_B P M_k Psi; image n is the sum
@@ -200,10 +201,12 @@ elfpie_status elfpie_grad_fields(elfpie_plan *plan, const void *psi, const void 
 elfpie_status elfpie_step(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                           double *d_loss4, void *stream);
 
-/* n_iter iterations (elfpie_step repeated), replayed from HIP graphs of 32, 8 and
- * 1 iterations (largest first), all captured by the first call with these state,
- * stack and history pointers; later calls with the same pointers only replay, so the
- * first call carries the capture cost.  d_loss_hist (optional, device, n_iter x 4
+/* n_iter iterations (elfpie_step repeated), replayed from HIP graphs of 32 iterations
+ * and then at most one each of 16, 8, 4, 2 and 1, all captured by the first call with
+ * these state, stack and history pointers; later calls with the same pointers only
+ * replay, so the first call carries the capture cost.  Graphs are captured again after
+ * elfpie_plan_set_penalty and when a pointer changes; the old ones are destroyed only
+ * after their last replays have finished.  d_loss_hist (optional, device, n_iter x 4
  * doubles) receives each iteration's loss terms.  checked = 1 waits for the
  * stream at the end and returns ELFPIE_E_NONFINITE if any loss was NaN / Inf;
  * checked = 0 returns at once. */
@@ -234,7 +237,12 @@ elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpi
 elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                                   int32_t n_rep, float *ms_out, void *stream);
 
-/* Text of the last error on `plan` (or of the last plan-less call when plan is NULL). */
+/* Graph bookkeeping of `plan` (host query): out[0] = graphs captured so far (elfpie_run's
+ * run graphs and the batch graphs that hold this plan), out[1] = run-graph replays so far.
+ * A caller can check that timed calls only replayed (out[0] unchanged across them).
+ * `out` is HOST, 2 int64. */
+elfpie_status elfpie_plan_stats(const elfpie_plan *plan, int64_t *out);
+
 /* ------------------------------------------------------------------------------------
  * Batches of independent fields of view (tiles), each with its own plan, state and
  * measured stack (sizes and K may differ).  One HIP graph replays one iteration of
@@ -270,6 +278,7 @@ elfpie_status elfpie_batch_tune(elfpie_batch *batch, int32_t n_rep, float *ms_ou
 
 const char *elfpie_batch_last_error(const elfpie_batch *batch);
 
+/* Text of the last error on `plan` (or of the last plan-less call when plan is NULL). */
 const char *elfpie_last_error(const elfpie_plan *plan);
 
 #ifdef __cplusplus

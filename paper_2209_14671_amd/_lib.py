@@ -43,6 +43,7 @@ FUNCTIONS = {
     "elfpie_plan_create": (c_int32, [ctypes.POINTER(ProblemC), c_void_p, c_size_t, ctypes.POINTER(c_void_p)]),
     "elfpie_plan_destroy": (c_int32, [c_void_p]),
     "elfpie_plan_info": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
+    "elfpie_plan_stats": (c_int32, [c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "elfpie_auto_penalty": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]),
     "elfpie_plan_set_penalty": (c_int32, [c_void_p, c_double, c_double]),
     "elfpie_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -23,9 +23,10 @@ thread_local std::string g_last_error;
 
 constexpr size_t kAlign = 256;
 // Iterations per replayed graph, largest first: a run of n iterations replays n / 32
-// graphs of 32, then graphs of 8, then of 1 (each replay adds a launch gap of a few us).
-// All are captured on the first run with a given state, stack and history.
-constexpr int kGraphSizes[] = {32, 8, 1};
+// graphs of 32, then at most one each of 16, 8, 4, 2 and 1 (each replay adds a launch
+// gap of a few us).  All are captured on the first run with a given state, stack and
+// history.
+constexpr int kGraphSizes[] = {32, 16, 8, 4, 2, 1};
 constexpr int kGraphLevels = sizeof kGraphSizes / sizeof kGraphSizes[0];
 #ifndef ELFPIE_FUSE_PUPIL
 #define ELFPIE_FUSE_PUPIL 1
@@ -331,6 +332,15 @@ struct elfpie_plan {
   elfpie_state gkey{};
   const void* gkey_meas = nullptr;
   const double* gkey_hist = nullptr;
+  // recorded on the launch stream after the last replay of the graphs above: a graph
+  // exec is destroyed only once its replays have finished
+  hipEvent_t gdone = nullptr;
+  // bumped whenever launch arguments baked into captured graphs change (the penalty
+  // weights), so that every holder of such a graph (the plan's own, a batch's) captures
+  // again before its next replay
+  uint64_t gen = 0;
+  int64_t captures = 0;  // graphs captured so far (run graphs and batch graphs)
+  int64_t replays = 0;   // graph launches so far
   std::string err;
 
   template <class X> X* at(size_t o) const { return reinterpret_cast<X*>(ws + o); }
@@ -1036,6 +1046,19 @@ elfpie_status check_ptr(elfpie_plan* pl, const void* q, const char* name, bool o
     if (s_ != ELFPIE_OK) return s_;   \
   } while (0)
 
+// Destroy the plan's run graphs after their last replays have finished (destroying an
+// exec whose replays are still in flight frees what the runtime is still using).
+void drop_run_graphs(elfpie_plan* pl) {
+  if (pl->gdone) (void)hipEventSynchronize(pl->gdone);
+  for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
+    if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
+    if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
+    pl->gexecs[g] = nullptr;
+    pl->graphs[g] = nullptr;
+  }
+  pl->gvalid = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1158,16 +1181,16 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
     return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));
+  if (hipEventCreateWithFlags(&pl->gdone, hipEventDisableTiming) != hipSuccess)
+    return cleanup(set_err(pl, ELFPIE_E_DEVICE, "event creation failed"));
   *out = pl;
   return ELFPIE_OK;
 }
 
 elfpie_status elfpie_plan_destroy(elfpie_plan* pl) {
   if (!pl) return ELFPIE_E_INVALID;
-  for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
-    if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
-    if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
-  }
+  drop_run_graphs(pl);
+  if (pl->gdone) (void)hipEventDestroy(pl->gdone);
   if (pl->cap) (void)hipStreamDestroy(pl->cap);
   delete pl;
   return ELFPIE_OK;
@@ -1265,13 +1288,7 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
     // (re)capture every graph now, so that later calls with these pointers only replay:
     // each graph is a whole run of its iterations; with the row form it opens a chain
     // (cont false) or continues one
-    pl->gvalid = false;
-    for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
-      if (pl->gexecs[g]) (void)hipGraphExecDestroy(pl->gexecs[g]);
-      if (pl->graphs[g]) (void)hipGraphDestroy(pl->graphs[g]);
-      pl->gexecs[g] = nullptr;
-      pl->graphs[g] = nullptr;
-    }
+    drop_run_graphs(pl);
     for (int g = 0; g < elfpie_plan::kGraphs; ++g) {
       const int level = g / 2;
       const bool cont = g % 2 == 1;
@@ -1289,6 +1306,7 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
       HIP_TRY(pl, ec);
       pl->graphs[g] = gr;
       HIP_TRY(pl, hipGraphInstantiate(&pl->gexecs[g], gr, nullptr, nullptr, 0));
+      ++pl->captures;
     }
     pl->gkey = *st;
     pl->gkey_meas = meas;
@@ -1297,6 +1315,7 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   }
   auto replay = [&](int level, bool cont) -> elfpie_status {
     HIP_TRY(pl, hipGraphLaunch(pl->gexecs[2 * level + (cont ? 1 : 0)], s));
+    ++pl->replays;
     return ELFPIE_OK;
   };
   // the first replay opens the chain, the others continue it, a last launch closes it
@@ -1312,6 +1331,7 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
         dispatch(pl, [&](auto ops) { return decltype(ops)::close_run(pl, st, d_loss_hist, s); });
     if (r != ELFPIE_OK) return r;
   }
+  HIP_TRY(pl, hipEventRecord(pl->gdone, s));
   if (checked) {
     HIP_TRY(pl, hipStreamSynchronize(s));
     int h = 0;
@@ -1361,7 +1381,10 @@ elfpie_status elfpie_plan_set_penalty(elfpie_plan* pl, double alpha, double beta
     return set_err(pl, ELFPIE_E_INVALID, "alpha and beta must be finite and >= 0");
   pl->prob.alpha = alpha;
   pl->prob.beta = beta;
-  pl->gvalid = false;  // captured graphs hold the old weights in their launch arguments
+  // captured graphs hold the old weights in their launch arguments: the plan's own are
+  // captured again on the next run, and a batch holding this plan sees the new generation
+  pl->gvalid = false;
+  ++pl->gen;
   return ELFPIE_OK;
 }
 
@@ -1373,6 +1396,13 @@ elfpie_status elfpie_stage_timing(elfpie_plan* pl, const elfpie_state* st, const
   if (!ms_out || n_rep < 1) return set_err(pl, ELFPIE_E_INVALID, "ms_out is NULL or n_rep < 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return dispatch(pl, [&](auto ops) { return decltype(ops)::stage_timing(pl, st, meas, n_rep, ms_out, s); });
+}
+
+elfpie_status elfpie_plan_stats(const elfpie_plan* pl, int64_t* out) {
+  if (!pl || !out) return ELFPIE_E_INVALID;
+  out[0] = pl->captures;
+  out[1] = pl->replays;
+  return ELFPIE_OK;
 }
 
 const char* elfpie_last_error(const elfpie_plan* pl) {
@@ -1411,9 +1441,11 @@ struct elfpie_batch {
   hipEvent_t join[kMaxBranch] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after the last replay of exec
   int exec_mode = -1;  // 0: update steps, 1: gradients (tuning)
   int exec_branches = 0;
   std::vector<double*> exec_hist;
+  std::vector<uint64_t> exec_gen;  // each plan's generation when exec was captured
   std::string err;
 };
 
@@ -1450,6 +1482,8 @@ void batch_assign(elfpie_batch* b, int nb) {
 }
 
 void batch_drop_graph(elfpie_batch* b) {
+  // the exec may still be replaying on the caller's stream: wait for its last replay
+  if (b->done) (void)hipEventSynchronize(b->done);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
@@ -1493,8 +1527,12 @@ elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
   b->exec_mode = mode;
   b->exec_branches = b->nbranch;
   b->exec_hist.assign(b->plans.size(), nullptr);
-  if (hist)
-    for (size_t t = 0; t < b->plans.size(); ++t) b->exec_hist[t] = hist[t];
+  b->exec_gen.assign(b->plans.size(), 0);
+  for (size_t t = 0; t < b->plans.size(); ++t) {
+    if (hist) b->exec_hist[t] = hist[t];
+    b->exec_gen[t] = b->plans[t]->gen;
+    ++b->plans[t]->captures;
+  }
   return ELFPIE_OK;
 }
 
@@ -1532,6 +1570,7 @@ elfpie_status elfpie_batch_create(elfpie_plan* const* plans, const elfpie_state*
     if (hipEventCreateWithFlags(&b->join[j], hipEventDisableTiming) != hipSuccess) return fail("event creation");
   }
   if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return fail("event creation");
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) return fail("event creation");
   batch_assign(b, std::min<int>(n_branches, n_tiles));
   *out = b;
   return ELFPIE_OK;
@@ -1545,6 +1584,7 @@ elfpie_status elfpie_batch_destroy(elfpie_batch* b) {
     if (b->join[j]) (void)hipEventDestroy(b->join[j]);
   }
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->done) (void)hipEventDestroy(b->done);
   delete b;
   return ELFPIE_OK;
 }
@@ -1554,8 +1594,9 @@ elfpie_status elfpie_batch_run(elfpie_batch* b, int32_t n_iter, double* const* d
   if (n_iter < 0) return batch_err(b, ELFPIE_E_INVALID, "n_iter must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool same = b->exec && b->exec_mode == 0 && b->exec_branches == b->nbranch;
+  // the same history pointers, and no plan whose captured launch arguments changed since
   for (size_t t = 0; same && t < b->plans.size(); ++t)
-    same = b->exec_hist[t] == (d_loss_hist ? d_loss_hist[t] : nullptr);
+    same = b->exec_hist[t] == (d_loss_hist ? d_loss_hist[t] : nullptr) && b->exec_gen[t] == b->plans[t]->gen;
   // the graph is captured on the batch's own streams and launched on `stream`
   for (elfpie_plan* pl : b->plans) {  // history slot counters and non-finite flags
     k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_ctr), 0, 1);
@@ -1567,6 +1608,7 @@ elfpie_status elfpie_batch_run(elfpie_batch* b, int32_t n_iter, double* const* d
     if (r != ELFPIE_OK) return r;
   }
   for (int i = 0; i < n_iter; ++i) BATCH_TRY(b, hipGraphLaunch(b->exec, s));
+  BATCH_TRY(b, hipEventRecord(b->done, s));
   return ELFPIE_OK;
 }
 
@@ -1591,6 +1633,7 @@ elfpie_status elfpie_batch_tune(elfpie_batch* b, int32_t n_rep, float* ms_out, i
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int i = 0; i < n_rep && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventRecord(b->done, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

@@ -273,12 +273,30 @@ class Plan:
         return l4
 
     def run(self, st: State, meas, n_iter: int, history=True, checked=False):
+        """n_iter iterations replayed from captured graphs.  `history`: True (a new
+        n_iter x 4 FP64 tensor of loss terms), False (none), or a caller-owned contiguous
+        FP64 tensor of at least n_iter x 4, which is filled from its first row.  The graphs
+        are keyed on the state, stack and history pointers, so passing the same history
+        buffer to repeated calls keeps them replay-only."""
         sc = self._state_c(st)
         self._need(meas, self.stack_shape, self.rdtype, "meas")
-        h = torch.empty((max(n_iter, 1), 4), dtype=torch.float64, device=self.device) if history else None
+        if isinstance(history, torch.Tensor):
+            h = history
+            if (h.device != self.device or h.dtype != torch.float64 or not h.is_contiguous() or h.dim() != 2
+                    or h.shape[1] != 4 or h.shape[0] < n_iter):
+                raise ValueError(f"history must be a contiguous float64 tensor of at least ({n_iter}, 4) "
+                                 f"on {self.device}")
+        else:
+            h = torch.empty((max(n_iter, 1), 4), dtype=torch.float64, device=self.device) if history else None
         self._check(self.lib.elfpie_run(self.handle, ctypes.byref(sc), _ptr(meas), int(n_iter), _ptr(h),
                                         1 if checked else 0, _stream()))
-        return h[:n_iter] if history else None
+        return h[:n_iter] if h is not None else None
+
+    def stats(self):
+        """{'captures': graphs captured so far, 'replays': run-graph launches so far}."""
+        out = (ctypes.c_int64 * 2)()
+        self._check(self.lib.elfpie_plan_stats(self.handle, out))
+        return {"captures": int(out[0]), "replays": int(out[1])}
 
     def object_from_spectrum(self, psi):
         self._need(psi, self.spec_shape, self.cdtype, "psi")

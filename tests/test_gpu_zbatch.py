@@ -1,15 +1,20 @@
 """Batches of independent fields of view (one graph replay = one iteration of every tile):
 each tile's trajectory must equal that of its plan run alone, bit for bit, whatever the
-branch count; tuning must leave the states untouched."""
+branch count, and the oracle's to the usual bounds; tuning must leave the states untouched.
+The tiles span every per-LED route: the LDS tile (32-128, FP32 and FP64) and the 192^2 and
+256^2 tiles through HBM scratch."""
 import numpy as np
 import pytest
 
+import oracle as orc
+from helpers import rel_l2
 from pairs import make_pair
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TILES = [(32, 4, 5, True, 0), (64, 4, 7, True, 1), (96, 4, 5, True, 2), (32, 4, 5, False, 3), (128, 4, 5, True, 4)]
+TILES = [(32, 4, 5, True, 0), (64, 4, 7, True, 1), (96, 4, 5, True, 2), (32, 4, 5, False, 3), (128, 4, 5, True, 4),
+         (192, 2, 3, True, 5), (256, 2, 3, True, 6)]
 
 
 def E():
@@ -24,15 +29,68 @@ def dev(x, f32):
     return t.to(torch.float32 if f32 else torch.float64).cuda()
 
 
-def build_tiles():
+def build_tiles(with_pairs=False):
+    """Tiles from the library's initial state, or (with_pairs) from the pairs' oracle
+    states, so that the oracle can follow them."""
     e = E()
-    out = []
+    out, pairs = [], []
     for n_lo, up, grid, f32, seed in TILES:
-        pair = make_pair(n_lo, up, grid, f32=f32, seed=seed, warm_steps=0)
+        pair = make_pair(n_lo, up, grid, f32=f32, seed=seed, warm_steps=1 if with_pairs else 0)
         plan = e.Plan(e.Problem(precision=e.F32 if f32 else e.F64, **pair.kw))
-        st = plan.init_state(dev(pair.meas, f32))
+        if with_pairs:
+            s = pair.state
+            st = e.State(psi=dev(s.psi, f32), P=dev(s.P, f32), mu_psi=dev(s.mu_psi, f32),
+                         v_psi=torch.from_numpy(s.v_psi.copy()).cuda(), delta_psi=dev(s.delta_psi, f32),
+                         mu_P=dev(s.mu_P, f32), v_P=torch.from_numpy(s.v_P.copy()).cuda(),
+                         delta_P=dev(s.delta_P, f32), t=torch.tensor([s.t], dtype=torch.int64).cuda())
+        else:
+            st = plan.init_state(dev(pair.meas, f32))
         out.append((plan, st, dev(pair.meas, f32)))
-    return out
+        pairs.append(pair)
+    return (out, pairs) if with_pairs else out
+
+
+def test_batch_tiles_match_the_oracle():
+    """Two batched iterations of every tile against two oracle iterations from the same
+    state: psi and P within 1e-5 (FP32) or 1e-12 (FP64), loss history likewise."""
+    e = E()
+    tiles, pairs = build_tiles(with_pairs=True)
+    batch = e.Batch(tiles, n_branches=4)
+    hist = batch.run(2)
+    torch.cuda.synchronize()
+    for (plan, st, _), pair, h, (n_lo, _, _, f32, _) in zip(tiles, pairs, hist, TILES):
+        ref, rh = orc.run(pair.state, pair.meas, pair.oprob, 2)
+        tol = 1e-5 if f32 else 1e-12
+        ep = rel_l2(st.psi.cpu().numpy().astype(np.complex128), ref.psi)
+        eP = rel_l2(st.P.cpu().numpy().astype(np.complex128), ref.P)
+        eh = np.max(np.abs(h.cpu().numpy() - rh) / np.abs(rh))
+        print(f"batch tile n_lo={n_lo} f32={f32}: psi {ep:.2e} P {eP:.2e} loss {eh:.2e}")
+        assert ep < tol and eP < tol and eh < tol
+        assert int(st.t.item()) == pair.state.t + 2
+    batch.close()
+
+
+def test_batch_follows_penalty_changes():
+    """A plan's new Eq. 8 weights reach the replays of a batch captured before the change:
+    batch.run(1), set_penalty, batch.run(1) equals the same on the plan alone, bit for bit."""
+    e = E()
+    tiles = build_tiles()[:3]
+    alone = [(p, st.clone(), m) for p, st, m in tiles]
+    batch = e.Batch(tiles, n_branches=2)
+    batch.run(1, history=False)  # no history: the same (null) pointers on both calls
+    torch.cuda.synchronize()
+    for p, st, m in alone:
+        p.run(st, m, 1)
+    torch.cuda.synchronize()
+    tiles[1][0].set_penalty(0.05, 0.02)
+    batch.run(1, history=False)
+    torch.cuda.synchronize()
+    for p, st, m in alone:
+        p.run(st, m, 1)
+    torch.cuda.synchronize()
+    for (p, sb, _), (_, sa, _) in zip(tiles, alone):
+        assert torch.equal(sb.psi, sa.psi) and torch.equal(sb.P, sa.P), p.n_lo
+    batch.close()
 
 
 @pytest.mark.parametrize("branches", [1, 3, 8])

@@ -233,3 +233,73 @@ def test_log_scaling_slope_is_exact_at_zero():
     x = np.array([0.0, 1.0, 3.0])
     assert np.allclose(orc.scaling_slope(x, orc.FID_LOG), [1.0, 0.5, 0.25])
     assert np.allclose(orc.scaling_slope(x, orc.FID_GAMMA, 0.5), [0.0, 0.5, 0.5 / math.sqrt(3.0)])
+
+
+def _l1_features(psi, P, meas, prob, part):
+    """Every feature the L1 terms see: the image differences of the fidelity residual of
+    each LED (Eq. 4 / 5), or the Hessian components of |O| and angle(O) (Eq. 6, 7)."""
+    if part == "fidelity":
+        e = [orc.fidelity_residual(o, m, prob.fidelity, prob.fid_gamma)
+             for o, m in zip(orc.fields(psi, P, prob), meas)]
+        return np.concatenate([np.stack([orc.dx(x), orc.dy(x)]).ravel() for x in e])
+    O = orc.object_from_spectrum(psi)
+    src = [np.abs(O), np.arctan2(O.imag, O.real)]
+    return np.concatenate([H(s).ravel() for s in src for H in (orc.hxx, orc.hyy, orc.hxy)])
+
+
+@pytest.mark.parametrize("part", ["fidelity", "hessian"])
+@pytest.mark.parametrize("norm", [orc.NORM_ANISO, orc.NORM_ISO])
+@pytest.mark.parametrize("fidelity", [orc.FID_INTENSITY, orc.FID_AMPLITUDE])
+def test_exact_l1_gradient_matches_finite_differences_between_kinks(fidelity, norm, part):
+    """l1_eps = 0: the literal L1 of Eq. 4-7 with omega = sign (anisotropic) or c / |c|
+    (isotropic) of Eq. 12 and the zero subgradient of Sec. 3.3.  Between the points where
+    a feature (or, isotropic, a feature pair or triple) vanishes the loss is smooth, so a
+    central difference whose step moves no feature across zero pins omega exactly.  The
+    step is shrunk until no feature changes sign between z - h d and z + h d (checked),
+    and the phase differences stay far from the branch cut of angle()."""
+    alpha, beta = ((0.0, 0.0) if part == "fidelity" else (0.7, 0.4))
+    prob, psi, P, meas = make_problem(fidelity, norm, eps=0.0, alpha=alpha, beta=beta)
+    rng = np.random.default_rng(11)
+    if part == "fidelity":
+        _, g, _ = orc.loss_and_grad(psi, P, meas, prob)
+        fun = lambda z: orc.loss(z, P, meas, prob)  # noqa: E731
+    else:
+        _, _, g = orc.hessian_loss_and_grad(psi, prob)
+
+        def fun(z):
+            LA, LP, _ = orc.hessian_loss_and_grad(z, prob, want_grad=False)
+            return alpha * LA + beta * LP
+    c0 = _l1_features(psi, P, meas, prob, part)
+    assert np.min(np.abs(c0[c0 != 0])) > 0
+    worst = 0.0
+    for _ in range(4):
+        d = rand_complex(rng, psi.shape)
+        d /= np.linalg.norm(d)
+        h = 1e-5
+        for _ in range(6):
+            cp = _l1_features(psi + h * d, P, meas, prob, part)
+            cm = _l1_features(psi - h * d, P, meas, prob, part)
+            same = np.array_equal(np.sign(cp), np.sign(c0)) and np.array_equal(np.sign(cm), np.sign(c0))
+            if same and np.max(np.abs(cp - cm)) < 1.0:
+                break
+            h /= 4.0
+        else:
+            pytest.fail("no step without a kink crossing")
+        fd = (fun(psi + h * d) - fun(psi - h * d)) / (2 * h)
+        an = 2.0 * float(np.real(np.vdot(g, d)))
+        worst = max(worst, abs(fd - an) / max(abs(an), 1e-3))
+    assert worst < 1e-6, worst
+
+
+def test_exact_l1_subgradient_is_zero_at_zero():
+    """Sec. 3.3: the subgradient of |x| at 0 is taken as 0; an isotropic normaliser of a
+    zero feature pair is 0 as well."""
+    z = np.zeros(4)
+    c = np.array([0.0, 2.0, -3.0, 0.0])
+    val, (om,) = orc.l1_value_and_omega([c], orc.NORM_ANISO, 0.0)
+    assert val == 5.0 and list(om) == [0.0, 1.0, -1.0, 0.0]
+    val, (ox, oy) = orc.l1_value_and_omega([c, z], orc.NORM_ISO, 0.0)
+    assert val == 5.0 and list(ox) == [0.0, 1.0, -1.0, 0.0] and list(oy) == [0.0] * 4
+    val, (ox, oy) = orc.l1_value_and_omega([np.array([3.0, 0.0]), np.array([4.0, 0.0])], orc.NORM_ISO, 0.0)
+    assert val == 5.0 and np.allclose(ox, [0.6, 0.0], rtol=0, atol=1e-15) and np.allclose(oy, [0.8, 0.0], rtol=0,
+                                                                                          atol=1e-15)
