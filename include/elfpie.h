@@ -195,6 +195,21 @@ elfpie_status elfpie_grad(elfpie_plan *plan, const void *psi, const void *P, con
 elfpie_status elfpie_grad_fields(elfpie_plan *plan, const void *psi, const void *P, const void *meas,
                                  const void *fields, void *g_psi, void *g_P, double *d_loss4, void *stream);
 
+/* elfpie_grad without a plan or a workspace, for callers that cannot allocate device
+ * memory (code under graph capture that may not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments and results as elfpie_grad (the
+ * problem `p` in place of a plan: validated, its tables built and copied for each call),
+ * bit for bit.  Allocates nothing on the device: the workspace is a static device array
+ * of 32 MiB (33554432 bytes) that the library holds on each GPU it runs on until the
+ * process ends; a problem whose elfpie_workspace_bytes exceeds it returns
+ * ELFPIE_E_WORKSPACE before any device work (512^2 / K = 225 / 128^2 in FP32 needs about
+ * 26 MiB).  Each call copies the tables on `stream` and waits for that stream before
+ * enqueuing the gradient evaluation, which returns without waiting.  Every call on one
+ * GPU uses the same array: calls on one stream are ordered, but calls that overlap on
+ * different streams of one GPU race and give wrong results. */
+elfpie_status elfpie_grad_noalloc(const elfpie_problem *p, const void *psi, const void *P, const void *meas,
+                                  void *g_psi, void *g_P, double *d_loss4, void *stream);
+
 /* One iteration of Algorithm 1 on `state`: gradients at (psi, P), Eq. 19 update
  * of psi, then (ELFPIE_LEARN_PUPIL) pre-filter and Eq. 19 update of P, then t += 1.
  * d_loss4 (optional, device) receives the loss terms at the pre-update state. */

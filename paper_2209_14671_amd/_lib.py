@@ -50,6 +50,8 @@ FUNCTIONS = {
     "elfpie_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "elfpie_grad_fields": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p, c_void_p]),
+    "elfpie_grad_noalloc": (c_int32, [ctypes.POINTER(ProblemC), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p]),
     "elfpie_step": (c_int32, [c_void_p, ctypes.POINTER(StateC), c_void_p, c_void_p, c_void_p]),
     "elfpie_run": (c_int32, [c_void_p, ctypes.POINTER(StateC), c_void_p, c_int32, c_void_p, c_int32, c_void_p]),
     "elfpie_object_from_spectrum": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -314,6 +315,34 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   return ELFPIE_OK;
 }
 
+}  // namespace
+
+// Workspace of the allocation-free entry point (elfpie_grad_noalloc): a file-scope
+// device array, one copy per GPU that the library runs on, held until the process
+// ends.  Host code uses it only through the address hipGetSymbolAddress gives on each
+// device (the array's name is a host-side stand-in there, not a device address).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device `dev` (current), looked up once per device.
+hipError_t scratch_base(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 }  // namespace
 
 struct elfpie_plan {
@@ -1046,6 +1075,57 @@ elfpie_status check_ptr(elfpie_plan* pl, const void* q, const char* name, bool o
     if (s_ != ELFPIE_OK) return s_;   \
   } while (0)
 
+// Copy the plan tables (windows, support rows, coverage and segment lists, twiddles
+// computed in FP64) into the plan's workspace and clear what must start at zero (loss
+// counters; the pupil partial sums, written on the support only), all on stream s, then
+// wait for s, so that the host tables may go and the workspace is ready for any stream.
+elfpie_status fill_workspace(elfpie_plan* pl, hipStream_t s) {
+  const Tables& t = pl->tb;
+  auto twiddles = [&](int n) {  // exp(-2 pi i k / n)
+    std::vector<double> tw(2 * (size_t)n);
+    for (int k = 0; k < n; ++k) {
+      const double a = -2.0 * M_PI * k / n;
+      tw[2 * k] = std::cos(a);
+      tw[2 * k + 1] = std::sin(a);
+    }
+    return tw;
+  };
+  auto put = [&](size_t off, const void* src, size_t bytes) -> elfpie_status {
+    if (!bytes) return ELFPIE_OK;
+    return hip_check(pl, hipMemcpyAsync(pl->ws + off, src, bytes, hipMemcpyHostToDevice, s), "hipMemcpyAsync(plan tables)");
+  };
+  std::vector<float> tw32[2];
+  std::vector<double> tw64[2];
+  auto put_tw = [&](int slot, size_t off, int n) -> elfpie_status {
+    tw64[slot] = twiddles(n);  // kept alive until the stream is synchronised below
+    if (t.prec == ELFPIE_F32) {
+      tw32[slot].assign(tw64[slot].begin(), tw64[slot].end());
+      return put(off, tw32[slot].data(), tw32[slot].size() * sizeof(float));
+    }
+    return put(off, tw64[slot].data(), tw64[slot].size() * sizeof(double));
+  };
+  elfpie_status st;
+  if ((st = put(t.o_win, t.win.data(), t.win.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_xlo, t.xlo.data(), t.xlo.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_xhi, t.xhi.data(), t.xhi.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_roff, t.rowoff.data(), t.rowoff.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_tptr, t.tile_ptr.data(), t.tile_ptr.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_tled, t.tile_led.data(), t.tile_led.size() * sizeof(int))) != ELFPIE_OK ||
+      (st = put(t.o_s2p, t.s2p.data(), t.s2p.size() * sizeof(int))) != ELFPIE_OK ||
+      (t.rowupd && (st = put(t.o_sptr, t.seg_ptr.data(), t.seg_ptr.size() * sizeof(int))) != ELFPIE_OK) ||
+      (t.rowupd && (st = put(t.o_sent, t.seg_ent.data(), t.seg_ent.size() * sizeof(int))) != ELFPIE_OK) ||
+      (st = put_tw(0, t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(1, t.o_twhi, t.n_hi)) != ELFPIE_OK)
+    return st;
+  // counters and pupil partial sums cleared by a fill kernel (no memset node, should a
+  // caller capture this work)
+  const size_t part_words = (size_t)t.nch * t.n_lo * t.n_lo * 2 * t.elem / sizeof(int);
+  k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(t.o_ctr), 0, 1);
+  k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(t.o_flag), 0, 1);
+  k_fill<int><<<(part_words + 255) / 256, 256, 0, s>>>(pl->at<int>(t.o_part), 0, part_words);
+  LAUNCH_CHECK(pl, "k_fill(plan set-up)");
+  return hip_check(pl, hipStreamSynchronize(s), "hipStreamSynchronize(plan set-up)");
+}
+
 // Destroy the plan's run graphs after their last replays have finished (destroying an
 // exec whose replays are still in flight frees what the runtime is still using).
 void drop_run_graphs(elfpie_plan* pl) {
@@ -1127,58 +1207,14 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
   pl->prob.led_k = nullptr;  // host array is not kept
   pl->tb = std::move(tb);
   pl->ws = static_cast<char*>(d_ws);
-  const Tables& t = pl->tb;
   auto cleanup = [&](elfpie_status st) {
     g_last_error = pl->err;
     elfpie_plan_destroy(pl);
     return st;
   };
   if (hipGetDevice(&pl->device) != hipSuccess) return cleanup(set_err(pl, ELFPIE_E_DEVICE, "hipGetDevice failed"));
-  // twiddle tables exp(-2 pi i k / n), computed in double
-  auto twiddles = [&](int n) {
-    std::vector<double> tw(2 * (size_t)n);
-    for (int k = 0; k < n; ++k) {
-      const double a = -2.0 * M_PI * k / n;
-      tw[2 * k] = std::cos(a);
-      tw[2 * k + 1] = std::sin(a);
-    }
-    return tw;
-  };
-  auto put = [&](size_t off, const void* src, size_t bytes) -> elfpie_status {
-    if (!bytes) return ELFPIE_OK;
-    return hip_check(pl, hipMemcpy(pl->ws + off, src, bytes, hipMemcpyHostToDevice), "hipMemcpy(plan tables)");
-  };
-  auto put_tw = [&](size_t off, int n) -> elfpie_status {
-    std::vector<double> tw = twiddles(n);
-    if (t.prec == ELFPIE_F32) {
-      std::vector<float> f(tw.begin(), tw.end());
-      return put(off, f.data(), f.size() * sizeof(float));
-    }
-    return put(off, tw.data(), tw.size() * sizeof(double));
-  };
   elfpie_status st;
-  if ((st = put(t.o_win, t.win.data(), t.win.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_xlo, t.xlo.data(), t.xlo.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_xhi, t.xhi.data(), t.xhi.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_roff, t.rowoff.data(), t.rowoff.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_tptr, t.tile_ptr.data(), t.tile_ptr.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_tled, t.tile_led.data(), t.tile_led.size() * sizeof(int))) != ELFPIE_OK ||
-      (st = put(t.o_s2p, t.s2p.data(), t.s2p.size() * sizeof(int))) != ELFPIE_OK ||
-      (t.rowupd && (st = put(t.o_sptr, t.seg_ptr.data(), t.seg_ptr.size() * sizeof(int))) != ELFPIE_OK) ||
-      (t.rowupd && (st = put(t.o_sent, t.seg_ent.data(), t.seg_ent.size() * sizeof(int))) != ELFPIE_OK) ||
-      (st = put_tw(t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(t.o_twhi, t.n_hi)) != ELFPIE_OK)
-    return cleanup(st);
-  const int zero = 0;
-  if ((st = put(t.o_ctr, &zero, sizeof zero)) != ELFPIE_OK || (st = put(t.o_flag, &zero, sizeof zero)) != ELFPIE_OK)
-    return cleanup(st);
-  // the pupil partial sums are written on the support only; the rest stays zero
-  const size_t part_bytes = (size_t)t.nch * t.n_lo * t.n_lo * 2 * t.elem;
-  if ((st = hip_check(pl, hipMemset(pl->ws + t.o_part, 0, part_bytes), "hipMemset(pupil partials)")) != ELFPIE_OK)
-    return cleanup(st);
-  // the memset runs on the null stream, which work on non-blocking streams does not
-  // wait for: finish it before the plan is handed out
-  if ((st = hip_check(pl, hipStreamSynchronize(nullptr), "hipStreamSynchronize(plan set-up)")) != ELFPIE_OK)
-    return cleanup(st);
+  if ((st = fill_workspace(pl, nullptr)) != ELFPIE_OK) return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(set_err(pl, ELFPIE_E_DEVICE, "stream creation failed"));
   if (hipEventCreateWithFlags(&pl->gdone, hipEventDisableTiming) != hipSuccess)
@@ -1250,6 +1286,44 @@ elfpie_status elfpie_grad_fields(elfpie_plan* pl, const void* psi, const void* P
     return decltype(ops)::iteration(pl, psi, P, meas, nullptr, g_psi, g_P, d_loss4, nullptr, s, nullptr, nullptr,
                                     fields);
   });
+}
+
+elfpie_status elfpie_grad_noalloc(const elfpie_problem* p, const void* psi, const void* P, const void* meas,
+                                  void* g_psi, void* g_P, double* d_loss4, void* stream) {
+  // host checks first: nothing reaches the device for a problem that does not fit
+  Tables tb;
+  std::string err;
+  elfpie_status st = build_tables(p, &tb, &err);
+  if (st != ELFPIE_OK) return set_err(nullptr, st, err);
+  if (tb.total > kScratchBytes)
+    return set_err(nullptr, ELFPIE_E_WORKSPACE,
+                   "the problem needs " + std::to_string(tb.total) + " bytes of workspace; the static scratch of "
+                   "elfpie_grad_noalloc holds " + std::to_string(kScratchBytes));
+  CHECK(check_ptr(nullptr, psi, "psi", false));
+  CHECK(check_ptr(nullptr, P, "P", false));
+  CHECK(check_ptr(nullptr, meas, "meas", false));
+  CHECK(check_ptr(nullptr, g_psi, "g_psi", false));
+  CHECK(check_ptr(nullptr, g_P, "g_P", true));
+  CHECK(check_ptr(nullptr, d_loss4, "d_loss4", true));
+  elfpie_plan pl;  // on the host stack: no run graphs, streams or events
+  pl.prob = *p;
+  pl.prob.led_k = nullptr;
+  pl.tb = std::move(tb);
+  if (hipGetDevice(&pl.device) != hipSuccess) return set_err(nullptr, ELFPIE_E_DEVICE, "hipGetDevice failed");
+  void* base = nullptr;
+  const hipError_t e = scratch_base(pl.device, &base);
+  if (e != hipSuccess)
+    return set_err(nullptr, ELFPIE_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  pl.ws = static_cast<char*>(base);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // tables and cleared buffers first (stream-ordered after earlier work on s, then s is
+  // synchronised), then the gradient evaluation, enqueued on s without waiting
+  if ((st = fill_workspace(&pl, s)) != ELFPIE_OK) return set_err(nullptr, st, pl.err);
+  st = dispatch(&pl, [&](auto ops) {
+    return decltype(ops)::iteration(&pl, psi, P, meas, nullptr, g_psi, g_P, d_loss4, nullptr, s);
+  });
+  if (st != ELFPIE_OK) return set_err(nullptr, st, pl.err);
+  return ELFPIE_OK;
 }
 
 elfpie_status elfpie_step(elfpie_plan* pl, const elfpie_state* st, const void* meas, double* d_loss4,

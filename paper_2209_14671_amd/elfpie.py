@@ -332,6 +332,26 @@ class Plan:
         return {n: float(ms[i]) for i, n in enumerate(names)}
 
 
+def grad_noalloc(problem: Problem, psi, P, meas, want_gP=True):
+    """elfpie_grad_noalloc: the loss terms and gradients of elfpie_grad with no plan and no
+    device workspace (the library's static scratch).  Returns (loss4, g_psi, g_P or None);
+    the outputs are allocated here, by torch, as for every other call of this binding."""
+    lib = _lib.load()
+    p, _keep = problem.to_c()
+    f32 = problem.precision == F32
+    cdt = torch.complex64 if f32 else torch.complex128
+    n_hi, n_lo = problem.n_lo * problem.upsample, problem.n_lo
+    for t, shape, name in ((psi, (n_hi, n_hi), "psi"), (P, (n_lo, n_lo), "P")):
+        if t.dtype != cdt or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {cdt} tensor of shape {shape}")
+    g = torch.empty((n_hi, n_hi), dtype=cdt, device=psi.device)
+    gP = torch.empty((n_lo, n_lo), dtype=cdt, device=psi.device) if want_gP else None
+    l4 = torch.empty(4, dtype=torch.float64, device=psi.device)
+    _lib.check(lib.elfpie_grad_noalloc(ctypes.byref(p), _ptr(psi), _ptr(P), _ptr(meas.contiguous()), _ptr(g),
+                                       _ptr(gP), _ptr(l4), _stream()))
+    return l4, g, gP
+
+
 class Batch:
     """Independent fields of view (tiles) run together: one replay of the batch graph is
     one iteration of every tile, the tiles spread over parallel graph branches.

@@ -128,3 +128,18 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     with pytest.raises(ImportError):
         _lib.load()
     monkeypatch.setattr(_lib, "_LIB", None)
+
+
+def test_grad_noalloc_rejects_a_problem_larger_than_its_scratch(lib):
+    """elfpie_grad_noalloc checks the workspace a problem needs against its 32 MiB static
+    scratch on the host, before any device work: 1024^2 / K = 225 / 256^2 needs ~245 MiB."""
+    import paper_2209_14671_amd as E
+    from paper_2209_14671_amd import _lib
+    case = synth.config_case(5)
+    prob = E.problem_from_optics(case.optics, case.led_k, precision=E.F32)
+    assert E.workspace_bytes(prob) > 32 << 20
+    p, _keep = prob.to_c()
+    fake = ctypes.c_void_p(1 << 20)  # aligned, never dereferenced: the call fails first
+    st = lib.elfpie_grad_noalloc(ctypes.byref(p), fake, fake, fake, fake, None, None, None)
+    assert st == _lib.E_WORKSPACE
+    assert b"33554432" in lib.elfpie_last_error(None)
