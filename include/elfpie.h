@@ -243,12 +243,15 @@ elfpie_status elfpie_init_state(elfpie_plan *plan, const void *meas, const elfpi
 /* Timing of the iteration's stages in isolation: each stage is launched n_rep
  * times back to back on `stream` between two HIP events, on the state's current
  * arrays (the state is left unchanged), and ms_out (HOST, 8 floats) receives the
- * mean milliseconds per launch: [0] per-LED kernel, [1] object branch (transforms
- * and Hessian penalties, gradient mode), [2] spectrum gather + update (gradient
- * mode, with the pupil partial sums), [3] iteration tail launched alone (pupil
- * gradient and loss reduction), [4..7] unused (0).  Inside elfpie_run the tail of
- * every iteration but the last rides in the next iteration's first launch.
- * Synchronous. */
+ * mean milliseconds per launch: [0] per-LED kernel (with the object-branch blocks
+ * when the branch rides in it, see [4]), [1] object-branch launches outside it
+ * (transforms and Hessian penalties, gradient mode; only the inverse row transforms
+ * of psi when the branch rides in the per-LED launch), [2] spectrum gather + update
+ * (gradient mode, with the pupil partial sums), [3] iteration tail launched alone
+ * (pupil gradient and loss reduction), [4] 1 when the object branch rides in the
+ * per-LED launch (512^2 spectrum, 128^2 tiles, FP32, with enough compute units left
+ * free by the LED blocks), else 0, [5..7] unused (0).  Inside elfpie_run the tail of
+ * every iteration but the last rides in a later launch.  Synchronous. */
 elfpie_status elfpie_stage_timing(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                                   int32_t n_rep, float *ms_out, void *stream);
 

@@ -41,6 +41,10 @@ constexpr bool kUseStrip = ELFPIE_STRIP != 0;  // column-strip fusion of the obj
 #define ELFPIE_ROW_UPDATE 1
 #endif
 constexpr bool kRowUpdate = ELFPIE_ROW_UPDATE != 0;  // update on whole rows, row transforms folded in
+#ifndef ELFPIE_FUSE_OBJ
+#define ELFPIE_FUSE_OBJ 1
+#endif
+constexpr bool kFuseObj = ELFPIE_FUSE_OBJ != 0;  // object branch as blocks of the per-LED launch
 
 // The tail of an iteration (pupil update, loss) waiting to be launched, either alone
 // or as extra blocks of the next iteration's first transform launch.
@@ -73,6 +77,8 @@ struct Tables {
   int ntiles_x = 0;                // 16 x 16 tiles per row of the spectrum
   bool strip = false;              // object branch on column strips (k_obj_strip)
   bool rowupd = false;             // spectrum update on whole rows (k_update_rows)
+  bool fused = false;              // object branch as the last nobj blocks of the per-LED launch
+  int nobj = 0;
   int nhp = 0;                     // Hessian loss partial pairs written per evaluation
   size_t hess_pairs = 0;           // pairs per Hessian partial buffer (two, by iteration parity)
   int nseg = 0;                    // 64-column segments per spectrum row
@@ -315,6 +321,26 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   return ELFPIE_OK;
 }
 
+// The object branch rides in the per-LED launch when the LED blocks leave enough compute
+// units free for strips of at most ObjWide::WMAX columns: one 1024-thread block per unit
+// (the 128^2 tile holds a unit's LDS), the object blocks last in the launch.  The 512^2
+// spectrum with 128^2 tiles in FP32 (the paper-shaped field of view) only.
+void set_fusion(Tables* tb, int device) {
+  tb->fused = false;
+  tb->nobj = 0;
+  if (!kFuseObj || tb->prec != ELFPIE_F32 || tb->n_lo != 128 || tb->n_hi != 512 || tb->mux != 1 || tb->big ||
+      !tb->rowupd)
+    return;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return;
+  const int free_cus = cus - tb->K;
+  constexpr int wmax = ObjWide<512, true>::WMAX;
+  const int need = (512 + wmax - 1) / wmax;
+  if (free_cus < need) return;
+  tb->nobj = std::min(free_cus, 64);
+  tb->fused = true;
+}
+
 }  // namespace
 
 // Workspace of the allocation-free entry point (elfpie_grad_noalloc): a file-scope
@@ -423,6 +449,19 @@ struct Ops {
     else k_led<T, N, false, false><<<K, NT, 0, s>>>(a);
   }
 
+  // The per-LED launch with the object branch as its last a.obj.nblk blocks.
+  template <int N, int NOBJ>
+  static void launch_led_obj(const LedArgs& a, int K, hipStream_t s) {
+    const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
+    const bool stored = (a.mode & LED_STORED) != 0;
+    constexpr int NT = LedShape<N>::NT;
+    const int grid = K + a.obj.nblk;
+    if (stored && scaled) k_led<T, N, true, true, NOBJ><<<grid, NT, 0, s>>>(a);
+    else if (stored) k_led<T, N, false, true, NOBJ><<<grid, NT, 0, s>>>(a);
+    else if (scaled) k_led<T, N, true, false, NOBJ><<<grid, NT, 0, s>>>(a);
+    else k_led<T, N, false, false, NOBJ><<<grid, NT, 0, s>>>(a);
+  }
+
   // n_lo = 192, 256: rows (inverse) -> column strips -> rows (forward), through HBM scratch.
   template <int N>
   static void launch_big(const Tables& tb, const LedArgs& a, C* A, C* B, hipStream_t s) {
@@ -453,7 +492,8 @@ struct Ops {
   }
 
   static elfpie_status led(elfpie_plan* pl, int mode, const void* psi, const void* P, const void* meas,
-                           void* fields, void* intens, hipStream_t s, int64_t* t_bump = nullptr) {
+                           void* fields, void* intens, hipStream_t s, int64_t* t_bump = nullptr,
+                           const LedObjArgs* obj = nullptr) {
     const Tables& tb = pl->tb;
     LedArgs a{};
     a.psi = psi;
@@ -485,6 +525,17 @@ struct Ops {
     a.fid_gamma = pl->prob.fid_gamma;
     a.norm = pl->prob.norm;
     if (tb.big) return led_big(pl, a, s);
+    if (obj) {
+      if constexpr (sizeof(T) == 4) {
+        if (tb.fused) {
+          a.obj = *obj;
+          launch_led_obj<128, 512>(a, tb.K, s);
+          LAUNCH_CHECK(pl, "k_led (with object blocks)");
+          return ELFPIE_OK;
+        }
+      }
+      return set_err(pl, ELFPIE_E_UNSUPPORTED, "object blocks in the per-LED launch need a fused plan");
+    }
     switch (tb.n_lo) {
       case 32: launch_led<32>(a, tb.K, s); break;
       case 64: launch_led<64>(a, tb.K, s); break;
@@ -575,6 +626,25 @@ struct Ops {
     a.norm = pl->prob.norm;
     a.want_grad = grad ? 1 : 0;
     return a;
+  }
+
+  // The object blocks of a fused per-LED launch: T1 (inverse row transforms of psi) in,
+  // the column-transformed Hessian-term gradient out in T2, loss partials in buffer par.
+  static LedObjArgs obj_args(elfpie_plan* pl, const void* T1, void* T2, int par) {
+    const Tables& tb = pl->tb;
+    LedObjArgs o{};
+    o.T1 = T1;
+    o.T2 = T2;
+    o.tw = pl->at<void>(tb.o_twhi);
+    o.partial = hess_partials(pl, par);
+    o.inv_n = 1.0 / tb.n_hi;
+    o.alpha = pl->prob.alpha;
+    o.beta = pl->prob.beta;
+    o.eta_h = pl->prob.eta_h;
+    o.eps = pl->prob.l1_eps;
+    o.norm = pl->prob.norm;
+    o.nblk = tb.nobj;
+    return o;
   }
 
   static elfpie_status hessian(elfpie_plan* pl, bool grad, const void* Ot, void* Gt, hipStream_t s, int par) {
@@ -768,13 +838,17 @@ struct Ops {
     return a;
   }
 
-  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist, int par) {
+  // Hessian loss partial pairs that an iteration's object branch writes: one per object
+  // block of the fused per-LED launch, else one per strip (or tile).
+  static int iter_nhp(const elfpie_plan* pl) { return pl->tb.fused ? pl->tb.nobj : pl->tb.nhp; }
+
+  static FinArgs fin_args(elfpie_plan* pl, double* loss4, double* hist, int par, int nhp) {
     const Tables& tb = pl->tb;
     FinArgs a{};
     a.fid_partial = pl->at<double>(tb.o_fid);
     a.K = tb.nfid;
     a.hess_partial = hess_partials(pl, par);
-    a.ntiles = tb.nhp;
+    a.ntiles = nhp;
     a.alpha = pl->prob.alpha;
     a.beta = pl->prob.beta;
     a.loss4 = loss4;
@@ -787,7 +861,7 @@ struct Ops {
   // The tail of an iteration: Eq. 19 on P (st != NULL) or the pupil gradient into
   // g_out (when pupil), and the loss terms into loss4 / the history.
   static TailReq tail_req(elfpie_plan* pl, bool pupil, const void* P, const elfpie_state* st, void* g_out,
-                          double* loss4, double* hist, int par = 0) {
+                          double* loss4, double* hist, int par, int nhp) {
     TailReq r;
     r.pupil = pupil;
     PupilArgs& a = r.a.pa;
@@ -801,7 +875,7 @@ struct Ops {
       a.t = reinterpret_cast<const long long*>(st->t);
       a.step = 1;
     }
-    r.a.fin = fin_args(pl, loss4, hist, par);
+    r.a.fin = fin_args(pl, loss4, hist, par, nhp);
     return r;
   }
 
@@ -833,22 +907,37 @@ struct Ops {
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
-    if ((r = object_branch(pl, psi, true, T1, T2, s, prev, t1_ready && tb.rowupd, !tb.rowupd, par)) != ELFPIE_OK)
-      return r;
     const int mode = stored_fields ? LED_GRAD | LED_STORED : LED_GRAD;
-    if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr)) !=
-        ELFPIE_OK)
-      return r;
+    if (tb.fused) {
+      // the inverse row transforms of psi first (unless the previous update left them in
+      // T1), with a pending tail riding along; else that tail alone: the per-LED launch
+      // reads P, so the previous pupil update finishes before it
+      if (!t1_ready) {
+        if ((r = lines<true, false>(pl, psi, T1, s, prev)) != ELFPIE_OK) return r;
+      } else if (prev && (r = tail(pl, *prev, s)) != ELFPIE_OK) {
+        return r;
+      }
+      const LedObjArgs o = obj_args(pl, T1, T2, par);
+      if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr, &o)) !=
+          ELFPIE_OK)
+        return r;
+    } else {
+      if ((r = object_branch(pl, psi, true, T1, T2, s, prev, t1_ready && tb.rowupd, !tb.rowupd, par)) != ELFPIE_OK)
+        return r;
+      if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr)) !=
+          ELFPIE_OK)
+        return r;
+    }
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     // a deferred tail leaves its loss reduction to this update launch, so that only
     // the pupil update rides in the next strip launch
     const bool split = tb.rowupd && defer;
-    const FinArgs fa = fin_args(pl, loss4, hist, par);
+    const FinArgs fa = fin_args(pl, loss4, hist, par, iter_nhp(pl));
     if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s, st != nullptr, nullptr, split ? &fa : nullptr)) !=
         ELFPIE_OK)
       return r;
-    TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist, par);
+    TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist, par, iter_nhp(pl));
     if (split) mine.fin = false;
     if (defer) {
       *defer = mine;
@@ -880,7 +969,7 @@ struct Ops {
   // reduced in the update launch), as iteration() returns it.
   static TailReq pending_pupil(elfpie_plan* pl, const elfpie_state* st, double* hist) {
     const bool learn_p = (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0;
-    TailReq r = tail_req(pl, learn_p, st->P, st, nullptr, nullptr, hist, 1);
+    TailReq r = tail_req(pl, learn_p, st->P, st, nullptr, nullptr, hist, 1, iter_nhp(pl));
     r.fin = false;
     return r;
   }
@@ -902,7 +991,7 @@ struct Ops {
     if (!want_loss) return ELFPIE_OK;
     void* T1 = pl->at<void>(pl->tb.o_T1);
     if ((r = object_branch(pl, psi, false, T1, nullptr, s)) != ELFPIE_OK) return r;
-    return tail(pl, tail_req(pl, false, P, nullptr, nullptr, loss4, nullptr), s);
+    return tail(pl, tail_req(pl, false, P, nullptr, nullptr, loss4, nullptr, 0, pl->tb.nhp), s);
   }
 
   static elfpie_status to_object(elfpie_plan* pl, const void* psi, void* obj, hipStream_t s) {
@@ -1020,7 +1109,10 @@ struct Ops {
     HIP_TRY(pl, hipEventCreate(&e0));
     HIP_TRY(pl, hipEventCreate(&e1));
     elfpie_status r = ELFPIE_OK;
-    const TailReq tq = tail_req(pl, true, st->P, nullptr, gP, l4, nullptr);
+    const TailReq tq = tail_req(pl, true, st->P, nullptr, gP, l4, nullptr, 0, iter_nhp(pl));
+    // a fused plan's per-LED launch reads T1: the inverse row transforms of psi first
+    if (tb.fused && (r = lines<true, false>(pl, st->psi, T1, s)) != ELFPIE_OK) return r;
+    const LedObjArgs o = obj_args(pl, T1, T2, 0);
     for (int stage = 0; stage < 4 && r == ELFPIE_OK; ++stage) {
       // warm the stage once, then time n_rep launches
       for (int rep = -1; rep < n_rep && r == ELFPIE_OK; ++rep) {
@@ -1028,9 +1120,13 @@ struct Ops {
           if (hipEventRecord(e0, s) != hipSuccess) r = set_err(pl, ELFPIE_E_DEVICE, "hipEventRecord");
         }
         switch (stage) {
-          case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s); break;
-          // with the row form, the update stage carries both row transforms, as in a run
-          case 1: r = object_branch(pl, st->psi, true, T1, T2, s, nullptr, false, !tb.rowupd); break;
+          case 0: r = led(pl, LED_GRAD, st->psi, st->P, meas, nullptr, nullptr, s, nullptr, tb.fused ? &o : nullptr); break;
+          // with the row form, the update stage carries both row transforms, as in a run;
+          // a fused plan's object launches outside the per-LED one are the row transforms
+          case 1:
+            r = tb.fused ? lines<true, false>(pl, st->psi, T1, s)
+                         : object_branch(pl, st->psi, true, T1, T2, s, nullptr, false, !tb.rowupd);
+            break;
           case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s, tb.rowupd, st->psi); break;
           case 3: r = tail(pl, tq, s); break;
         }
@@ -1043,6 +1139,7 @@ struct Ops {
       ms[stage] = t / (float)n_rep;
     }
     for (int i = 4; i < 8; ++i) ms[i] = 0.f;
+    ms[4] = tb.fused ? 1.f : 0.f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return r;
@@ -1213,6 +1310,7 @@ elfpie_status elfpie_plan_create(const elfpie_problem* p, void* d_ws, size_t ws_
     return st;
   };
   if (hipGetDevice(&pl->device) != hipSuccess) return cleanup(set_err(pl, ELFPIE_E_DEVICE, "hipGetDevice failed"));
+  set_fusion(&pl->tb, pl->device);
   elfpie_status st;
   if ((st = fill_workspace(pl, nullptr)) != ELFPIE_OK) return cleanup(st);
   if (hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking) != hipSuccess)
@@ -1310,6 +1408,7 @@ elfpie_status elfpie_grad_noalloc(const elfpie_problem* p, const void* psi, cons
   pl.prob.led_k = nullptr;
   pl.tb = std::move(tb);
   if (hipGetDevice(&pl.device) != hipSuccess) return set_err(nullptr, ELFPIE_E_DEVICE, "hipGetDevice failed");
+  set_fusion(&pl.tb, pl.device);
   void* base = nullptr;
   const hipError_t e = scratch_base(pl.device, &base);
   if (e != hipSuccess)

@@ -9,6 +9,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "cx.hpp"
 #include "fft.hpp"
@@ -171,10 +172,19 @@ __device__ __forceinline__ int xcd_order(int b, int n) {
   return x * q + min(x, r) + b / 8;
 }
 
+// The object-branch role of the per-LED launch (defined with the other object kernels):
+// block b of the launch's nblk object blocks, its shared memory carved from `lds`.
+template <class T, int N, int NT>
+__device__ void obj_strip_wide(const LedObjArgs& o, int b, char* lds);
+template <class T, int N, int NT>
+constexpr size_t obj_wide_lds_bytes();
+
 // Every pass of each 2-D transform is spread over the whole block (StockhamPass).
 // SCALED: compiled with the Sec. 6.3 fidelity scalings (used only for them).
 // STORED: the LED_STORED mode (fields read, not recomputed), in its own instantiation.
-template <class T, int N, bool SCALED = false, bool STORED = false>
+// NOBJ > 0: the last a.obj.nblk blocks of the launch run the object branch of an
+// NOBJ x NOBJ spectrum (obj_strip_wide) in the LDS of the per-LED tile instead.
+template <class T, int N, bool SCALED = false, bool STORED = false, int NOBJ = 0>
 __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   using Sh = LedShape<N>;
   constexpr int NT = Sh::NT, R1 = Sh::R1, R2 = Sh::R2, PITCH = N + 1;
@@ -205,7 +215,16 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   const cx<T>* twb = TWB ? twb_s : twl;
 
   const int tid = threadIdx.x;
-  const int k = ELFPIE_LED_XCD ? xcd_order(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  int nled = gridDim.x;
+  if constexpr (NOBJ > 0) {
+    static_assert(obj_wide_lds_bytes<T, NOBJ, NT>() <= sizeof(img), "object blocks fit the tile's LDS");
+    nled -= a.obj.nblk;
+    if ((int)blockIdx.x >= nled) {  // block-uniform: an object block
+      obj_strip_wide<T, NOBJ, NT>(a.obj, blockIdx.x - nled, reinterpret_cast<char*>(img));
+      return;
+    }
+  }
+  const int k = ELFPIE_LED_XCD ? xcd_order(blockIdx.x, nled) : (int)blockIdx.x;
   led_bump_step(a, k, tid);
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
@@ -1096,6 +1115,259 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
     if (!early) pupil_prefetch<T>(ta.pa, pp, pf);
     pupil_finish<T>(ta.pa, pbc, pp, pf);  // pbc: written before the first barrier
   }
+}
+
+// ---------------------------------------------------------------------------
+// The object branch as blocks of the per-LED launch: k_obj_strip's work on a wide strip
+// of W <= WMAX output columns per block, so that a few blocks on the compute units the
+// LED blocks leave free cover the whole spectrum while those run.
+// ---------------------------------------------------------------------------
+// Object block b of nblk takes columns c0 = b N / nblk .. c1 - 1 (W = c1 - c0) and the two
+// halo columns on each side (NL = W + 4 lines), all in LDS: the column inverse DFT gives
+// O = (-1)^(x+y) Ot / n on the lines; then, in chunks of CH rows, |O| and angle(O) of the
+// chunk's rows and two halo rows each side (the two rows above carried over from the
+// previous chunk, whose own rows have been overwritten by G), omega of the three H
+// components on columns c0 - 1 .. c1 and rows r0 - 1 .. r0 + CH (zero where the stencil
+// leaves the grid), the loss terms of the own pixels, and on the own pixels
+// q = H^T omega and G = alpha q_a O / (2|O|) + beta q_phi i O / (2(|O|^2 + eta)), stored as
+// (-1)^(x+y) G / n over O.  Finally the forward DFT along the W own columns into T2.
+// The exact anisotropic L1 (omega = sign, the default) keeps omega as bytes, which leaves
+// room for chunks of 128 rows; the other forms keep it in the working precision, in
+// chunks of 64.  The arithmetic per element is that of k_obj_strip.
+template <int N, bool SIGN> struct ObjWide {
+  static constexpr int WMAX = 17, CH = SIGN ? 128 : 64, NLM = WMAX + 4, OWM = WMAX + 2, OH = CH + 2, RS = CH + 4;
+  static constexpr int PITCH = N + 1;  // odd: the lines of a pass spread over the banks
+  static_assert(N % CH == 0, "whole chunks");
+};
+
+template <class T, int N, bool INV, int NT, int NLMAX, int PITCH>
+__device__ __forceinline__ void fft_lines_rt(cx<T>* buf, int nl, const cx<T>* tw, int tid) {
+  using Rd = LineRadix<N>;
+  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3;
+  StockhamPass<T, N, R1, 1, INV, NT, ceil_div(NLMAX * (N / R1), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
+  StockhamPass<T, N, R2, R1, INV, NT, ceil_div(NLMAX * (N / R2), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
+  if constexpr (R3 > 1)
+    StockhamPass<T, N, R3, R1 * R2, INV, NT, ceil_div(NLMAX * (N / R3), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
+}
+
+// Shared-memory bytes of one form of obj_strip_wide: lines, twiddles, chunk |O| and
+// angle(O), omega, block sums.
+template <class T, int N, int NT, bool SIGN>
+constexpr size_t obj_wide_form_bytes() {
+  using Sh = ObjWide<N, SIGN>;
+  return sizeof(cx<T>) * (Sh::NLM * Sh::PITCH + N) + sizeof(T) * 2 * Sh::NLM * Sh::RS +
+         (SIGN ? 1 : sizeof(T)) * 6 * Sh::OWM * Sh::OH + 8 + sizeof(double) * 2 * (NT / 64);
+}
+template <class T, int N, int NT>
+constexpr size_t obj_wide_lds_bytes() {
+  return obj_wide_form_bytes<T, N, NT, true>() > obj_wide_form_bytes<T, N, NT, false>()
+             ? obj_wide_form_bytes<T, N, NT, true>()
+             : obj_wide_form_bytes<T, N, NT, false>();
+}
+
+template <class T, int N, int NT, bool SIGN>
+__device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
+  using Sh = ObjWide<N, SIGN>;
+  using OmT = typename std::conditional<SIGN, signed char, T>::type;  // omega storage
+  constexpr int CH = Sh::CH, NLM = Sh::NLM, OWM = Sh::OWM, OH = Sh::OH, RS = Sh::RS, PITCH = Sh::PITCH;
+  constexpr int PL = OWM * OH;  // one omega plane
+  cx<T>* buf = reinterpret_cast<cx<T>*>(lds);  // line l = column c0 - 2 + l
+  cx<T>* twl = buf + NLM * PITCH;
+  T* sa = reinterpret_cast<T*>(twl + N);  // chunk rows i = y - r0 + 2, line-major
+  T* sp = sa + NLM * RS;
+  OmT* om = reinterpret_cast<OmT*>(sp + NLM * RS);  // 3 components of |O|, then of angle(O)
+  double* red = reinterpret_cast<double*>(lds + ((reinterpret_cast<char*>(om + 6 * PL) - lds + 7) & ~size_t(7)));
+  const int tid = threadIdx.x;
+  const int c0 = b * N / o.nblk, c1 = (b + 1) * N / o.nblk, W = c1 - c0, NL = W + 4, OW = W + 2;
+  const T inv_n = T(o.inv_n), eps = T(o.eps);
+  const cx<T>* T1 = static_cast<const cx<T>*>(o.T1);
+  cx<T>* T2 = static_cast<cx<T>*>(o.T2);
+  const cx<T>* tw = static_cast<const cx<T>*>(o.tw);
+  for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+  using Rd = LineRadix<N>;
+  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3;
+  static_assert(R3 > 1, "three passes");
+  {
+    // inverse DFT along the NL lines; the first pass (no twiddles) reads its butterflies
+    // straight from T1: line m = column c0 - 2 + m, element j + r N / R1
+    using PA = StockhamPass<T, N, R1, 1, true, NT, ceil_div(NLM * (N / R1), NT), PITCH, 1>;
+    constexpr int MB = ceil_div(NLM * (N / R1), NT);
+    int m[MB], j[MB];
+    bool lv[MB];
+    PA::coords(NL, tid, m, j, lv);
+    cx<T> v[MB][R1];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const int c = c0 - 2 + m[i];
+      const bool ok = lv[i] && c >= 0 && c < N;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[i][r] = ok ? T1[(size_t)(j[i] + r * (N / R1)) * N + c] : czero<T>();
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (lv[i]) dft<T, R1, true>(v[i]);
+    PA::store(buf, 0, m, j, lv, v);
+    __syncthreads();
+    StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, NL, twl, tid);
+    StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, NL, twl, tid);
+  }
+  double la = 0.0, lp = 0.0;
+  for (int r0 = 0; r0 < N; r0 += CH) {
+    // |O| and angle(O) on chunk rows i0 .. RS - 1 (rows 0, 1 carried over after the first)
+    const int i0 = r0 == 0 ? 0 : 2, nr = RS - i0;
+    for (int p = tid; p < NL * nr; p += NT) {
+      const int l = p / nr, i = i0 + p % nr, y = r0 - 2 + i, c = c0 - 2 + l;
+      T am = T(0), ph = T(0);
+      if (y >= 0 && y < N) {
+        const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
+        am = sqrt_t(norm2(O));
+        ph = atan2(O.y, O.x);
+      }
+      sa[l * RS + i] = am;
+      sp[l * RS + i] = ph;
+    }
+    __syncthreads();
+    // omega on lines 1 .. W + 2 (columns c0 - 1 .. c1), rows r0 - 1 .. r0 + CH
+    T ta_ = T(0), tp_ = T(0);
+    for (int p = tid; p < OW * OH; p += NT) {
+      const int li = p / OH, yi = p % OH;
+      const int l = li + 1, y = r0 - 1 + yi, c = c0 - 2 + l, i = yi + 1;
+      const bool in = y >= 0 && y < N && c >= 0 && c < N;
+      const bool vxx = in && c >= 1 && c <= N - 2, vyy = in && y >= 1 && y <= N - 2;
+      const bool vxy = in && c <= N - 2 && y <= N - 2;
+      const bool own = l >= 2 && l <= W + 1 && yi >= 1 && yi <= CH && in;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const T* src = f == 0 ? sa : sp;
+        const T ctr = src[l * RS + i];
+        const T sl = src[(l - 1) * RS + i], sr = src[(l + 1) * RS + i];
+        const T su = src[l * RS + i - 1], sd = src[l * RS + i + 1], srd = src[(l + 1) * RS + i + 1];
+        const T hxx = vxx ? sl - T(2) * ctr + sr : T(0);
+        const T hyy = vyy ? su - T(2) * ctr + sd : T(0);
+        const T hxy = vxy ? ctr - sr - sd + srd : T(0);
+        OmT* omf = om + 3 * f * PL + li * OH + yi;
+        if constexpr (SIGN) {  // omega = sign, rho = |.|, summed per lane in T
+          omf[0] = (signed char)sign_unit(hxx);
+          omf[PL] = (signed char)sign_unit(hyy);
+          omf[2 * PL] = (signed char)sign_unit(hxy);
+          const T lv = fabs(hxx) + fabs(hyy) + fabs(hxy);
+          if (f == 0) ta_ += own ? lv : T(0);
+          else tp_ += own ? lv : T(0);
+        } else {
+          T wxx, wyy, wxy;
+          if (o.norm == 0) {
+            wxx = omega(hxx, eps);
+            wyy = omega(hyy, eps);
+            wxy = omega(hxy, eps);
+          } else {
+            const T inv = inv_norm(hxx * hxx + hyy * hyy + hxy * hxy, eps);
+            wxx = hxx * inv;
+            wyy = hyy * inv;
+            wxy = hxy * inv;
+          }
+          omf[0] = wxx;
+          omf[PL] = wyy;
+          omf[2 * PL] = wxy;
+          if (own) {
+            double lv;
+            if (o.norm == 0) {
+              lv = double(rho(hxx, eps)) + double(rho(hyy, eps)) + double(rho(hxy, eps));
+            } else {
+              const T s2 = hxx * hxx + hyy * hyy + hxy * hxy;
+              lv = eps > T(0) ? double(sqrt_t(s2 + eps * eps) - eps) : double(sqrt_t(s2));
+            }
+            if (f == 0) la += lv;
+            else lp += lv;
+          }
+        }
+      }
+    }
+    la += double(ta_);
+    lp += double(tp_);
+    __syncthreads();
+    for (int p = tid; p < W * CH; p += NT) {
+      const int li = p / CH, yi = p % CH;
+      const int l = li + 2, y = r0 + yi, c = c0 + li;
+      const int oi = (li + 1) * OH + (yi + 1);  // omega index of the own pixel
+      T q[2];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const OmT* wx = om + 3 * f * PL;
+        const OmT* wy = wx + PL;
+        const OmT* wz = wy + PL;
+        if constexpr (SIGN) {  // sums of signs: exact in integers, as in T
+          q[f] = T(int(wx[oi - OH]) - 2 * int(wx[oi]) + int(wx[oi + OH]) + int(wy[oi - 1]) - 2 * int(wy[oi]) +
+                   int(wy[oi + 1]) + int(wz[oi]) - int(wz[oi - OH]) - int(wz[oi - 1]) + int(wz[oi - OH - 1]));
+        } else {
+          q[f] = wx[oi - OH] - T(2) * wx[oi] + wx[oi + OH] + wy[oi - 1] - T(2) * wy[oi] + wy[oi + 1] + wz[oi] -
+                 wz[oi - OH] - wz[oi - 1] + wz[oi - OH - 1];
+        }
+      }
+      const T sgn = ((c + y) & 1) ? -inv_n : inv_n;
+      const cx<T> O = scale(buf[l * PITCH + y], sgn);
+      const T a2 = norm2(O);
+      cx<T> G = czero<T>();
+      if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * q[0] * rsqrt_t(a2));
+      const T den = a2 + T(o.eta_h);
+      if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * q[1] * rcp_t(den));
+      buf[l * PITCH + y] = scale(G, sgn);
+    }
+    // the next chunk's two rows above (this chunk's last two) are kept: their own pixels
+    // now hold G in buf
+    for (int p = tid; p < 2 * NL; p += NT) {
+      const int l = p >> 1, i = p & 1;
+      sa[l * RS + i] = sa[l * RS + CH + i];
+      sp[l * RS + i] = sp[l * RS + CH + i];
+    }
+    __syncthreads();
+  }
+  // deterministic block sums of the two penalty partials
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    la += __shfl_down(la, off, 64);
+    lp += __shfl_down(lp, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6) + 0] = la;
+    red[2 * (tid >> 6) + 1] = lp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      s0 += red[2 * w];
+      s1 += red[2 * w + 1];
+    }
+    o.partial[2 * b + 0] = s0;
+    o.partial[2 * b + 1] = s1;
+  }
+  // forward DFT along the own columns (lines 2 .. W + 1); the last pass stores its outputs
+  // straight to T2 (line m = column c0 + m)
+  {
+    cx<T>* own = buf + 2 * PITCH;
+    constexpr int WM = Sh::WMAX;
+    StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, W, twl, tid);
+    StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, W, twl, tid);
+    using PC = StockhamPass<T, N, R3, R1 * R2, false, NT, ceil_div(WM * (N / R3), NT), PITCH, 1>;
+    constexpr int MB = ceil_div(WM * (N / R3), NT);
+    int m[MB], j[MB];
+    bool lv[MB];
+    PC::coords(W, tid, m, j, lv);
+    cx<T> v[MB][R3];
+    PC::load(own, 0, m, j, lv, twl, v);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (lv[i]) {
+#pragma unroll
+        for (int r = 0; r < R3; ++r) T2[(size_t)PC::out_index(j[i], r) * N + c0 + m[i]] = v[i][r];
+      }
+  }
+}
+
+template <class T, int N, int NT>
+__device__ void obj_strip_wide(const LedObjArgs& o, int b, char* lds) {
+  if (o.norm == 0 && !(o.eps > 0.0)) obj_strip_wide_form<T, N, NT, true>(o, b, lds);
+  else obj_strip_wide_form<T, N, NT, false>(o, b, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,21 @@ enum LedMode : int {
   LED_STORED = 16   // read the fields (as written by LED_FIELDS) instead of recomputing them
 };
 
+// The object branch riding in the per-LED launch: the last nblk blocks of the launch
+// each take a wide column strip of the n_hi x n_hi object (the work of k_obj_strip:
+// column inverse DFT, Hessian penalties and their gradient, column forward DFT) on the
+// compute units that the LED blocks leave free.
+struct LedObjArgs {
+  const void* T1;       // inverse row transforms of Psi (n_hi x n_hi complex)
+  void* T2;             // out: the Hessian-term gradient after its column transforms
+  const void* tw;       // n_hi forward twiddles exp(-2 pi i k / n_hi)
+  double* partial;      // 2 doubles per object block: sum rho(H|O|), sum rho(H angle O)
+  double inv_n;
+  double alpha, beta, eta_h, eps;
+  int norm;
+  int nblk;             // object blocks (0: none)
+};
+
 struct LedArgs {
   const void* psi;      // n_hi x n_hi complex
   const void* P;        // n_lo x n_lo complex
@@ -39,6 +54,7 @@ struct LedArgs {
   double fid_gamma;     // exponent of g(x) = x^gamma
   long long* t_bump;    // step counter, advanced once by block 0 in step mode (else NULL)
   int mux;              // LEDs per image (Eq. 1's M); block b serves LEDs b M .. b M + M - 1
+  LedObjArgs obj;       // object blocks of the launch (instantiations with the object role)
 };
 
 struct HessArgs {

@@ -329,7 +329,9 @@ class Plan:
         self._check(self.lib.elfpie_stage_timing(self.handle, ctypes.byref(sc), _ptr(meas), int(n_rep), ms,
                                                  _stream()))
         names = ["led", "object", "update", "tail"]
-        return {n: float(ms[i]) for i, n in enumerate(names)}
+        out = {n: float(ms[i]) for i, n in enumerate(names)}
+        out["object_in_led_launch"] = bool(ms[4] > 0.5)
+        return out
 
 
 def grad_noalloc(problem: Problem, psi, P, meas, want_gP=True):
