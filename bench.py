@@ -244,6 +244,48 @@ def sweep_bench(args, dev, iters=100):
                       "rows": rows}), flush=True)
 
 
+def precision_bench(args, dev):
+    """1024^2 high-res / K = 225 / 256^2 low-res, FP32: the plain form (FFT row and column
+    transforms) against ELFPIE_F32_MFMA_BF16X3 (the row transforms as split-BF16 DFT-matrix
+    products on the matrix cores), same stack and initial state: microseconds per iteration
+    over `steps` timed iterations after `warmup`, and the isolated per-LED branch.  Their
+    errors against the FP64 oracle after 100 iterations come from
+    tests/test_gpu_precision_study.py (the oracle is not run here)."""
+    import torch
+
+    import synth
+    import paper_2209_14671_amd as E
+    case = synth.config_case(5)
+    o = case.optics
+    meas = simulated_stack(case, dev)
+    flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
+    forms = {}
+    for name, prec in (("fft_f32", E.F32), ("mfma_bf16x3", E.F32_MFMA_BF16X3)):
+        plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=prec, flags=flags), device=dev)
+        st = plan.init_state(meas)
+        hist = torch.empty((max(args.warmup, args.steps, 1), 4), dtype=torch.float64, device=dev)
+        if args.warmup:
+            plan.run(st, meas, args.warmup, history=hist)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        h = plan.run(st, meas, args.steps, history=hist)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / max(args.steps, 1)
+        stages = plan.stage_timing(st, meas, max(args.stage_reps // 5, 3))
+        L = h[:, 3].cpu().numpy()
+        forms[name] = {"us_per_iter": round(ms * 1e3, 2), "value": round(plan.K / (ms * 1e-3), 1),
+                       "led_branch_us": round(stages["led"] * 1e3, 2), "loss_first": float(L[0]),
+                       "loss_last": float(L[-1])}
+        log(f"{name}: {ms * 1e3:.1f} us/iteration, LED branch {stages['led'] * 1e3:.1f} us")
+        plan.close()
+    print(json.dumps({"metric": "LED sub-image updates/sec (K x iters/s): FFT form vs split-BF16 MFMA row transforms",
+                      "unit": "LED-updates/s", "steps": args.steps, "warmup": args.warmup, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": WORKLOADS[5][1], "K": 225, "n_lo": 256, "n_hi": 1024},
+                      "forms": forms, "source_hash": kernel_source_hash()}), flush=True)
+
+
 def batch_bench(args, dev):
     """Config 3: 64 independent tiles in one batch (parallel graph branches, branch count
     tuned on gradient evaluations), `steps` replays timed; value = sum of K over tiles x
@@ -377,12 +419,15 @@ def main():
     ap.add_argument("--config", type=int, choices=sorted(WORKLOADS), default=2,
                     help="workload of the iteration line: 2 is the headline (512^2 / K=225 / 128^2, FP32); "
                          "1, 4 and 5 give the absolute numbers of the other single-FOV shapes")
-    ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers", "sweep"], default="iteration",
+    ap.add_argument("--workload", choices=["iteration", "autograd", "optimizers", "sweep", "precision"],
+                    default="iteration",
                     help="iteration: the throughput line (default); autograd: forward + backward of the "
                          "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields; "
                          "optimizers: loss curves of Eq. 19 and the Sec. 6.2 alternatives on the "
                          "512^2 / K=225 / 128^2 stack; sweep: reconstruction quality (LSNR, Eq. 22) over LED "
-                         "shift, uneven illumination and noise (the Tables 2-4 grid) on synthetic stacks")
+                         "shift, uneven illumination and noise (the Tables 2-4 grid) on synthetic stacks; "
+                         "precision: the FFT form against the split-BF16 matrix-core row transforms at "
+                         "1024^2 / K=225 / 256^2")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -404,6 +449,9 @@ def main():
         return
     if args.workload == "sweep":
         sweep_bench(args, dev)
+        return
+    if args.workload == "precision":
+        precision_bench(args, dev)
         return
     if args.config == 3:
         batch_bench(args, dev)

@@ -76,7 +76,13 @@ enum { ELFPIE_NORM_ANISO = 0, ELFPIE_NORM_ISO = 1 };          /* Eq. 12        *
  * (Zhuang et al. 2020: second moment of (g - m) plus eps).  g = dL/d(conj x);
  * squared magnitudes are squared moduli. */
 enum { ELFPIE_OPT_ELFPIE = 0, ELFPIE_OPT_SGD = 1, ELFPIE_OPT_NADAM = 2, ELFPIE_OPT_ADABELIEF = 3 };
-enum { ELFPIE_F64 = 0, ELFPIE_F32 = 1 };                      /* arithmetic    */
+/* Arithmetic of the plan.  ELFPIE_F32_MFMA_BF16X3 (n_lo = 256 only): FP32 everywhere
+ * except the two row transforms of each LED's low-resolution tile (F_B of Eq. 1 and
+ * F_B^H of Eq. 9 along the tile's rows, restricted to the pupil's support box), which are
+ * DFT-matrix products on the matrix cores with every FP32 operand split into a BF16 high
+ * and low part and three products (hi hi, hi lo, lo hi) accumulated in FP32: each product
+ * carries a relative error of about 2^-16 (FP32: 2^-24).  Arrays are as for ELFPIE_F32. */
+enum { ELFPIE_F64 = 0, ELFPIE_F32 = 1, ELFPIE_F32_MFMA_BF16X3 = 2 };
 enum {
   ELFPIE_LEARN_PUPIL = 1u,    /* update P with Eq. 19 after each Psi update          */
   ELFPIE_PUPIL_SUPPORT = 2u,  /* P is confined to the NA disc (forward uses P * 1_S) */
@@ -101,7 +107,7 @@ typedef struct {
   double l1_eps;           /* L1 smoothing: rho(x) = sqrt(x^2 + eps^2) - eps; 0 = exact |x| */
   int32_t fidelity;        /* ELFPIE_FID_*                                                  */
   int32_t norm;            /* ELFPIE_NORM_* (fidelity and Hessian terms)                    */
-  int32_t precision;       /* ELFPIE_F32 or ELFPIE_F64                                      */
+  int32_t precision;       /* ELFPIE_F32, ELFPIE_F64 or ELFPIE_F32_MFMA_BF16X3              */
   uint32_t flags;          /* ELFPIE_LEARN_PUPIL | ELFPIE_PUPIL_SUPPORT | ELFPIE_PUPIL_FILTER */
   double fid_gamma;        /* exponent of ELFPIE_FID_GAMMA, in (0, 4]; ignored otherwise    */
   int32_t optimizer;       /* ELFPIE_OPT_* (default Eq. 19)                                 */

@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_RANGE", 3: "E_UNSUPPORTED", 4: "E
 FID_AMPLITUDE, FID_INTENSITY, FID_GAMMA, FID_LOG = 0, 1, 2, 3
 OPT_ELFPIE, OPT_SGD, OPT_NADAM, OPT_ADABELIEF = 0, 1, 2, 3
 NORM_ANISO, NORM_ISO = 0, 1
-F64, F32 = 0, 1
+F64, F32, F32_MFMA_BF16X3 = 0, 1, 2
 LEARN_PUPIL, PUPIL_SUPPORT, PUPIL_FILTER = 1, 2, 4
 
 

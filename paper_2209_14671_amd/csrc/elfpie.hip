@@ -15,6 +15,7 @@
 #include "elfpie.h"
 #include "kernels.hpp"
 #include "big_led.hpp"
+#include "mfma_rows.hpp"
 
 using namespace elfpie;
 
@@ -71,6 +72,8 @@ struct Tables {
   int n_lo = 0, n_hi = 0, K = 0, S = 0, prec = 0;
   int mux = 1, nimg = 0;           // LEDs per image; images (K / mux)
   bool big = false;                // n_lo = 256: the per-LED branch through HBM scratch
+  bool mfma = false;               // its row transforms as split-BF16 GEMMs on the matrix cores
+  int mf_ksi = 0, mf_nti = 0, mf_ksf = 0, mf_ntf = 0;  // k-steps and n-tiles of the two row GEMMs
   int nfid = 0;                    // fidelity loss partials per evaluation
   int y_min = 0, y_max = -1, x_min = 0, x_max = -1;
   int kc = 0;                      // LED nearest the optical axis
@@ -94,6 +97,7 @@ struct Tables {
   std::vector<int> s2p;            // support index -> pupil pixel index
   size_t o_C = 0, o_D = 0, o_T1 = 0, o_T2 = 0, o_G = 0, o_gP = 0, o_part = 0, o_Pf = 0;
   size_t o_fid = 0, o_hess = 0, o_loss = 0, o_ctr = 0, o_flag = 0, o_mux = 0, o_bigA = 0, o_bigB = 0;
+  size_t o_mfi = 0, o_mff = 0;     // DFT tables of the row GEMMs (BF16 hi / lo, fragment order)
   size_t total = 0;
 };
 
@@ -105,12 +109,14 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
     return s;
   };
   if (!p) return fail(ELFPIE_E_INVALID, "problem is NULL");
-  if (p->precision != ELFPIE_F32 && p->precision != ELFPIE_F64)
-    return fail(ELFPIE_E_UNSUPPORTED, "precision must be ELFPIE_F32 or ELFPIE_F64");
+  if (p->precision != ELFPIE_F32 && p->precision != ELFPIE_F64 && p->precision != ELFPIE_F32_MFMA_BF16X3)
+    return fail(ELFPIE_E_UNSUPPORTED, "precision must be ELFPIE_F32, ELFPIE_F64 or ELFPIE_F32_MFMA_BF16X3");
+  if (p->precision == ELFPIE_F32_MFMA_BF16X3 && p->n_lo != 256)
+    return fail(ELFPIE_E_UNSUPPORTED, "ELFPIE_F32_MFMA_BF16X3 needs n_lo = 256");
   if (p->K < 1) return fail(ELFPIE_E_INVALID, "K must be >= 1");
   if (!p->led_k) return fail(ELFPIE_E_INVALID, "led_k is NULL");
   if (p->n_lo < 2 || p->upsample < 1) return fail(ELFPIE_E_INVALID, "n_lo must be >= 2 and upsample >= 1");
-  const bool f32 = p->precision == ELFPIE_F32;
+  const bool f32 = p->precision != ELFPIE_F64;
   const int nl = p->n_lo;
   const bool lo_ok = f32 ? (nl == 32 || nl == 64 || nl == 96 || nl == 128 || nl == 192 || nl == 256)
                          : (nl == 32 || nl == 64);
@@ -152,7 +158,8 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->nimg = p->K / p->mux;
   tb->big = p->n_lo > 128;  // 192 and 256: the per-LED branch through HBM scratch
   tb->nfid = !tb->big ? tb->nimg : p->K * (p->n_lo == 256 ? 256 / BigLed<256>::W : 192 / BigLed<192>::W);
-  tb->prec = p->precision;
+  tb->prec = f32 ? ELFPIE_F32 : ELFPIE_F64;  // the arithmetic of every kernel outside the row GEMMs
+  tb->mfma = p->precision == ELFPIE_F32_MFMA_BF16X3;
   tb->elem = f32 ? 4 : 8;
   const int n = tb->n_lo;
   const double fov = n * p->dx_lo_um;
@@ -317,6 +324,15 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   const size_t band = tb->big ? (size_t)(tb->y_max - tb->y_min + 1) : 0;
   tb->o_bigA = tb->big ? take((size_t)tb->K * band * n * cxb) : 0;
   tb->o_bigB = tb->big ? take((size_t)tb->K * band * n * cxb) : 0;
+  if (tb->mfma) {
+    const int box = tb->x_max - tb->x_min + 1;
+    tb->mf_ksi = (box + 31) / 32;
+    tb->mf_nti = n / 16;
+    tb->mf_ksf = n / 32;
+    tb->mf_ntf = (box + 15) / 16;
+    tb->o_mfi = take((size_t)tb->mf_ksi * tb->mf_nti * 4 * 1024);
+    tb->o_mff = take((size_t)tb->mf_ksf * tb->mf_ntf * 4 * 1024);
+  }
   tb->total = off;
   return ELFPIE_OK;
 }
@@ -464,15 +480,30 @@ struct Ops {
 
   // n_lo = 192, 256: rows (inverse) -> column strips -> rows (forward), through HBM scratch.
   template <int N>
-  static void launch_big(const Tables& tb, const LedArgs& a, C* A, C* B, hipStream_t s) {
+  static void launch_big(const Tables& tb, const LedArgs& a, C* A, C* B, hipStream_t s, const MfmaTabs* mt) {
     using Sh = BigLed<N>;
     const int nband = tb.y_max - tb.y_min + 1;
     const dim3 rows((nband + Sh::RB - 1) / Sh::RB, tb.K), cols(N / Sh::W, tb.K);
+    const dim3 mrows((nband + MfmaRows<N>::MB - 1) / MfmaRows<N>::MB, tb.K);
     const bool scaled = a.fidelity == ELFPIE_FID_GAMMA || a.fidelity == ELFPIE_FID_LOG;
-    if (!(a.mode & LED_STORED)) k_big_rows_inv<T, N><<<rows, Sh::RNT, 0, s>>>(a, A);
+    if (!(a.mode & LED_STORED)) {
+      if constexpr (sizeof(T) == 4) {
+        if (mt) k_mfma_rows_inv<N><<<mrows, 64 * (mt->nti / 2), 0, s>>>(a, *mt, A);
+        else k_big_rows_inv<T, N><<<rows, Sh::RNT, 0, s>>>(a, A);
+      } else {
+        k_big_rows_inv<T, N><<<rows, Sh::RNT, 0, s>>>(a, A);
+      }
+    }
     if (scaled) k_big_cols<T, N, true><<<cols, Sh::CNT, 0, s>>>(a, A, B);
     else k_big_cols<T, N, false><<<cols, Sh::CNT, 0, s>>>(a, A, B);
-    if (a.mode & LED_GRAD) k_big_rows_fwd<T, N><<<rows, Sh::RNT, 0, s>>>(a, B);
+    if (a.mode & LED_GRAD) {
+      if constexpr (sizeof(T) == 4) {
+        if (mt) k_mfma_rows_fwd<N><<<mrows, 64 * ((mt->ntf + 1) / 2), 0, s>>>(a, *mt, B);
+        else k_big_rows_fwd<T, N><<<rows, Sh::RNT, 0, s>>>(a, B);
+      } else {
+        k_big_rows_fwd<T, N><<<rows, Sh::RNT, 0, s>>>(a, B);
+      }
+    }
   }
 
   static elfpie_status led_big(elfpie_plan* pl, const LedArgs& a, hipStream_t s) {
@@ -480,8 +511,17 @@ struct Ops {
       const Tables& tb = pl->tb;
       C* A = pl->at<C>(tb.o_bigA);
       C* B = pl->at<C>(tb.o_bigB);
-      if (tb.n_lo == 192) launch_big<192>(tb, a, A, B, s);
-      else launch_big<256>(tb, a, A, B, s);
+      MfmaTabs mt{};
+      if (tb.mfma) {
+        mt.inv = pl->at<bf16x8>(tb.o_mfi);
+        mt.fwd = pl->at<bf16x8>(tb.o_mff);
+        mt.ksi = tb.mf_ksi;
+        mt.nti = tb.mf_nti;
+        mt.ksf = tb.mf_ksf;
+        mt.ntf = tb.mf_ntf;
+      }
+      if (tb.n_lo == 192) launch_big<192>(tb, a, A, B, s, nullptr);
+      else launch_big<256>(tb, a, A, B, s, tb.mfma ? &mt : nullptr);
       LAUNCH_CHECK(pl, "k_big");
       return ELFPIE_OK;
     } else {
@@ -1213,6 +1253,51 @@ elfpie_status fill_workspace(elfpie_plan* pl, hipStream_t s) {
       (t.rowupd && (st = put(t.o_sent, t.seg_ent.data(), t.seg_ent.size() * sizeof(int))) != ELFPIE_OK) ||
       (st = put_tw(0, t.o_twlo, t.n_lo)) != ELFPIE_OK || (st = put_tw(1, t.o_twhi, t.n_hi)) != ELFPIE_OK)
     return st;
+  // DFT tables of the row GEMMs: FP64 values split into BF16 hi / lo, in fragment order
+  std::vector<uint16_t> mft[2];
+  if (t.mfma) {
+    auto bf16 = [](float f) {  // round to nearest even
+      uint32_t u;
+      std::memcpy(&u, &f, 4);
+      u += 0x7FFFu + ((u >> 16) & 1u);
+      return uint16_t(u >> 16);
+    };
+    auto unbf16 = [](uint16_t h) {
+      const uint32_t u = uint32_t(h) << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      return f;
+    };
+    const int n = t.n_lo, box = t.x_max - t.x_min + 1;
+    for (int which = 0; which < 2; ++which) {
+      const int ksn = which ? t.mf_ksf : t.mf_ksi, ntn = which ? t.mf_ntf : t.mf_nti;
+      std::vector<uint16_t>& tab = mft[which];
+      tab.assign((size_t)ksn * ntn * 4 * 64 * 8, 0);
+      for (int ks = 0; ks < ksn; ++ks)
+        for (int nt = 0; nt < ntn; ++nt)
+          for (int lane = 0; lane < 64; ++lane)
+            for (int i = 0; i < 8; ++i) {
+              const int kk = ks * 32 + 8 * (lane / 16) + i, nn = nt * 16 + lane % 16;
+              // inverse: k = u - x_min, n = x, exp(+2 pi i u x / n); forward: k = x,
+              // n = u - x_min, exp(-2 pi i u x / n); zero past the box
+              const int u = which ? t.x_min + nn : t.x_min + kk, x = which ? kk : nn;
+              const bool in = which ? nn < box : kk < box;
+              const double ang = (which ? -2.0 : 2.0) * M_PI * (double)(((long long)u * x) % n) / n;
+              const double re = in ? std::cos(ang) : 0.0, im = in ? std::sin(ang) : 0.0;
+              const double comp[2] = {re, im};
+              for (int c = 0; c < 2; ++c) {
+                const uint16_t hi = bf16((float)comp[c]);
+                const uint16_t lo = bf16((float)(comp[c] - (double)unbf16(hi)));
+                const size_t base = ((((size_t)ks * ntn + nt) * 4 + 2 * c) * 64 + lane) * 8 + i;
+                tab[base] = hi;
+                tab[base + 64 * 8] = lo;  // the next component: re_lo after re_hi, im_lo after im_hi
+              }
+            }
+    }
+    if ((st = put(t.o_mfi, mft[0].data(), mft[0].size() * 2)) != ELFPIE_OK ||
+        (st = put(t.o_mff, mft[1].data(), mft[1].size() * 2)) != ELFPIE_OK)
+      return st;
+  }
   // counters and pupil partial sums cleared by a fill kernel (no memset node, should a
   // caller capture this work)
   const size_t part_words = (size_t)t.nch * t.n_lo * t.n_lo * 2 * t.elem / sizeof(int);

@@ -27,6 +27,17 @@ namespace elfpie {
 // TWB selects the twiddle table: false, the natural table above; true, a table laid out
 // per butterfly class, tw[(j mod NS) R + r] = exp(-2 pi i r (j mod NS) / (NS R)), so that the
 // R - 1 twiddles of a butterfly are one address plus immediate offsets.
+// A runtime divisor with its reciprocal: the quotient b / n for 0 <= b < 2^16 and
+// 1 <= n < 2^16 is the high word of b * ceil(2^32 / n) (exact: the rounding-up error of
+// the reciprocal times b stays below 1 / n), one multiply instead of a division sequence.
+// Made once per kernel for a count that all threads share.
+struct Div {
+  int n;
+  unsigned magic;
+};
+__device__ __forceinline__ Div make_div(int n) { return {n, n > 1 ? 0xFFFFFFFFu / unsigned(n) + 1u : 0u}; }
+__device__ __forceinline__ int div_q(int b, Div d) { return d.n > 1 ? (int)__umulhi((unsigned)b, d.magic) : b; }
+
 template <class T, int N, int R, int NS, bool INV, int NT, int MAXB, int TS, int ES, int NTR = 0,
           bool TWB = false>
 struct StockhamPass {
@@ -49,6 +60,17 @@ struct StockhamPass {
       live[i] = b < n * BPT;
       j[i] = b / n;
       m[i] = b - j[i] * n;
+    }
+  }
+
+  // The same for a runtime count held with its reciprocal.
+  __device__ static __forceinline__ void coords(Div d, int tid, int (&m)[MAXB], int (&j)[MAXB], bool (&live)[MAXB]) {
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int b = tid + i * NT;
+      live[i] = b < d.n * BPT;
+      j[i] = div_q(b, d);
+      m[i] = b - j[i] * d.n;
     }
   }
 
@@ -88,7 +110,8 @@ struct StockhamPass {
   }
 
   // Full in-place pass over transforms m0 .. m0 + ntr - 1: load, barrier, store, barrier.
-  __device__ static __forceinline__ void run(cx<T>* buf, int m0, int ntr, const cx<T>* tw, int tid) {
+  template <class Count>
+  __device__ static __forceinline__ void run(cx<T>* buf, int m0, Count ntr, const cx<T>* tw, int tid) {
     int m[MAXB], j[MAXB];
     bool live[MAXB];
     coords(ntr, tid, m, j, live);

@@ -300,7 +300,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     __syncthreads();
 
     // inverse DFT: rows that hold support pixels, then every column
-    const int nband = a.y_max - a.y_min + 1;
+    const Div nband = make_div(a.y_max - a.y_min + 1);
     P1iR::run(img, a.y_min, nband, twl, tid);
     P2iR::run(img, a.y_min, nband, twb, tid);
     P1iC::run(img, 0, N, twl, tid);
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   // forward DFT of dL/d(conj o): all rows, then only columns that hold support
   P1fR::run(img, 0, N, twl, tid);
   P2fR::run(img, 0, N, twb, tid);
-  const int ncol = a.x_max - a.x_min + 1;
+  const Div ncol = make_div(a.x_max - a.x_min + 1);
   P1fC::run(img, a.x_min, ncol, twl, tid);
   P2fC::coords(ncol, tid, mm, jj, lv);
   cx<T> Y[MB2][R2];
@@ -1140,16 +1140,6 @@ template <int N, bool SIGN> struct ObjWide {
   static_assert(N % CH == 0, "whole chunks");
 };
 
-template <class T, int N, bool INV, int NT, int NLMAX, int PITCH>
-__device__ __forceinline__ void fft_lines_rt(cx<T>* buf, int nl, const cx<T>* tw, int tid) {
-  using Rd = LineRadix<N>;
-  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3;
-  StockhamPass<T, N, R1, 1, INV, NT, ceil_div(NLMAX * (N / R1), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
-  StockhamPass<T, N, R2, R1, INV, NT, ceil_div(NLMAX * (N / R2), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
-  if constexpr (R3 > 1)
-    StockhamPass<T, N, R3, R1 * R2, INV, NT, ceil_div(NLMAX * (N / R3), NT), PITCH, 1>::run(buf, 0, nl, tw, tid);
-}
-
 // Shared-memory bytes of one form of obj_strip_wide: lines, twiddles, chunk |O| and
 // angle(O), omega, block sums.
 template <class T, int N, int NT, bool SIGN>
@@ -1179,6 +1169,7 @@ __device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
   double* red = reinterpret_cast<double*>(lds + ((reinterpret_cast<char*>(om + 6 * PL) - lds + 7) & ~size_t(7)));
   const int tid = threadIdx.x;
   const int c0 = b * N / o.nblk, c1 = (b + 1) * N / o.nblk, W = c1 - c0, NL = W + 4, OW = W + 2;
+  const Div dNL = make_div(NL), dW = make_div(W);
   const T inv_n = T(o.inv_n), eps = T(o.eps);
   const cx<T>* T1 = static_cast<const cx<T>*>(o.T1);
   cx<T>* T2 = static_cast<cx<T>*>(o.T2);
@@ -1194,7 +1185,7 @@ __device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
     constexpr int MB = ceil_div(NLM * (N / R1), NT);
     int m[MB], j[MB];
     bool lv[MB];
-    PA::coords(NL, tid, m, j, lv);
+    PA::coords(dNL, tid, m, j, lv);
     cx<T> v[MB][R1];
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
@@ -1208,15 +1199,16 @@ __device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
       if (lv[i]) dft<T, R1, true>(v[i]);
     PA::store(buf, 0, m, j, lv, v);
     __syncthreads();
-    StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, NL, twl, tid);
-    StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, NL, twl, tid);
+    StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
+    StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
   }
   double la = 0.0, lp = 0.0;
   for (int r0 = 0; r0 < N; r0 += CH) {
     // |O| and angle(O) on chunk rows i0 .. RS - 1 (rows 0, 1 carried over after the first)
     const int i0 = r0 == 0 ? 0 : 2, nr = RS - i0;
+    const Div dnr = make_div(nr);
     for (int p = tid; p < NL * nr; p += NT) {
-      const int l = p / nr, i = i0 + p % nr, y = r0 - 2 + i, c = c0 - 2 + l;
+      const int l = div_q(p, dnr), i = i0 + p - l * nr, y = r0 - 2 + i, c = c0 - 2 + l;
       T am = T(0), ph = T(0);
       if (y >= 0 && y < N) {
         const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
@@ -1346,13 +1338,13 @@ __device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
   {
     cx<T>* own = buf + 2 * PITCH;
     constexpr int WM = Sh::WMAX;
-    StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, W, twl, tid);
-    StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, W, twl, tid);
+    StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
+    StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
     using PC = StockhamPass<T, N, R3, R1 * R2, false, NT, ceil_div(WM * (N / R3), NT), PITCH, 1>;
     constexpr int MB = ceil_div(WM * (N / R3), NT);
     int m[MB], j[MB];
     bool lv[MB];
-    PC::coords(W, tid, m, j, lv);
+    PC::coords(dW, tid, m, j, lv);
     cx<T> v[MB][R3];
     PC::load(own, 0, m, j, lv, twl, v);
 #pragma unroll

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (F32, F64, FID_AMPLITUDE, FID_GAMMA, FID_INTENSITY, FID_LOG, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
+from ._lib import (F32, F32_MFMA_BF16X3, F64, FID_AMPLITUDE, FID_GAMMA, FID_INTENSITY, FID_LOG, LEARN_PUPIL, NORM_ANISO, NORM_ISO,  # noqa: F401
                    OPT_ADABELIEF, OPT_ELFPIE, OPT_NADAM, OPT_SGD, PUPIL_FILTER, PUPIL_SUPPORT, ElfpieError)
 
 
@@ -134,8 +134,9 @@ class Plan:
         self.n_hi, self.S, self.K, self.n_lo, self.kc = (int(v) for v in info)
         self.mux = int(problem.mux)
         self.n_img = self.K // self.mux
-        self.rdtype = torch.float32 if problem.precision == F32 else torch.float64
-        self.cdtype = torch.complex64 if problem.precision == F32 else torch.complex128
+        f32 = problem.precision != F64  # ELFPIE_F32 and the split-BF16 GEMM form keep FP32 arrays
+        self.rdtype = torch.float32 if f32 else torch.float64
+        self.cdtype = torch.complex64 if f32 else torch.complex128
 
     def close(self):
         if getattr(self, "handle", None):
@@ -340,7 +341,7 @@ def grad_noalloc(problem: Problem, psi, P, meas, want_gP=True):
     the outputs are allocated here, by torch, as for every other call of this binding."""
     lib = _lib.load()
     p, _keep = problem.to_c()
-    f32 = problem.precision == F32
+    f32 = problem.precision != F64
     cdt = torch.complex64 if f32 else torch.complex128
     n_hi, n_lo = problem.n_lo * problem.upsample, problem.n_lo
     for t, shape, name in ((psi, (n_hi, n_hi), "psi"), (P, (n_lo, n_lo), "P")):

@@ -697,3 +697,73 @@ def test_radix3_sizes_match_oracle(n_lo, up, grid):
     assert eg < 1e-4 and egp < 1e-4
     assert es < 1e-5 and rel_l2(host(st.P), ref.P) < 1e-5
     assert ei < 1e-6
+
+
+# --- the split-precision matrix-core form of the 256^2 row transforms ---
+
+MFMA_TOL = dict(field=2e-5, grad=5e-4, state=1e-5)
+
+
+@pytest.mark.parametrize("up,fidelity,norm", [(2, orc.FID_INTENSITY, orc.NORM_ANISO),
+                                              (4, orc.FID_AMPLITUDE, orc.NORM_ISO)])
+def test_mfma_rows_match_oracle(up, fidelity, norm):
+    """ELFPIE_F32_MFMA_BF16X3 at n_lo = 256 (smoothed L1): the row transforms as DFT-matrix
+    products on the matrix cores with BF16 hi + lo operands, three products accumulated in
+    FP32, about 2^-16 relative error per product (FP32: 2^-24).  Stated bounds, from that
+    error through two transform stages (fields ~4e-6 measured): fields and images 2e-5;
+    gradients 5e-4 (the smoothed normaliser amplifies the fields' error as in FP32, whose
+    gradients are held to 1e-4); the state after one step 1e-5; loss 1e-5.  Stored fields
+    give the gradients bit for bit."""
+    e = E()
+    pair = make_pair(256, up, 3, f32=True, fidelity=fidelity, norm=norm)
+    plan = e.Plan(e.Problem(precision=e.F32_MFMA_BF16X3, **pair.kw))
+    psi, P, meas = dev(pair.psi, True), dev(pair.P, True), dev(pair.meas, True)
+    out = plan.forward(psi, P, meas, fields=True, intens=True, loss=True)
+    l4, g, gP = plan.grad(psi, P, meas)
+    _, g2, gP2 = plan.grad(psi, P, meas, fields=out["fields"])
+    st = gpu_state(plan, pair, True)
+    plan.step(st, meas)
+    torch.cuda.synchronize()
+    rl4, rg, rgP = orc.loss_and_grad(pair.psi, pair.P, pair.meas, pair.oprob)
+    ref, _ = orc.step(pair.state, pair.meas, pair.oprob)
+    ef = rel_l2(host(out["fields"]), orc.fields(pair.psi, pair.P, pair.oprob))
+    ei = rel_l2(host(out["intens"]), orc.intensities(pair.psi, pair.P, pair.oprob))
+    eg, egp = rel_l2(host(g), rg), rel_l2(host(gP), rgP)
+    es, esp = rel_l2(host(st.psi), ref.psi), rel_l2(host(st.P), ref.P)
+    el = np.max(np.abs(host(l4) - rl4) / np.abs(rl4))
+    print(f"mfma n_lo=256 up={up} fid={fidelity} norm={norm}: fields {ef:.2e} intens {ei:.2e} g_psi {eg:.2e} "
+          f"g_P {egp:.2e} step psi {es:.2e} P {esp:.2e} loss {el:.2e}")
+    assert ef < MFMA_TOL["field"] and ei < MFMA_TOL["field"]
+    assert eg < MFMA_TOL["grad"] and egp < MFMA_TOL["grad"]
+    assert es < MFMA_TOL["state"] and esp < MFMA_TOL["state"] and el < 1e-5
+    assert torch.equal(g, g2) and torch.equal(gP, gP2)
+
+
+def test_mfma_run_equals_steps_and_full_size_step():
+    """The matrix-core form is deterministic (a 9-iteration run equals 9 steps bit for bit)
+    and, at 1024^2 / K = 225 / 256^2 (smoothed L1), one step matches the oracle within the
+    form's bound."""
+    e = E()
+    pair = make_pair(256, 2, 3, f32=True)
+    plan = e.Plan(e.Problem(precision=e.F32_MFMA_BF16X3, **pair.kw))
+    meas = dev(pair.meas, True)
+    a = gpu_state(plan, pair, True)
+    b = a.clone()
+    plan.run(a, meas, 9)
+    for _ in range(9):
+        plan.step(b, meas)
+    torch.cuda.synchronize()
+    for k in ("psi", "P", "mu_psi", "v_psi", "delta_psi", "t"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    pair = _config2_pair(1e-3, config=5)
+    kw = dict(pair.kw)
+    plan = e.Plan(e.Problem(precision=e.F32_MFMA_BF16X3, **kw))
+    assert (plan.K, plan.n_lo, plan.n_hi) == (225, 256, 1024)
+    st = gpu_state(plan, pair, True)
+    hist = plan.run(st, dev(pair.meas, True), 1)
+    torch.cuda.synchronize()
+    ref, rl4 = orc.step(pair.state, pair.meas, pair.oprob)
+    e_psi, e_P = rel_l2(host(st.psi), ref.psi), rel_l2(host(st.P), ref.P)
+    el = np.max(np.abs(host(hist)[0] - rl4) / np.abs(rl4))
+    print(f"mfma config5 step: psi {e_psi:.2e} P {e_P:.2e} loss {el:.2e}")
+    assert e_psi < MFMA_TOL["state"] and e_P < MFMA_TOL["state"] and el < 1e-5

@@ -1,0 +1,57 @@
+"""Accuracy of the two FP32 forms over a whole reconstruction at 1024^2 / K = 225 / 256^2
+(the matrix-core form's workload): 100 iterations of the plain form (FFT transforms) and of
+ELFPIE_F32_MFMA_BF16X3 (split-BF16 DFT-matrix row transforms) from the oracle's initial
+state on the oracle's stack, against 100 FP64 oracle iterations: relative L2 error of the
+object O = F_A Psi and of the pupil P.  The oracle takes about two minutes on one core, so
+the study runs on request (ELFPIE_PRECISION_STUDY=1); it writes its numbers to
+gpurun_out/precision_study.json when that folder exists."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import synth
+from helpers import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("ELFPIE_PRECISION_STUDY") != "1",
+                                 reason="two minutes of oracle time: run with ELFPIE_PRECISION_STUDY=1")]
+
+
+def test_precision_forms_after_100_iterations():
+    import paper_2209_14671_amd as E
+    iters = 100
+    case = synth.config_case(5)
+    o = case.optics
+    flags = orc.LEARN_PUPIL | orc.PUPIL_SUPPORT | orc.PUPIL_FILTER
+    oprob = orc.problem_from_optics(o, case.led_k, flags=flags)
+    sim = orc.problem_from_optics(o, case.led_k_true)
+    meas = orc.intensities(orc.spectrum_from_object(case.obj), case.pupil, sim).astype(np.float32).astype(np.float64)
+    st0 = orc.init_state(meas, oprob)
+    ref, rh = orc.run(st0, meas, oprob, iters)
+    O_ref = orc.object_from_spectrum(ref.psi)
+    c = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(torch.complex64).cuda()  # noqa: E731
+    out = {"iterations": iters, "workload": "1024^2 high-res, K=225, 256^2 low-res, literal L1, pupil learned"}
+    for name, prec in (("fft_f32", E.F32), ("mfma_bf16x3", E.F32_MFMA_BF16X3)):
+        plan = E.Plan(E.problem_from_optics(o, case.led_k, precision=prec, flags=flags))
+        st = plan.new_state(c(st0.psi), c(st0.P))
+        h = plan.run(st, torch.from_numpy(meas).to(torch.float32).cuda(), iters)
+        O = plan.object_from_spectrum(st.psi)
+        torch.cuda.synchronize()
+        eO = rel_l2(O.cpu().numpy().astype(np.complex128), O_ref)
+        eP = rel_l2(st.P.cpu().numpy().astype(np.complex128), ref.P)
+        eL = float(np.abs(h.cpu().numpy()[-1, 3] - rh[-1, 3]) / abs(rh[-1, 3]))
+        out[name] = {"rel_l2_O": eO, "rel_l2_P": eP, "final_loss_rel": eL}
+        print(f"{name}: O {eO:.3e} P {eP:.3e} final loss {eL:.3e}")
+        plan.close()
+    print(json.dumps(out))
+    if os.path.isdir("gpurun_out"):
+        with open(os.path.join("gpurun_out", "precision_study.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+    # both forms follow the FP64 trajectory; the matrix-core form within ten times the plain
+    # form's error or 1e-3, whichever is larger
+    assert out["fft_f32"]["rel_l2_O"] < 1e-2
+    assert out["mfma_bf16x3"]["rel_l2_O"] < max(10 * out["fft_f32"]["rel_l2_O"], 1e-3)
