@@ -1533,11 +1533,14 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
   const Tables& tb = pl->tb;
   int* ctr = pl->at<int>(tb.o_ctr);
   int* flag = pl->at<int>(tb.o_flag);
-  // reset the history slot counter and the non-finite flag (kernels, not memsets)
-  k_fill<int><<<1, 64, 0, s>>>(ctr, 0, 1);
-  k_fill<int><<<1, 64, 0, s>>>(flag, 0, 1);
-  LAUNCH_CHECK(pl, "k_fill");
-  if (n_iter == 0) return ELFPIE_OK;
+  if (n_iter == 0) {
+    // reset the history slot counter and the non-finite flag (kernels, not memsets); a run
+    // of iterations does it in its opening graph
+    k_fill<int><<<1, 64, 0, s>>>(ctr, 0, 1);
+    k_fill<int><<<1, 64, 0, s>>>(flag, 0, 1);
+    LAUNCH_CHECK(pl, "k_fill");
+    return ELFPIE_OK;
+  }
   const bool chain = tb.rowupd;
   // the graphs bake in every pointer of the iteration: reuse them only for the same ones
   const bool same = pl->gvalid && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
@@ -1552,6 +1555,10 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
       const bool cont = g % 2 == 1;
       if (cont && !chain) continue;
       HIP_TRY(pl, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+      if (!cont) {  // an opening graph resets the history slot counter and the non-finite flag
+        k_fill<int><<<1, 64, 0, pl->cap>>>(ctr, 0, 1);
+        k_fill<int><<<1, 64, 0, pl->cap>>>(flag, 0, 1);
+      }
       const elfpie_status r = dispatch(pl, [&](auto ops) {
         return decltype(ops)::iterations(pl, st, meas, kGraphSizes[level], d_loss_hist, pl->cap, cont, !chain);
       });
@@ -1576,11 +1583,19 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
     ++pl->replays;
     return ELFPIE_OK;
   };
-  // the first replay opens the chain, the others continue it, a last launch closes it
+  // the first replay opens the chain, the others continue it, a last launch closes it.
+  // n_iter = 32 q + r: the graphs of r's binary digits go first, smallest first, then the q
+  // graphs of 32, so that the host submits each larger graph while the GPU runs the smaller
+  // ones before it (a graph of many nodes takes longer to submit than a small one to run)
+  int reps[kGraphLevels] = {};
   int left = n_iter;
+  for (int level = 0; level < kGraphLevels; ++level) {
+    reps[level] = left / kGraphSizes[level];
+    left -= reps[level] * kGraphSizes[level];
+  }
   bool opened = false;
-  for (int level = 0; level < kGraphLevels; ++level)
-    for (; left >= kGraphSizes[level]; left -= kGraphSizes[level]) {
+  for (int level = kGraphLevels - 1; level >= 0; --level)
+    for (int i = 0; i < reps[level]; ++i) {
       CHECK(replay(level, chain && opened));
       opened = true;
     }
