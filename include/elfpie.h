@@ -285,11 +285,14 @@ elfpie_status elfpie_batch_create(elfpie_plan *const *plans, const elfpie_state 
                                   int32_t n_tiles, int32_t n_branches, elfpie_batch **out);
 elfpie_status elfpie_batch_destroy(elfpie_batch *batch);
 
-/* n_iter iterations of Algorithm 1 on every tile, each a replay of the batch graph on
- * `stream`.  d_loss_hist: NULL, or a HOST array of n_tiles DEVICE pointers, each
- * n_iter x 4 doubles as in elfpie_run (NULL entries allowed).  The graph is captured
- * on the first call and again whenever the history pointers or the branch count
- * change.  Results per tile equal those of elfpie_run on that tile alone. */
+/* n_iter iterations of Algorithm 1 on every tile, replays of the batch graphs on
+ * `stream`: one graph of one iteration of every tile opens a chain of iterations (as
+ * elfpie_run does for a single plan), a second continues it n_iter - 1 times, a third
+ * closes it.  d_loss_hist: NULL, or a HOST array of n_tiles DEVICE pointers, each
+ * n_iter x 4 doubles as in elfpie_run (NULL entries allowed).  The graphs are captured
+ * on the first call and again whenever the history pointers, the branch count or a
+ * plan's penalty weights change; old graphs are destroyed after their last replays.
+ * Results per tile equal those of elfpie_run on that tile alone. */
 elfpie_status elfpie_batch_run(elfpie_batch *batch, int32_t n_iter, double *const *d_loss_hist, void *stream);
 
 /* Branch-count tuning: for 1, 2, 4 and 8 branches (at most n_tiles) the batch graph

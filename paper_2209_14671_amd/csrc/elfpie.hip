@@ -1712,9 +1712,13 @@ struct elfpie_batch {
   hipStream_t streams[kMaxBranch] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kMaxBranch] = {};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipEvent_t done = nullptr;  // recorded after the last replay of exec
+  // graphs of one iteration of every tile: [0] opens a chain of iterations (or, in tuning
+  // mode, one gradient evaluation), [1] continues it, [2] closes it (the pending pupil
+  // updates); tiles whose plans do not chain run whole iterations in [0] and [1]
+  static constexpr int kNG = 3;
+  hipGraph_t graph[kNG] = {};
+  hipGraphExec_t exec[kNG] = {};
+  hipEvent_t done = nullptr;  // recorded after the last replay of the execs
   int exec_mode = -1;  // 0: update steps, 1: gradients (tuning)
   int exec_branches = 0;
   std::vector<double*> exec_hist;
@@ -1755,18 +1759,21 @@ void batch_assign(elfpie_batch* b, int nb) {
 }
 
 void batch_drop_graph(elfpie_batch* b) {
-  // the exec may still be replaying on the caller's stream: wait for its last replay
+  // the execs may still be replaying on the caller's stream: wait for their last replay
   if (b->done) (void)hipEventSynchronize(b->done);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
+  for (int g = 0; g < elfpie_batch::kNG; ++g) {
+    if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+    if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+    b->exec[g] = nullptr;
+    b->graph[g] = nullptr;
+  }
   b->exec_mode = -1;
 }
 
-// Capture one iteration (mode 0) or one gradient evaluation (mode 1) of every tile.
-elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
-  batch_drop_graph(b);
+// Capture graph `which` of every tile: in update mode (mode 0) the opening (0), continuing
+// (1) or closing (2) graph of a chain of single iterations, in tuning mode (mode 1) one
+// gradient evaluation.  The tiles run on their branches between a fork and a join.
+elfpie_status batch_capture_one(elfpie_batch* b, int mode, int which, double* const* hist) {
   hipStream_t origin = b->streams[0];
   BATCH_TRY(b, hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
   elfpie_status r = ELFPIE_OK;
@@ -1776,11 +1783,20 @@ elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
     elfpie_plan* pl = b->plans[t];
     const elfpie_state* st = &b->states[t];
     hipStream_t s = b->streams[b->branch[t]];
+    double* h = hist ? hist[t] : nullptr;
+    const bool chain = pl->tb.rowupd;  // as in elfpie_run: row-form plans chain their iterations
     r = dispatch(pl, [&](auto ops) {
       using O = decltype(ops);
-      if (mode == 0) return O::iterations(pl, st, b->meas[t], 1, hist ? hist[t] : nullptr, s);
-      return O::iteration(pl, st->psi, st->P, b->meas[t], nullptr, pl->template at<void>(pl->tb.o_G),
-                          pl->template at<void>(pl->tb.o_gP), pl->template at<double>(pl->tb.o_loss), nullptr, s);
+      if (mode == 1)
+        return O::iteration(pl, st->psi, st->P, b->meas[t], nullptr, pl->template at<void>(pl->tb.o_G),
+                            pl->template at<void>(pl->tb.o_gP), pl->template at<double>(pl->tb.o_loss), nullptr, s);
+      if (which == 0) {  // the history slot counter and the non-finite flag start at zero
+        k_fill<int><<<1, 64, 0, s>>>(pl->template at<int>(pl->tb.o_ctr), 0, 1);
+        k_fill<int><<<1, 64, 0, s>>>(pl->template at<int>(pl->tb.o_flag), 0, 1);
+      }
+      if (!chain) return which == 2 ? ELFPIE_OK : O::iterations(pl, st, b->meas[t], 1, h, s);
+      if (which == 2) return O::close_run(pl, st, h, s);
+      return O::iterations(pl, st, b->meas[t], 1, h, s, which == 1, false);
     });
     if (r != ELFPIE_OK) b->err = pl->err;
   }
@@ -1795,8 +1811,24 @@ elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
     if (r != ELFPIE_OK) return batch_err(b, r, b->err);
     return batch_err(b, ELFPIE_E_DEVICE, std::string("batch capture: ") + hipGetErrorString(e != hipSuccess ? e : ec));
   }
-  b->graph = g;
-  BATCH_TRY(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->graph[which] = g;
+  BATCH_TRY(b, hipGraphInstantiate(&b->exec[which], g, nullptr, nullptr, 0));
+  return ELFPIE_OK;
+}
+
+// Capture the graphs of update mode (opening, continuing, closing) or of tuning mode.
+elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
+  batch_drop_graph(b);
+  bool any_chain = false;
+  for (elfpie_plan* pl : b->plans) any_chain = any_chain || pl->tb.rowupd;
+  for (int which = 0; which < (mode == 0 ? elfpie_batch::kNG : 1); ++which) {
+    if (which == 2 && !any_chain) break;  // nothing to close
+    const elfpie_status r = batch_capture_one(b, mode, which, hist);
+    if (r != ELFPIE_OK) {
+      batch_drop_graph(b);
+      return r;
+    }
+  }
   b->exec_mode = mode;
   b->exec_branches = b->nbranch;
   b->exec_hist.assign(b->plans.size(), nullptr);
@@ -1866,21 +1898,27 @@ elfpie_status elfpie_batch_run(elfpie_batch* b, int32_t n_iter, double* const* d
   if (!b) return ELFPIE_E_INVALID;
   if (n_iter < 0) return batch_err(b, ELFPIE_E_INVALID, "n_iter must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  bool same = b->exec && b->exec_mode == 0 && b->exec_branches == b->nbranch;
+  bool same = b->exec[0] && b->exec_mode == 0 && b->exec_branches == b->nbranch;
   // the same history pointers, and no plan whose captured launch arguments changed since
   for (size_t t = 0; same && t < b->plans.size(); ++t)
     same = b->exec_hist[t] == (d_loss_hist ? d_loss_hist[t] : nullptr) && b->exec_gen[t] == b->plans[t]->gen;
-  // the graph is captured on the batch's own streams and launched on `stream`
-  for (elfpie_plan* pl : b->plans) {  // history slot counters and non-finite flags
-    k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_ctr), 0, 1);
-    k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_flag), 0, 1);
+  if (n_iter == 0) {  // history slot counters and non-finite flags only
+    for (elfpie_plan* pl : b->plans) {
+      k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_ctr), 0, 1);
+      k_fill<int><<<1, 64, 0, s>>>(pl->at<int>(pl->tb.o_flag), 0, 1);
+    }
+    BATCH_TRY(b, hipGetLastError());
+    return ELFPIE_OK;
   }
-  BATCH_TRY(b, hipGetLastError());
+  // the graphs are captured on the batch's own streams and launched on `stream`: the first
+  // replay opens a chain of iterations (resetting the counters), the others continue it, and
+  // the closing graph runs the last pending pupil updates
   if (!same) {
     const elfpie_status r = batch_capture(b, 0, d_loss_hist);
     if (r != ELFPIE_OK) return r;
   }
-  for (int i = 0; i < n_iter; ++i) BATCH_TRY(b, hipGraphLaunch(b->exec, s));
+  for (int i = 0; i < n_iter; ++i) BATCH_TRY(b, hipGraphLaunch(b->exec[i == 0 ? 0 : 1], s));
+  if (b->exec[2]) BATCH_TRY(b, hipGraphLaunch(b->exec[2], s));
   BATCH_TRY(b, hipEventRecord(b->done, s));
   return ELFPIE_OK;
 }
@@ -1902,9 +1940,9 @@ elfpie_status elfpie_batch_tune(elfpie_batch* b, int32_t n_rep, float* ms_out, i
     if (nb > (int)b->plans.size()) break;
     batch_assign(b, nb);
     if ((r = batch_capture(b, 1, nullptr)) != ELFPIE_OK) break;
-    hipError_t e = hipGraphLaunch(b->exec, s);  // warm
+    hipError_t e = hipGraphLaunch(b->exec[0], s);  // warm
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int i = 0; i < n_rep && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec, s);
+    for (int i = 0; i < n_rep && e == hipSuccess; ++i) e = hipGraphLaunch(b->exec[0], s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventRecord(b->done, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
