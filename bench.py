@@ -193,13 +193,25 @@ def optimizer_bench(args, dev):
                       "optimizers": rows}), flush=True)
 
 
+SWEEP_NOISES = ("gaussian", "snp", "poisson")
+# Table 1's dark-field noise levels (%), by noise type, then c in (0.25, 0.5, 0.75), then level.
+TABLE1_NL = {
+    "gaussian": ((20.49, 99.18, 800.10, 7669.71), (31.02, 102.59, 796.48, 7662.03), (41.98, 107.06, 793.00, 7656.55)),
+    "snp": ((989.06, 9583.58, 47757.62, 95453.10), (971.87, 9648.64, 47799.04, 95697.25),
+            (972.56, 9543.86, 47771.76, 95571.99)),
+    "poisson": ((36.37, 66.13, 81.07, 94.23), (41.78, 67.58, 80.57, 92.12), (49.39, 70.74, 81.67, 91.36)),
+}
+
+
 def sweep_bench(args, dev, iters=100):
-    """Sec. 4.2 grid on synthetic stacks of the paper's shape (512^2 / K=225 / 128^2, FP32):
-    LED shift d in {0, 0.5, 2} mm, uneven illumination c in {0.25, 0.75} (radial fall-off of
-    strength c), and Gaussian (sigma 1e-3 of the peak), Poisson (1e3 photons at the peak) or
-    salt-and-pepper (1e-3) noise.  Each case: simulate, degrade, reconstruct for `iters`
-    iterations from the standard initial state, report LSNR of |O| and angle(O) against the
-    ground truth, the dark-field noise level (Eq. 21) and the GPU time."""
+    """Sec. 4.2's simulation study on synthetic stacks of the paper's shape (512^2 / K=225 /
+    128^2, FP32, pupil learning on), every case reconstructed together in ONE batch (one
+    graph replay per iteration of all of them): LED shift d in {0, 0.5, 2} mm (simulation
+    only), illumination strength c in {0.25, 0.5, 0.75} and Table 1's four levels of
+    Gaussian, salt-and-pepper and Poisson noise (Eq. 20), `reps` seeds per cell (an object
+    and an LED shift per seed, shared by the cells).  Per cell: the dark-field noise level
+    (Eq. 21) beside Table 1's, and the LSNR (Eq. 22) of abs(O) and angle(O) after `iters`
+    iterations, averaged over seeds.  Also the batch's time per iteration."""
     import torch
 
     import synth
@@ -207,40 +219,71 @@ def sweep_bench(args, dev, iters=100):
     from paper_2209_14671_amd import metrics
     optics = synth.Optics(n_lo=128, upsample=4, led_grid=15)
     flags = E.LEARN_PUPIL | E.PUPIL_SUPPORT | E.PUPIL_FILTER
-    noises = {"gaussian": dict(gauss_sigma_rel=1e-3), "poisson": dict(photons=1e3), "snp": dict(snp_prob=1e-3)}
+    cells, tiles, k_total = [], [], 0
+    for rep in range(args.reps):
+        for di, d in enumerate((0.0, 0.5, 2.0)):
+            base = synth.make_case(optics, [6, rep], jitter_mm=d)
+            sim = E.Plan(E.problem_from_optics(optics, base.led_k_true, precision=E.F32), device=dev)
+            psi_true = sim.spectrum_from_object(torch.from_numpy(base.obj).to(torch.complex64).to(dev))
+            clean = sim.forward(psi_true, torch.from_numpy(base.pupil).to(torch.complex64).to(dev),
+                                intens=True)["intens"].cpu().numpy().astype(np.float64)
+            sim.close()
+            dark = metrics.dark_field(base.led_k_true, optics.n_lo, optics.dx_lo_um, optics.wavelength_um, optics.na)
+            for ci, c in enumerate((0.25, 0.5, 0.75)):
+                for ni, noise in enumerate(SWEEP_NOISES):
+                    for lv in range(4):
+                        deg = synth.sweep_degradation(noise, lv, c)
+                        noisy = synth.degrade(clean, deg, np.random.SeedSequence([6, rep, di, ci, ni, lv]), dark=dark)
+                        meas = torch.from_numpy(noisy).to(torch.float32).to(dev)
+                        plan = E.Plan(E.problem_from_optics(optics, base.led_k, precision=E.F32, flags=flags),
+                                      device=dev)
+                        tiles.append((plan, plan.init_state(meas), meas))
+                        k_total += plan.K
+                        cells.append({"rep": rep, "d_mm": d, "c": c, "noise": noise, "level": lv + 1, "obj": base.obj,
+                                      "nl": metrics.noise_level(clean, noisy, dark)})
+            log(f"seed {rep}, d = {d} mm: {len(tiles)} stacks built")
+    batch = E.Batch(tiles, n_branches=4)
+    tune = batch.tune(2)
+    branches = batch.n_branches
+    log(f"{len(tiles)} tiles in one batch, {branches} branches ({tune})")
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    batch.run(iters, history=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    for cell, (plan, st, _) in zip(cells, tiles):
+        O = plan.object_from_spectrum(st.psi).cpu().numpy().astype(np.complex128)
+        cell["la"] = metrics.lsnr(np.abs(O), np.abs(cell["obj"]))
+        cell["lp"] = metrics.lsnr(np.angle(O), np.angle(cell["obj"]))
+    batch.close()
+    for plan, _, _ in tiles:
+        plan.close()
     rows = []
     for d in (0.0, 0.5, 2.0):
-        for c in (0.25, 0.75):
-            for name, kw in noises.items():
-                case = synth.make_case(optics, [5, int(d * 10), int(c * 100), len(rows)], jitter_mm=d,
-                                       degradation=synth.Degradation(vignetting=c, **kw))
-                sim = E.Plan(E.problem_from_optics(optics, case.led_k_true, precision=E.F32), device=dev)
-                psi_true = sim.spectrum_from_object(torch.from_numpy(case.obj).to(torch.complex64).to(dev))
-                clean = sim.forward(psi_true, torch.from_numpy(case.pupil).to(torch.complex64).to(dev),
-                                    intens=True)["intens"].cpu().numpy().astype(np.float64)
-                sim.close()
-                noisy = synth.degrade(clean, case.degradation, case.noise_seed)
-                meas = torch.from_numpy(noisy).to(torch.float32).to(dev)
-                plan = E.Plan(E.problem_from_optics(optics, case.led_k, precision=E.F32, flags=flags), device=dev)
-                st = plan.init_state(meas)
-                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                ev0.record()
-                plan.run(st, meas, iters)
-                ev1.record()
-                torch.cuda.synchronize()
-                O = plan.object_from_spectrum(st.psi).cpu().numpy().astype(np.complex128)
-                plan.close()
-                dark = metrics.dark_field(case.led_k_true, optics.n_lo, optics.dx_lo_um, optics.wavelength_um,
-                                          optics.na)
-                la = metrics.lsnr(np.abs(O), np.abs(case.obj))
-                lp = metrics.lsnr(np.angle(O), np.angle(case.obj))
-                rows.append({"d_mm": d, "c": c, "noise": name, "NL_pct": round(metrics.noise_level(clean, noisy, dark), 2),
-                             "lsnr_amp_db": round(la, 2), "lsnr_phase_db": round(lp, 2),
-                             "lsnr_mean_db": round((la + lp) / 2, 2), "gpu_ms": round(ev0.elapsed_time(ev1), 2)})
-                log(f"d={d} c={c} {name}: LSNR amp {la:.2f} dB, phase {lp:.2f} dB")
-    print(json.dumps({"metric": "reconstruction LSNR (Eq. 22) over the Sec. 4.2 grid, synthetic stacks",
-                      "unit": "dB", "iterations": iters, "dtype": "f32", "data": "synthetic",
-                      "config": {"workload": "512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, circular pupil"},
+        for ci, c in enumerate((0.25, 0.5, 0.75)):
+            for noise in SWEEP_NOISES:
+                for lv in range(1, 5):
+                    sel = [x for x in cells if x["d_mm"] == d and x["c"] == c and x["noise"] == noise
+                           and x["level"] == lv]
+                    la = float(np.mean([x["la"] for x in sel]))
+                    lp = float(np.mean([x["lp"] for x in sel]))
+                    rows.append({"d_mm": d, "c": c, "noise": noise, "level": lv,
+                                 "NL_pct": round(float(np.mean([x["nl"] for x in sel])), 2),
+                                 "NL_pct_table1": TABLE1_NL[noise][ci][lv - 1],
+                                 "lsnr_amp_db": round(la, 2), "lsnr_phase_db": round(lp, 2),
+                                 "lsnr_mean_db": round((la + lp) / 2, 2)})
+                    if lv in (1, 4):
+                        log(f"d={d} c={c} {noise} Lv{lv}: NL {rows[-1]['NL_pct']} % (Table 1: "
+                            f"{rows[-1]['NL_pct_table1']} %), LSNR amp {la:.2f} dB, phase {lp:.2f} dB")
+    print(json.dumps({"metric": "reconstruction LSNR (Eq. 22) over the Sec. 4.2 grid with Table 1's noise levels",
+                      "unit": "dB", "iterations": iters, "reps": args.reps, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "512x512 high-res, 15x15 LEDs (K=225), 128x128 low-res, circular "
+                                             "pupil; every case in one batch", "tiles": len(tiles),
+                                 "branches": branches},
+                      "batch_ms_per_iter": round(ms / iters, 4),
+                      "led_updates_per_s": round(k_total * iters / (ms / 1e3), 1),
                       "rows": rows}), flush=True)
 
 
@@ -413,6 +456,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-reps", type=int, default=50)
+    ap.add_argument("--reps", type=int, default=1,
+                    help="sweep: seeds per cell of the grid (108 cells, one 512^2 / K=225 stack each)")
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the plain device copy timed after the run (0: skip); the same copy "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters in counter runs")
@@ -425,7 +470,8 @@ def main():
                          "differentiable loss at 256^2 / K=121 / 64^2, recomputed against stored fields; "
                          "optimizers: loss curves of Eq. 19 and the Sec. 6.2 alternatives on the "
                          "512^2 / K=225 / 128^2 stack; sweep: reconstruction quality (LSNR, Eq. 22) over LED "
-                         "shift, uneven illumination and noise (the Tables 2-4 grid) on synthetic stacks; "
+                         "shift, uneven illumination and Table 1's noise levels (the Tables 2-4 grid) on "
+                         "synthetic stacks, all reconstructed in one batch; "
                          "precision: the FFT form against the split-BF16 matrix-core row transforms at "
                          "1024^2 / K=225 / 256^2")
     args = ap.parse_args()

@@ -31,6 +31,7 @@ import numpy as np
 __all__ = [
     "Optics", "Degradation", "Case", "smooth_field", "make_object", "led_grid_positions",
     "led_wavevectors", "true_pupil", "degrade", "make_case", "config_case", "config3_tiles", "centre_subgrid",
+    "illumination_field", "poisson_rel_mad", "poisson_counts_per_unit", "SWEEP_UNIT_DF_MEAN", "SWEEP_LEVELS", "sweep_degradation",
 ]
 
 
@@ -64,13 +65,29 @@ class Optics:
 class Degradation:
     """Measurement corruptions applied to a clean intensity stack (all optional).
 
-    Applied in this order: radial vignetting, Poisson photon noise, additive
-    Gaussian noise, salt-and-pepper, clipping at zero.
+    Two families.  Relative ones (``vignetting``, ``photons``, ``gauss_sigma_rel``,
+    ``snp_prob``) are scaled by the stack maximum.  The noise model of Eq. (20) works in
+    camera units instead: with ``unit_df_mean`` > 0 the stack is first scaled so that the
+    dark-field images' mean readings have ``unit_df_mean`` as their harmonic mean, the
+    per-image illumination field of strength ``illum_c`` multiplies each image, then
+    Poisson noise (``poisson_nl_pct``), additive Gaussian noise (``gauss_abs``) and
+    salt-and-pepper of density ``snp_density`` (salt = 1, the full-scale reading) are
+    applied in those units, and the result is scaled back.
+
+    Applied in this order: unit scaling, illumination field, radial vignetting, Poisson
+    photon noise, additive Gaussian noise, salt-and-pepper, clipping at zero (a camera
+    reads no negative intensity), scaling back.
     """
     vignetting: float = 0.0          # V(rho) = 1 - vignetting * (rho / rho_max)^2
     photons: float = 0.0             # photon count at the stack maximum (0: no Poisson noise)
     gauss_sigma_rel: float = 0.0     # Gaussian sigma as a fraction of the stack maximum
     snp_prob: float = 0.0            # salt-and-pepper probability per pixel (half 0, half max)
+    unit_df_mean: float = 0.0        # > 0: camera units (harmonic mean of the dark-field mean readings)
+    illum_c: float = 0.0             # Eq. 20's c: each image times (1 - c) + c u_n
+    illum_waist_px: float = 15.0     # 1/e^2 radius of the Gaussian blur that makes u_n
+    poisson_nl_pct: float = 0.0      # Poisson counts set for this Eq. 21 noise level (0: none)
+    gauss_abs: float = 0.0           # Eq. 20's a for Gaussian noise, in camera units
+    snp_density: float = 0.0         # Eq. 20's a for salt-and-pepper (half 0, half 1)
 
 
 @dataclasses.dataclass
@@ -148,11 +165,75 @@ def true_pupil(optics: Optics, zernike_rad: Optional[np.ndarray] = None) -> np.n
     return p
 
 
-def degrade(clean: np.ndarray, spec: Degradation, seed: np.random.SeedSequence) -> np.ndarray:
-    """Corrupt a clean (K, n, n) intensity stack per ``spec``; returns float64."""
+def illumination_field(rng: np.random.Generator, n: int, waist_px: float) -> np.ndarray:
+    """u_n of Eq. (20): standard normal noise blurred (periodically) by a Gaussian of 1/e^2
+    radius ``waist_px`` (std waist/2), min-max scaled to [0, 1]."""
+    z = rng.standard_normal((n, n))
+    f = np.fft.fftfreq(n)
+    sig = waist_px / 2.0
+    g = np.exp(-2.0 * (math.pi * sig) ** 2 * (f[:, None] ** 2 + f[None, :] ** 2))
+    s = np.real(np.fft.ifft2(np.fft.fft2(z) * g))
+    s -= s.min()
+    m = s.max()
+    return s / m if m > 0 else s
+
+
+def poisson_rel_mad(mu: np.ndarray) -> np.ndarray:
+    """E|X - mu| / mu for X ~ Poisson(mu), mu > 0: the mean absolute deviation of the
+    Poisson law is 2 mu^(k+1) e^-mu / k! with k = floor(mu), so the ratio is
+    2 mu^k e^-mu / k!, continuous and decreasing in mu (2 as mu -> 0)."""
+    from scipy.special import gammaln
+    mu = np.asarray(mu, dtype=np.float64)
+    k = np.floor(mu)
+    return 2.0 * np.exp(k * np.log(mu) - mu - gammaln(k + 1.0))
+
+
+def poisson_counts_per_unit(images: np.ndarray, nl_pct: float) -> float:
+    """Counts per camera unit s at which Poisson noise alone has expected Eq. 21 level
+    nl_pct over ``images`` (readings in camera units): the mean over images of
+    sum_p E|X_p - s r_p| / sum_p s r_p, X_p ~ Poisson(s r_p).  The mean is decreasing in
+    s; bisection on a log scale."""
+    target = nl_pct / 100.0
+    r = np.asarray(images, dtype=np.float64).reshape(len(images), -1)
+    tot = r.sum(axis=1)
+    if not 0.0 < target < 2.0 or r.size == 0 or np.any(tot <= 0) or np.any(r < 0):
+        raise ValueError("a Poisson noise level lies in (0, 200) % over non-negative, non-empty images")
+    pos = r > 0
+
+    def level(s):
+        mu = s * r
+        mad = np.where(pos, mu * poisson_rel_mad(np.where(pos, mu, 1.0)), 0.0)
+        return float((mad.sum(axis=1) / (s * tot)).mean())
+
+    lo, hi = 1e-6 / r.max(), 1e8 * r.shape[1] / tot.min()
+    for _ in range(80):
+        mid = math.sqrt(lo * hi)
+        if level(mid) > target:
+            lo = mid
+        else:
+            hi = mid
+    return math.sqrt(lo * hi)
+
+
+def degrade(clean: np.ndarray, spec: Degradation, seed: np.random.SeedSequence,
+            dark: Optional[np.ndarray] = None) -> np.ndarray:
+    """Corrupt a clean (K, n, n) intensity stack per ``spec``; returns float64.  ``dark``
+    (a boolean per image) marks the dark-field images; camera units need it."""
     rng = np.random.default_rng(seed)
     img = np.array(clean, dtype=np.float64, copy=True)
     n = img.shape[-1]
+    unit = 1.0
+    if spec.unit_df_mean:
+        if dark is None or not np.any(dark):
+            raise ValueError("camera units need the dark-field images (dark)")
+        means = img[np.asarray(dark, dtype=bool)].mean(axis=(1, 2))
+        if np.any(means <= 0.0):
+            raise ValueError("a dark-field image is empty")
+        unit = spec.unit_df_mean * float(np.mean(1.0 / means))
+        img *= unit
+    if spec.illum_c:
+        for k in range(img.shape[0]):
+            img[k] *= (1.0 - spec.illum_c) + spec.illum_c * illumination_field(rng, n, spec.illum_waist_px)
     if spec.vignetting:
         c = (n - 1) / 2.0
         y, x = np.meshgrid(np.arange(n) - c, np.arange(n) - c, indexing="ij")
@@ -162,13 +243,54 @@ def degrade(clean: np.ndarray, spec: Degradation, seed: np.random.SeedSequence) 
     if spec.photons and peak > 0:
         s = spec.photons / peak
         img = rng.poisson(np.clip(img, 0.0, None) * s).astype(np.float64) / s
+    if spec.poisson_nl_pct:
+        if not spec.unit_df_mean:
+            raise ValueError("Poisson noise by level needs camera units")
+        s = poisson_counts_per_unit(img[np.asarray(dark, dtype=bool)][:, ::4, ::4], spec.poisson_nl_pct)
+        img = rng.poisson(np.clip(img, 0.0, None) * s).astype(np.float64) / s
     if spec.gauss_sigma_rel:
         img += rng.normal(0.0, spec.gauss_sigma_rel * peak, size=img.shape)
+    if spec.gauss_abs:
+        img += rng.normal(0.0, spec.gauss_abs, size=img.shape)
     if spec.snp_prob:
         u = rng.random(img.shape)
         img[u < spec.snp_prob / 2] = 0.0
         img[(u >= spec.snp_prob / 2) & (u < spec.snp_prob)] = peak
-    return np.clip(img, 0.0, None)
+    if spec.snp_density:
+        u = rng.random(img.shape)
+        img[u < spec.snp_density / 2] = 0.0
+        img[(u >= spec.snp_density / 2) & (u < spec.snp_density)] = 1.0
+    img = np.clip(img, 0.0, None)
+    return img / unit if unit != 1.0 else img
+
+
+# Eq. (20)'s noise grid in camera units.  Table 1 prints the dark-field noise level of
+# Eq. (21) per level.  Additive Gaussian noise of std a, clipped at zero, leaves a mean
+# absolute error of a / sqrt(2 pi) on a dark pixel, and Table 1's Gaussian row grows as
+# about 7.7e5 a percent, which puts the dark-field readings at about 5.2e-5 units (the
+# harmonic mean of the images' mean readings, as Eq. 21 averages per-image ratios).
+SWEEP_UNIT_DF_MEAN = 5.2e-5
+SWEEP_LEVELS = {
+    "gaussian": (1e-5, 1e-4, 1e-3, 1e-2),      # a, Table 1
+    "snp": (1e-3, 1e-2, 1e-1, 2e-1),           # density a, Table 1
+    "poisson": (36.37, 66.13, 81.07, 94.23),   # Lv 1-4: Table 1's noise level (%) at c = 0.25
+}
+
+
+def sweep_degradation(noise: str, level: int, c: float) -> Degradation:
+    """Eq. (20) at Table 1's level ``level`` (0-3) of ``noise`` with illumination strength c.
+    Poisson Lv n has no printed photon count: its counts per unit give Poisson noise alone,
+    on the illuminated dark-field images (every fourth pixel in each direction), the
+    expected noise level Table 1 prints for Lv n at c = 0.25."""
+    if noise not in SWEEP_LEVELS:
+        raise ValueError(f"unknown noise type {noise!r}")
+    a = SWEEP_LEVELS[noise][level]
+    kw = dict(unit_df_mean=SWEEP_UNIT_DF_MEAN, illum_c=c)
+    if noise == "gaussian":
+        return Degradation(gauss_abs=a, **kw)
+    if noise == "snp":
+        return Degradation(snp_density=a, **kw)
+    return Degradation(poisson_nl_pct=a, **kw)
 
 
 def make_case(optics: Optics, seed, *, zernike_std: float = 0.0, jitter_mm: float = 0.0,

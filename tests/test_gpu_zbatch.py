@@ -7,8 +7,9 @@ import numpy as np
 import pytest
 
 import oracle as orc
+import synth
 from helpers import rel_l2
-from pairs import make_pair
+from pairs import Pair, make_pair
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -123,4 +124,70 @@ def test_batch_tuning_keeps_states_and_picks_a_count():
     h = batch.run(2)
     torch.cuda.synchronize()
     assert all(torch.isfinite(x).all() for x in h)
+    batch.close()
+
+
+def test_sweep_stacks_in_one_batch_match_the_oracle():
+    """The robustness sweep's inputs (Eq. 20 with Table 1's second level of Gaussian,
+    salt-and-pepper and Poisson noise, c = 0.25 and 0.75, LEDs shifted 0.5 mm) in one batch,
+    literal L1 as the sweep runs it, from the oracle's state two iterations in: the next batched
+    iteration of every tile against the oracle's step at the library's sign decisions
+    (rel-L2 1e-5 and elementwise), then three more batched iterations equal to the same
+    tile run alone, bit for bit."""
+    import ties
+    from paper_2209_14671_amd import metrics
+    e = E()
+    optics = synth.Optics(n_lo=32, upsample=4, led_grid=9)
+    base = synth.make_case(optics, [8, 0], jitter_mm=0.5)
+    sim = orc.problem_from_optics(optics, base.led_k_true, flags=orc.PUPIL_SUPPORT)
+    clean = orc.intensities(orc.spectrum_from_object(base.obj), base.pupil, sim)
+    dark = metrics.dark_field(base.led_k_true, optics.n_lo, optics.dx_lo_um, optics.wavelength_um, optics.na)
+    flags = orc.LEARN_PUPIL | orc.PUPIL_SUPPORT | orc.PUPIL_FILTER
+    oprob = orc.problem_from_optics(optics, base.led_k, flags=flags)
+    kw = dict(n_lo=optics.n_lo, upsample=optics.upsample, led_k=base.led_k, wavelength_um=optics.wavelength_um,
+              na=optics.na, dx_lo_um=optics.dx_lo_um, flags=flags)
+    f = lambda a: a.astype(np.complex64).astype(np.complex128)  # noqa: E731
+    tiles, pairs = [], []
+    for ci, c in enumerate((0.25, 0.75)):
+        for ni, noise in enumerate(("gaussian", "snp", "poisson")):
+            noisy = synth.degrade(clean, synth.sweep_degradation(noise, 1, c), np.random.SeedSequence([8, ci, ni]),
+                                  dark=dark)
+            meas = noisy.astype(np.float32).astype(np.float64)
+            s0 = orc.init_state(meas, oprob)
+            for _ in range(2):  # off the initial state, whose object is real (all phase features tie)
+                s0, _ = orc.step(s0, meas, oprob)
+            r = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+            s0 = orc.State(f(s0.psi), f(s0.P), f(s0.mu_psi), s0.v_psi, r(s0.delta_psi), f(s0.mu_P), s0.v_P,
+                           r(s0.delta_P), s0.t)
+            pair = Pair(oprob, kw, s0.psi, s0.P, meas, s0)
+            plan = e.Plan(e.Problem(precision=e.F32, **kw))
+            st = e.State(psi=dev(s0.psi, True), P=dev(s0.P, True), mu_psi=dev(s0.mu_psi, True),
+                         v_psi=torch.from_numpy(s0.v_psi.copy()).cuda(), delta_psi=dev(s0.delta_psi, True),
+                         mu_P=dev(s0.mu_P, True), v_P=torch.from_numpy(s0.v_P.copy()).cuda(),
+                         delta_P=dev(s0.delta_P, True), t=torch.tensor([s0.t], dtype=torch.int64).cuda())
+            tiles.append((plan, st, dev(meas, True)))
+            pairs.append((pair, noise, c))
+    grads = []
+    for (plan, _, m), (pair, _, _) in zip(tiles, pairs):
+        _, g, gP = plan.grad(dev(pair.psi, True), dev(pair.P, True), m)
+        grads.append((g.cpu().numpy().astype(np.complex128), gP.cpu().numpy().astype(np.complex128)))
+    batch = e.Batch(tiles, n_branches=3)
+    batch.run(1, history=False)
+    torch.cuda.synchronize()
+    for (plan, st, _), (pair, noise, c), (gh, gph) in zip(tiles, pairs, grads):
+        T = ties.infer(pair, gh, gph)
+        ref = ties.step_from(pair, T.g_psi, T.g_P)
+        got, gotP = st.psi.cpu().numpy().astype(np.complex128), st.P.cpu().numpy().astype(np.complex128)
+        es, esp = rel_l2(got, ref["psi"]), rel_l2(gotP, ref["P"])
+        xs, xsp = ties.elementwise_excess(got, ref["psi"]), ties.elementwise_excess(gotP, ref["P"])
+        print(f"sweep tile {noise} c={c}: ties {T.n_fid}/{T.n_hess}, flips {T.flips_fid}/{T.flips_hess}; "
+              f"step psi {es:.2e} P {esp:.2e} elementwise {xs:.3f} {xsp:.3f}")
+        assert es < 1e-5 and esp < 1e-5 and xs <= 1.0 and xsp <= 1.0
+    alone = [(p, st.clone(), m) for p, st, m in tiles]
+    batch.run(3, history=False)
+    for p, st, m in alone:
+        p.run(st, m, 3, history=False)
+    torch.cuda.synchronize()
+    for (p, sb, _), (_, sa, _) in zip(tiles, alone):
+        assert torch.equal(sb.psi, sa.psi) and torch.equal(sb.P, sa.P)
     batch.close()

@@ -79,9 +79,9 @@ def _fidelity_ties(psi, P, meas, prob):
         bx[:, :-1] += err[:, 1:]
         by = err.copy()
         by[:-1, :] += err[1:, :]
-        tx = np.abs(cx) <= bx
+        tx = (np.abs(cx) <= bx) & (bx > 0)  # a zero bound: exact zeros on both sides
         tx[:, -1] = False  # structurally zero on both sides
-        ty = np.abs(cy) <= by
+        ty = (np.abs(cy) <= by) & (by > 0)
         ty[-1, :] = False
         items = [(0, y, x, np.sign(cx[y, x]), abs(cx[y, x]) / bx[y, x]) for y, x in zip(*np.nonzero(tx))]
         items += [(1, y, x, np.sign(cy[y, x]), abs(cy[y, x]) / by[y, x]) for y, x in zip(*np.nonzero(ty))]
