@@ -55,6 +55,13 @@ struct TailReq {
   TailArgs a{};
 };
 
+// A tail with nothing to do.
+inline TailReq no_tail() {
+  TailReq r;
+  r.fin = false;
+  return r;
+}
+
 // Blocks of NT threads that the tail needs: pupil pixels, then one loss block.
 inline TailArgs shape_tail(const TailReq& r, int nt) {
   TailArgs a = r.a;
@@ -318,6 +325,7 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->o_loss = take(4 * sizeof(double));
   tb->o_ctr = take(sizeof(int));
   tb->o_flag = take(sizeof(int));
+
   // multiplexed plans keep every LED's field between the two passes of the image
   tb->o_mux = tb->mux > 1 ? take((size_t)tb->K * n * n * cxb) : 0;
   // the large tile keeps the band rows of each LED's row transforms between launches
@@ -670,9 +678,17 @@ struct Ops {
 
   // The object blocks of a fused per-LED launch: T1 (inverse row transforms of psi) in,
   // the column-transformed Hessian-term gradient out in T2, loss partials in buffer par.
-  static LedObjArgs obj_args(elfpie_plan* pl, const void* T1, void* T2, int par) {
+  // pf: the LED blocks also write the pre-filtered pupil (for a step that filters it).
+  static LedObjArgs obj_args(elfpie_plan* pl, const void* T1, void* T2, int par, bool pf = false) {
     const Tables& tb = pl->tb;
     LedObjArgs o{};
+    if (pf) {
+      const PupilArgs pa = pupil_args(pl, nullptr);
+      o.Pf = pl->at<void>(tb.o_Pf);
+      o.w_c = pa.w_c;
+      o.w_e = pa.w_e;
+      o.w_k = pa.w_k;
+    }
     o.T1 = T1;
     o.T2 = T2;
     o.tw = pl->at<void>(tb.o_twhi);
@@ -763,7 +779,11 @@ struct Ops {
     a.pupil_blocks = 0;  // pupil partial sums and pre-filter, in blocks of NT threads
     if (pupil) {
       a.pupil_blocks = ((tb.S + NT - 1) / NT) * tb.nch;
-      if (prefilter) a.pupil_blocks += (tb.n_lo * tb.n_lo + NT - 1) / NT;
+      if (pa.final_in_launch)  // 32 support pixels per block, then the pixels off the
+                               // support; a multiple of 8 blocks
+        a.pupil_blocks = ((tb.S + 31) / 32 + (tb.n_lo * tb.n_lo + NT - 1) / NT + 7) / 8 * 8;
+      else if (prefilter)
+        a.pupil_blocks += (tb.n_lo * tb.n_lo + NT - 1) / NT;
     }
     const FinArgs fa = fin ? *fin : FinArgs{};
     k_update_rows<T, N><<<N / UpdRows<N>::RB + a.pupil_blocks + (fin ? 1 : 0), NT, 0, s>>>(a, pa, fa);
@@ -772,9 +792,12 @@ struct Ops {
   // With the row form (tb.rowupd), gH is the Hessian-term gradient before its forward
   // row transforms, and inv asks for the inverse row transforms of psi (as the launch
   // leaves it) in T1.
+  // final_pupil (row form only): the pupil update (or gradient) as the tail would apply it,
+  // completed in this launch (PupilArgs::final_in_launch; Pf from the per-LED launch).
   static elfpie_status update(elfpie_plan* pl, const elfpie_state* st, void* g_out, const void* gH,
                               const void* P, bool pupil, bool prefilter, hipStream_t s, bool inv = false,
-                              const void* psi = nullptr, const FinArgs* fin = nullptr) {
+                              const void* psi = nullptr, const FinArgs* fin = nullptr,
+                              const PupilArgs* final_pupil = nullptr) {
     const Tables& tb = pl->tb;
     UpdArgs a{};
     if (st) {
@@ -808,6 +831,12 @@ struct Ops {
     a.step = st ? 1 : 0;
     PupilArgs pa = pupil_args(pl, P);
     pa.filter = prefilter ? 1 : 0;
+    if (final_pupil && pupil) {
+      if (!tb.rowupd) return set_err(pl, ELFPIE_E_INVALID, "pupil update in the update launch needs the row form");
+      pa = *final_pupil;
+      pa.filter = prefilter ? 1 : 0;
+      pa.final_in_launch = 1;
+    }
     int pblocks = 0;
     if (pupil) {
       pblocks = ((tb.S + 255) / 256) * tb.nch;
@@ -948,6 +977,8 @@ struct Ops {
     void* T2 = pl->at<void>(tb.o_T2);
     elfpie_status r;
     const int mode = stored_fields ? LED_GRAD | LED_STORED : LED_GRAD;
+    const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
+    const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     if (tb.fused) {
       // the inverse row transforms of psi first (unless the previous update left them in
       // T1), with a pending tail riding along; else that tail alone: the per-LED launch
@@ -957,10 +988,19 @@ struct Ops {
       } else if (prev && (r = tail(pl, *prev, s)) != ELFPIE_OK) {
         return r;
       }
-      const LedObjArgs o = obj_args(pl, T1, T2, par);
+      const LedObjArgs o = obj_args(pl, T1, T2, par, pre);
       if ((r = led(pl, mode, psi, P, meas, const_cast<void*>(stored_fields), nullptr, s, st ? st->t : nullptr, &o)) !=
           ELFPIE_OK)
         return r;
+      // the pupil update (or gradient) and the loss complete in the update launch: nothing
+      // is left for a tail
+      const TailReq mine = tail_req(pl, learn_p, P, st, g_P, loss4, hist, par, iter_nhp(pl));
+      const FinArgs fa = fin_args(pl, loss4, hist, par, iter_nhp(pl));
+      if ((r = update(pl, st, g_psi, T2, P, learn_p, pre, s, st != nullptr, nullptr, &fa, &mine.a.pa)) !=
+          ELFPIE_OK)
+        return r;
+      if (defer) *defer = no_tail();
+      return ELFPIE_OK;
     } else {
       if ((r = object_branch(pl, psi, true, T1, T2, s, prev, t1_ready && tb.rowupd, !tb.rowupd, par)) != ELFPIE_OK)
         return r;
@@ -968,8 +1008,6 @@ struct Ops {
           ELFPIE_OK)
         return r;
     }
-    const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
-    const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
     // a deferred tail leaves its loss reduction to this update launch, so that only
     // the pupil update rides in the next strip launch
     const bool split = tb.rowupd && defer;
@@ -1008,6 +1046,7 @@ struct Ops {
   // The tail that a row-form update step defers: the pupil update alone (its loss was
   // reduced in the update launch), as iteration() returns it.
   static TailReq pending_pupil(elfpie_plan* pl, const elfpie_state* st, double* hist) {
+    if (pl->tb.fused) return no_tail();  // a fused plan's iterations leave no tail
     const bool learn_p = (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0;
     TailReq r = tail_req(pl, learn_p, st->P, st, nullptr, nullptr, hist, 1, iter_nhp(pl));
     r.fin = false;
@@ -1149,10 +1188,14 @@ struct Ops {
     HIP_TRY(pl, hipEventCreate(&e0));
     HIP_TRY(pl, hipEventCreate(&e1));
     elfpie_status r = ELFPIE_OK;
-    const TailReq tq = tail_req(pl, true, st->P, nullptr, gP, l4, nullptr, 0, iter_nhp(pl));
+    // a fused plan's update launch completes the pupil gradient and the loss, as in a run:
+    // its tail stage is empty
+    const TailReq tp = tail_req(pl, true, st->P, nullptr, gP, l4, nullptr, 0, iter_nhp(pl));
+    const TailReq tq = tb.fused ? no_tail() : tp;
+    const FinArgs fa = fin_args(pl, l4, nullptr, 0, iter_nhp(pl));
     // a fused plan's per-LED launch reads T1: the inverse row transforms of psi first
     if (tb.fused && (r = lines<true, false>(pl, st->psi, T1, s)) != ELFPIE_OK) return r;
-    const LedObjArgs o = obj_args(pl, T1, T2, 0);
+    const LedObjArgs o = obj_args(pl, T1, T2, 0, tb.fused);
     for (int stage = 0; stage < 4 && r == ELFPIE_OK; ++stage) {
       // warm the stage once, then time n_rep launches
       for (int rep = -1; rep < n_rep && r == ELFPIE_OK; ++rep) {
@@ -1167,7 +1210,10 @@ struct Ops {
             r = tb.fused ? lines<true, false>(pl, st->psi, T1, s)
                          : object_branch(pl, st->psi, true, T1, T2, s, nullptr, false, !tb.rowupd);
             break;
-          case 2: r = update(pl, nullptr, G, T2, st->P, true, true, s, tb.rowupd, st->psi); break;
+          case 2:
+            r = tb.fused ? update(pl, nullptr, G, T2, st->P, true, false, s, true, st->psi, &fa, &tp.a.pa)
+                         : update(pl, nullptr, G, T2, st->P, true, true, s, tb.rowupd, st->psi);
+            break;
           case 3: r = tail(pl, tq, s); break;
         }
       }
@@ -1819,10 +1865,10 @@ elfpie_status batch_capture_one(elfpie_batch* b, int mode, int which, double* co
 // Capture the graphs of update mode (opening, continuing, closing) or of tuning mode.
 elfpie_status batch_capture(elfpie_batch* b, int mode, double* const* hist) {
   batch_drop_graph(b);
-  bool any_chain = false;
-  for (elfpie_plan* pl : b->plans) any_chain = any_chain || pl->tb.rowupd;
+  bool any_close = false;  // a tile whose chain leaves a pupil update for the closing graph
+  for (elfpie_plan* pl : b->plans) any_close = any_close || (pl->tb.rowupd && !pl->tb.fused);
   for (int which = 0; which < (mode == 0 ? elfpie_batch::kNG : 1); ++which) {
-    if (which == 2 && !any_chain) break;  // nothing to close
+    if (which == 2 && !any_close) break;  // nothing to close
     const elfpie_status r = batch_capture_one(b, mode, which, hist);
     if (r != ELFPIE_OK) {
       batch_drop_graph(b);

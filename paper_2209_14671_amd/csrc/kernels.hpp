@@ -178,6 +178,8 @@ template <class T, int N, int NT>
 __device__ void obj_strip_wide(const LedObjArgs& o, int b, char* lds);
 template <class T, int N, int NT>
 constexpr size_t obj_wide_lds_bytes();
+template <class T>
+__device__ __forceinline__ cx<T> pupil_gauss3(const cx<T>* P, int n, int p, double w_c, double w_e, double w_k);
 
 // Every pass of each 2-D transform is spread over the whole block (StockhamPass).
 // SCALED: compiled with the Sec. 6.3 fidelity scalings (used only for them).
@@ -228,6 +230,15 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   led_bump_step(a, k, tid);
   const cx<T>* psi = static_cast<const cx<T>*>(a.psi);
   const cx<T>* P = static_cast<const cx<T>*>(a.P);
+  if constexpr (NOBJ > 0) {
+    // a slice of the pupil's pre-filtered copy (P is read-only in this launch)
+    if (a.obj.Pf) {
+      constexpr int NP = N * N;
+      const int per = (NP + nled - 1) / nled, p1 = min(NP, (k + 1) * per);
+      for (int p = k * per + tid; p < p1; p += NT)
+        static_cast<cx<T>*>(a.obj.Pf)[p] = pupil_gauss3<T>(P, N, p, a.obj.w_c, a.obj.w_e, a.obj.w_k);
+    }
+  }
   for (int i = tid; i < N; i += NT) {
     twl[i] = static_cast<const cx<T>*>(a.tw)[i];
     srow[i] = make_int4(a.xlo[i], a.xhi[i], a.rowoff[i] - a.xlo[i], 0);
@@ -1556,6 +1567,29 @@ constexpr int kPupilChunk = 16;
 // Virtual block vb of the pupil work carried by the spectrum-update launch:
 // vb < nsb * nch: partial sum of LED chunk vb / nsb for NT support pixels;
 // after that: the 3 x 3 Gaussian of the current pupil (zero padding) for NT pixels.
+// The 3 x 3 Gaussian of the n x n pupil P at pixel p (zero padding; Algorithm 1's
+// pre-filter): weights w_c at the centre, w_e on the edges, w_k on the corners.
+template <class T>
+__device__ __forceinline__ cx<T> pupil_gauss3(const cx<T>* P, int n, int p, double w_c, double w_e, double w_k) {
+  const int y = p / n, x = p % n;
+  cx<T> nb[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = min(max(y + t / 3 - 1, 0), n - 1), xx = min(max(x + t % 3 - 1, 0), n - 1);
+    nb[t] = P[yy * n + xx];
+  }
+  cx<T> acc = czero<T>();
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const bool in = y + dy >= 0 && y + dy < n && x + dx >= 0 && x + dx < n;
+    const int ring = (dy != 0) + (dx != 0);
+    const T w = in ? T(ring == 0 ? w_c : (ring == 1 ? w_e : w_k)) : T(0);
+    acc = acc + scale(nb[t], w);
+  }
+  return acc;
+}
+
 template <class T, int NT>
 __device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid) {
   const int nsb = (a.S + NT - 1) / NT;
@@ -1563,24 +1597,7 @@ __device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid)
     const int p = (vb - nsb * a.nch) * NT + tid;
     const int n = a.n_lo;
     if (p >= n * n) return;
-    const int y = p / n, x = p % n;
-    const cx<T>* P = static_cast<const cx<T>*>(a.P);
-    cx<T> nb[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = min(max(y + t / 3 - 1, 0), n - 1), xx = min(max(x + t % 3 - 1, 0), n - 1);
-      nb[t] = P[yy * n + xx];
-    }
-    cx<T> acc = czero<T>();
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int dy = t / 3 - 1, dx = t % 3 - 1;
-      const bool in = y + dy >= 0 && y + dy < n && x + dx >= 0 && x + dx < n;
-      const int ring = (dy != 0) + (dx != 0);
-      const T w = in ? T(ring == 0 ? a.w_c : (ring == 1 ? a.w_e : a.w_k)) : T(0);
-      acc = acc + scale(nb[t], w);
-    }
-    static_cast<cx<T>*>(a.Pf_out)[p] = acc;
+    static_cast<cx<T>*>(a.Pf_out)[p] = pupil_gauss3<T>(static_cast<const cx<T>*>(a.P), n, p, a.w_c, a.w_e, a.w_k);
     return;
   }
   const int ch = vb / nsb;
@@ -1599,6 +1616,57 @@ __device__ __forceinline__ void pupil_block(const PupilArgs& a, int vb, int tid)
   for (int j = 0; j < kPupilChunk; ++j)
     if (k0 + j < a.K) acc = acc + v[j];
   static_cast<cx<T>*>(a.part)[(size_t)ch * a.n_lo * a.n_lo + a.s2p[s]] = acc;
+}
+
+// The pupil work of an update launch in which the pupil update completes
+// (PupilArgs::final_in_launch), with no dependence between blocks: virtual block vb < nsb
+// takes PX support pixels whole.  Its NT / PX groups of PX threads each sum a contiguous
+// run of LEDs of every pixel (ascending LED order; lanes on consecutive pixels, so each
+// LED's row of D is read in one run), the group sums are added in group order, and the
+// first group applies Eq. 19 (or writes the gradient).  Blocks past those update the
+// pixels off the support (zero gradient).  red: PX * NT / PX complex of shared memory;
+// sbc: the shared bias corrections.
+template <class T>
+__device__ __forceinline__ void pupil_update_g(const PupilArgs& a, const double* sbc, int p, cx<T> g);
+
+template <class T, int NT>
+__device__ __forceinline__ void pupil_block_final(const PupilArgs& a, int vb, int tid, double* sbc, cx<T>* red) {
+  constexpr int PX = 32, G = NT / PX;
+  static_assert(NT % PX == 0, "whole groups");
+  const int nsb = (a.S + PX - 1) / PX;
+  if (a.step && tid == 0) bias_corrections(a.lg1, a.lg2, double(*a.t), sbc);
+  if (vb >= nsb) {
+    __syncthreads();  // sbc
+    const int n = a.n_lo, p = (vb - nsb) * NT + tid;
+    if (p >= n * n) return;
+    const int y = p / n, x = p % n;
+    if (x >= a.xlo[y] && x <= a.xhi[y]) return;  // on the support: a pixel block's
+    pupil_update_g<T>(a, sbc, p, czero<T>());
+    return;
+  }
+  const int sl = tid % PX, grp = tid / PX;
+  const int s = vb * PX + sl;
+  const int kc = (a.K + G - 1) / G, k0 = grp * kc, k1 = min(a.K, k0 + kc);
+  const cx<T>* D = static_cast<const cx<T>*>(a.D);
+  cx<T> acc = czero<T>();
+  if (s < a.S) {
+    constexpr int B = 8;  // loads in flight per batch
+    for (int kb = k0; kb < k1; kb += B) {
+      cx<T> v[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) v[j] = kb + j < k1 ? D[(size_t)(kb + j) * a.S + s] : czero<T>();
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (kb + j < k1) acc = acc + v[j];
+    }
+  }
+  red[grp * PX + sl] = acc;
+  __syncthreads();
+  if (grp == 0 && s < a.S) {
+    cx<T> g = red[sl];
+    for (int q = 1; q < G; ++q) g = g + red[q * PX + sl];
+    pupil_update_g<T>(a, sbc, a.s2p[s], g);
+  }
 }
 
 // Spectrum gradient gather (the segmented sum of the LED contributions that cover
@@ -1725,14 +1793,22 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
     finalize_block<NT>(fa, tid, fred);
     return;
   }
-  if ((int)blockIdx.x >= N / RB) {
+  // the pupil blocks: first in the launch when the pupil update completes here (their
+  // count a multiple of 8, so the rows keep their XCDs), else after the rows
+  const int pfirst = pa.final_in_launch ? a.pupil_blocks : 0;
+  if (pa.final_in_launch && (int)blockIdx.x < pfirst) {
+    static_assert(RB * PITCH >= NT, "the group sums fit the row buffer");
+    pupil_block_final<T, NT>(pa, blockIdx.x, tid, sbc, buf);
+    return;
+  }
+  if (!pa.final_in_launch && (int)blockIdx.x >= N / RB) {
     pupil_block<T, NT>(pa, blockIdx.x - N / RB, tid);
     return;
   }
   // runs of G neighbouring rows per XCD (their contribution segments meet in cache lines
   // of C), the runs still spread over the XCDs in turn
   constexpr int G = ELFPIE_UPD_PAIR;
-  int rb = blockIdx.x;
+  int rb = blockIdx.x - pfirst;
   if (G > 1 && (N / RB) % (8 * G) == 0) rb = (rb / (8 * G)) * 8 * G + (rb % 8) * G + (rb / 8) % G;
   const int r0 = rb * RB;
   const bool step = a.step != 0, keep_x = step || a.inv;
@@ -2008,6 +2084,29 @@ __device__ __forceinline__ void pupil_update_body(const PupilArgs& a, const doub
   PupilPre<T> f;
   pupil_prefetch<T>(a, p, f);
   pupil_finish<T>(a, sbc, p, f);
+}
+
+// Eq. 19 on pupil pixel p with its summed gradient g (zero off the support), or the
+// gradient itself; the same arithmetic as pupil_finish.
+template <class T>
+__device__ __forceinline__ void pupil_update_g(const PupilArgs& a, const double* sbc, int p, cx<T> g) {
+  const int n = a.n_lo, y = p / n, x = p % n;
+  const bool in = x >= a.xlo[y] && x <= a.xhi[y];
+  if (!in) g = czero<T>();
+  if (!a.step) {
+    static_cast<cx<T>*>(a.g_out)[p] = g;
+    return;
+  }
+  cx<T> xv = a.filter ? static_cast<const cx<T>*>(a.Pf)[p] : static_cast<const cx<T>*>(a.P)[p];
+  cx<T> mu = static_cast<const cx<T>*>(a.mu)[p];
+  double v = a.v[p];
+  T d = static_cast<const T*>(a.delta)[p];
+  optimizer_elem(a.opt, xv, g, mu, v, d, a.g1, a.g2, a.eta, a.lr, sbc);
+  if (a.support && !in) xv = czero<T>();
+  static_cast<cx<T>*>(a.P_out)[p] = xv;
+  static_cast<cx<T>*>(a.mu)[p] = mu;
+  a.v[p] = v;
+  static_cast<T*>(a.delta)[p] = d;
 }
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,11 @@ struct LedObjArgs {
   double alpha, beta, eta_h, eps;
   int norm;
   int nblk;             // object blocks (0: none)
+  // the 3 x 3 Gaussian pre-filter of the pupil (Algorithm 1), taken by the LED blocks in
+  // slices while P (LedArgs::P) is read-only, for the pupil update that completes in the
+  // update launch
+  void* Pf;             // out: the pre-filtered pupil (NULL: not needed)
+  double w_c, w_e, w_k; // Gaussian weights: centre, edge, corner
 };
 
 struct LedArgs {
@@ -137,6 +142,10 @@ struct PupilArgs {
   int step;
   int filter;
   int support;
+  // 1: the pupil update completes in the launch that sums the LED contributions, each
+  // block taking some support pixels over every LED; further blocks take the pixels off
+  // the support.  Pf then comes from the per-LED launch.
+  int final_in_launch;
 };
 
 // End of an iteration: Eq. 19 on the pupil (or its gradient) and the loss reduction.
