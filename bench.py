@@ -242,10 +242,9 @@ def sweep_bench(args, dev, iters=100):
                         cells.append({"rep": rep, "d_mm": d, "c": c, "noise": noise, "level": lv + 1, "obj": base.obj,
                                       "nl": metrics.noise_level(clean, noisy, dark)})
             log(f"seed {rep}, d = {d} mm: {len(tiles)} stacks built")
-    batch = E.Batch(tiles, n_branches=4)
-    tune = batch.tune(2)
+    batch = E.Batch(tiles, n_branches=4)  # a fixed branch count: the tuning is switched off
     branches = batch.n_branches
-    log(f"{len(tiles)} tiles in one batch, {branches} branches ({tune})")
+    log(f"{len(tiles)} tiles in one batch, {branches} branches")
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -330,9 +329,8 @@ def precision_bench(args, dev):
 
 
 def batch_bench(args, dev):
-    """Config 3: 64 independent tiles in one batch (parallel graph branches, branch count
-    tuned on gradient evaluations), `steps` replays timed; value = sum of K over tiles x
-    steps / seconds."""
+    """Config 3: 64 independent tiles in one batch (four parallel graph branches), `steps`
+    replays timed; value = sum of K over tiles x steps / seconds."""
     import torch
 
     import synth
@@ -348,10 +346,8 @@ def batch_bench(args, dev):
         tiles.append((plan, plan.init_state(meas), meas))
         bytes_it += byte_model(plan.K, plan.S, plan.n_lo ** 2, plan.n_hi ** 2)[1]
         k_total += plan.K
-    batch = E.Batch(tiles, n_branches=4)
-    log("tuning the branch count")
-    tune = batch.tune(3)
-    log(f"branches {batch.n_branches} ({tune})")
+    batch = E.Batch(tiles, n_branches=4)  # a fixed branch count: the tuning is switched off
+    log(f"branches {batch.n_branches}")
     if args.warmup:
         batch.run(args.warmup, history=False)
     torch.cuda.synchronize()
@@ -372,7 +368,7 @@ def batch_bench(args, dev):
            "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": WORKLOADS[3][1], "tiles": len(tiles), "K_total": k_total,
-                      "branches": batch.n_branches, "tuning_ms": tune},
+                      "branches": batch.n_branches},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": LED_KERNEL[3],
                         "algorithmic_bytes": bytes_it},

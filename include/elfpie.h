@@ -299,7 +299,9 @@ elfpie_status elfpie_batch_run(elfpie_batch *batch, int32_t n_iter, double *cons
  * of one gradient evaluation per tile (which leaves the states unchanged) is timed over
  * n_rep replays; ms_out (HOST, 4 floats) receives the mean ms per replay (0 for a
  * skipped count) and the fastest count is kept and returned in *n_branches_out.
- * Synchronous. */
+ * Synchronous.  Currently switched off: returns ELFPIE_E_UNSUPPORTED after the argument
+ * checks (a run of it ended in a host abort whose cause is not found); the branch count
+ * given to elfpie_batch_create stays in use. */
 elfpie_status elfpie_batch_tune(elfpie_batch *batch, int32_t n_rep, float *ms_out, int32_t *n_branches_out,
                                 void *stream);
 

@@ -1748,6 +1748,10 @@ double tile_cost(const Tables& tb) {
 }
 }  // namespace
 
+// Branch-count tuning (elfpie_batch_tune) is switched off: one GPU test run of it ended in a
+// host abort (no device fault reported) whose cause reading the code has not found.
+constexpr bool kBatchTune = false;
+
 struct elfpie_batch {
   std::vector<elfpie_plan*> plans;
   std::vector<elfpie_state> states;
@@ -1972,6 +1976,9 @@ elfpie_status elfpie_batch_run(elfpie_batch* b, int32_t n_iter, double* const* d
 elfpie_status elfpie_batch_tune(elfpie_batch* b, int32_t n_rep, float* ms_out, int32_t* n_branches_out, void* stream) {
   if (!b) return ELFPIE_E_INVALID;
   if (n_rep < 1 || !ms_out || !n_branches_out) return batch_err(b, ELFPIE_E_INVALID, "n_rep >= 1 and outputs required");
+  if (!kBatchTune)
+    return batch_err(b, ELFPIE_E_UNSUPPORTED,
+                     "branch-count tuning is switched off: a run of it ended in a host abort whose cause is not found");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   BATCH_TRY(b, hipEventCreate(&e0));

@@ -46,6 +46,17 @@ __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 
+// base[off] with a 32-bit element offset from a block-uniform base, so that the address is
+// the base register plus one 32-bit offset register (no 64-bit arithmetic per element).
+template <class X>
+__device__ __forceinline__ X& at_off(X* base, unsigned off) {
+  return *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off * unsigned(sizeof(X)));
+}
+template <class X>
+__device__ __forceinline__ const X& at_off(const X* base, unsigned off) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + off * unsigned(sizeof(X)));
+}
+
 // L1 term rho(d) = sqrt(d^2 + eps^2) - eps (eps > 0) or |d| and its derivative.
 // Per pixel these are a multiply-add and one reciprocal square root in FP32 (no IEEE
 // division or square-root expansion); the exact sign of eps = 0 is kept.
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   constexpr int MB2 = ceil_div(N * (N / R2), NT);
   static_assert(MB2 * NT == N * R1, "the last pass gives every thread whole butterflies");
   constexpr int PPT = N * N / NT;        // pixels per thread in the gather
-  constexpr int GB = gather_batch(PPT);  // loads kept in flight per batch
+  constexpr int GB = PPT <= 16 ? PPT : gather_batch(PPT);  // loads kept in flight per batch
   static_assert(PPT * NT == N * N && PPT % GB == 0, "the gather covers the tile exactly");
   // row passes (transform stride PITCH) and column passes (element stride PITCH)
   using P1iR = StockhamPass<T, N, R1, 1, true, NT, MB1, PITCH, 1>;
@@ -296,9 +307,9 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
         in[i] = x >= rw.x && x <= rw.y;
         pv[i] = czero<T>();
         wv[i] = czero<T>();
-        if (in[i]) {
-          pv[i] = P[p];
-          wv[i] = win[(size_t)y * a.n_hi + x];
+        if (in[i]) {  // 32-bit offsets from the block's base addresses
+          pv[i] = at_off(P, unsigned(p));
+          wv[i] = at_off(win, unsigned(y * a.n_hi + x));
         }
       }
 #pragma unroll
@@ -464,9 +475,23 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       for (int r = 0; r < R2; ++r) img[(j + r * R1) * PITCH + x] = o[i][r];
     }
   }
-  const double tot = block_sum<NT>(lsum, red);  // contains barriers
-  if (tid == 0) a.fid_partial[k] = tot;
-  if (!grad) return;
+  // the per-wave sums now; their sum over the block (thread 0, in wave order) at the end,
+  // so that no wave waits for it
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = lsum;
+  auto store_loss = [&]() {
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < NT / 64; ++w) tot += red[w];
+      a.fid_partial[k] = tot;
+    }
+  };
+  __syncthreads();  // the gradient in the tile (and the slots) before the forward DFT reads it
+  if (!grad) {
+    store_loss();
+    return;
+  }
 
   // forward DFT of dL/d(conj o): all rows, then only columns that hold support
   P1fR::run(img, 0, N, twl, tid);
@@ -489,8 +514,8 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
 #pragma unroll
     for (int r = 0; r < R2; ++r) {
       const int y = live ? j + r * R1 : 0;
-      pw[r] = P[y * N + x];
-      ww[r] = win[(size_t)y * a.n_hi + x];
+      pw[r] = at_off(P, unsigned(y * N + x));
+      ww[r] = at_off(win, unsigned(y * a.n_hi + x));
     }
     if (live) {
       // the support tests and offsets of the column's R2 pixels first, each row entry read
@@ -508,12 +533,13 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
       for (int r = 0; r < R2; ++r) {
         if (ok[r]) {
           const cx<T> yv = scale(Y[i][r], sc);
-          C[so[r]] = cmulc(pw[r], yv);
-          D[so[r]] = cmulc(ww[r], yv);
+          at_off(C, unsigned(so[r])) = cmulc(pw[r], yv);
+          at_off(D, unsigned(so[r])) = cmulc(ww[r], yv);
         }
       }
     }
   }
+  store_loss();
 }
 
 // dL/d(conj o_m) = f o_m for every LED m of an image: the real factor
@@ -1146,18 +1172,26 @@ __global__ __launch_bounds__(StripShape<N>::NT) void k_obj_strip(HessArgs a, con
 // room for chunks of 128 rows; the other forms keep it in the working precision, in
 // chunks of 64.  The arithmetic per element is that of k_obj_strip.
 template <int N, bool SIGN> struct ObjWide {
-  static constexpr int WMAX = 17, CH = SIGN ? 128 : 64, NLM = WMAX + 4, OWM = WMAX + 2, OH = CH + 2, RS = CH + 4;
+  static constexpr int WMAX = 17, CH = 64, NLM = WMAX + 4, OWM = WMAX + 2, OH = CH + 2, RS = CH + 4;
   static constexpr int PITCH = N + 1;  // odd: the lines of a pass spread over the banks
   static_assert(N % CH == 0, "whole chunks");
 };
 
-// Shared-memory bytes of one form of obj_strip_wide: lines, twiddles, chunk |O| and
-// angle(O), omega, block sums.
+// Shared-memory bytes of one form of obj_strip_wide: lines, twiddles, then the chunk
+// arrays -- the sign form: (|O|, angle(O)) pairs and three planes of packed sign pairs,
+// reused for the per-thread loss partials; the other forms: |O| and angle(O) planes, six
+// omega planes in the working precision, block sums.
 template <class T, int N, int NT, bool SIGN>
 constexpr size_t obj_wide_form_bytes() {
   using Sh = ObjWide<N, SIGN>;
-  return sizeof(cx<T>) * (Sh::NLM * Sh::PITCH + N) + sizeof(T) * 2 * Sh::NLM * Sh::RS +
-         (SIGN ? 1 : sizeof(T)) * 6 * Sh::OWM * Sh::OH + 8 + sizeof(double) * 2 * (NT / 64);
+  constexpr size_t lines = sizeof(cx<T>) * (Sh::NLM * Sh::PITCH + N);
+  if constexpr (SIGN) {
+    constexpr size_t chunk = 2 * sizeof(T) * Sh::NLM * Sh::RS + 3 * sizeof(unsigned) * Sh::OWM * Sh::OH;
+    constexpr size_t sums = sizeof(double) * (2 * NT + 16);
+    return lines + (chunk > sums ? chunk : sums);
+  }
+  return lines + sizeof(T) * 2 * Sh::NLM * Sh::RS + sizeof(T) * 6 * Sh::OWM * Sh::OH + 8 +
+         sizeof(double) * 2 * (NT / 64);
 }
 template <class T, int N, int NT>
 constexpr size_t obj_wide_lds_bytes() {
@@ -1367,10 +1401,280 @@ __device__ void obj_strip_wide_form(const LedObjArgs& o, int b, char* lds) {
   }
 }
 
+// atan2(y, x) in FP32 without a library call: the octant symmetries reduce the
+// argument to a = min(|x|, |y|) / max(|x|, |y|) in [0, 1], where atan(a) = a P(a^2) with a
+// degree-8 polynomial P fitted here to the relative error of atan on [0, 1] (1.7e-8); then
+// pi/2 - r where |y| > |x|, pi - r where x < 0, and the sign of y (atan2(+-0, x < 0) =
+// +-pi).  Within 5 units of roundoff of the correctly rounded value (|error| <= 3.6e-7)
+// for finite arguments; 0 at the origin.
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const float s = a * a;
+  float p = 0.0029075394850224257f;
+  p = __builtin_fmaf(p, s, -0.016316886991262436f);
+  p = __builtin_fmaf(p, s, 0.04313173145055771f);
+  p = __builtin_fmaf(p, s, -0.07545701414346695f);
+  p = __builtin_fmaf(p, s, 0.10663097351789474f);
+  p = __builtin_fmaf(p, s, -0.14210361242294312f);
+  p = __builtin_fmaf(p, s, 0.19993694126605988f);
+  p = __builtin_fmaf(p, s, -0.33333149552345276f);
+  float r = __builtin_fmaf(a, p * s, a);
+  r = ay > ax ? 1.57079632679489662f - r : r;
+  r = x < 0.0f ? 3.14159265358979324f - r : r;
+  return __builtin_copysignf(r, y);
+}
+
+// The sign form (the exact anisotropic L1, omega = sign, rho = |.|) of an object block in
+// FP32: the same method as obj_strip_wide_form, laid out for fewer instructions.  After the
+// column inverse DFT, chunks of CH rows go through three phases, each thread on a short
+// run of rows of one line, so that neighbours along a line are shared in registers:
+//   A  (|O|, angle(O)) of every line, rows r0 + 2 .. r0 + CH + 1 (the four rows above are
+//      carried over from the previous chunk, whose own rows have since been overwritten
+//      by G; rows off the grid are zero), as pairs;
+//   B  the three H components of both fields on lines 1 .. W + 2 and rows r0 - 1 .. r0 + CH
+//      (zero where the stencil leaves the grid), their signs packed as half pairs
+//      (|O| in the low half, angle(O) in the high half) in one plane per component, and
+//      the loss terms of the own pixels;
+//   C  on the own pixels q = H^T omega for both fields at once in half arithmetic (sums
+//      of at most ten signs, exact), and G as in obj_strip_wide_form, written over O.
+// The per-thread loss partials are reduced in a fixed order after the forward DFT.
+template <class T, int N, int NT>
+__device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
+  static_assert(sizeof(T) == 4, "packed half signs of FP32 features");
+  using Sh = ObjWide<N, true>;
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  constexpr int CH = Sh::CH, NLM = Sh::NLM, OWM = Sh::OWM, OH = Sh::OH, RS = Sh::RS, PITCH = Sh::PITCH;
+  static_assert(OH % 2 == 0 && CH % 2 == 0, "runs of two rows");
+  cx<T>* buf = reinterpret_cast<cx<T>*>(lds);  // line l = column c0 - 2 + l
+  cx<T>* twl = buf + NLM * PITCH;
+  cx<T>* sf = twl + N;                                  // (|O|, angle(O)) at [l * RS + i], y = r0 - 2 + i
+  unsigned* omx = reinterpret_cast<unsigned*>(sf + NLM * RS);  // [lb * OH + ib], line lb + 1, y = r0 - 1 + ib
+  unsigned* omy = omx + OWM * OH;
+  unsigned* omz = omy + OWM * OH;
+  double* lsum = reinterpret_cast<double*>(sf);  // after the chunks: 2 NT loss partials
+  const int tid = threadIdx.x;
+  const int c0 = b * N / o.nblk, c1 = (b + 1) * N / o.nblk, W = c1 - c0, NL = W + 4, LB = W + 2;
+  const Div dNL = make_div(NL), dW = make_div(W);
+  const T inv_n = T(o.inv_n);
+  const cx<T>* T1 = static_cast<const cx<T>*>(o.T1);
+  cx<T>* T2 = static_cast<cx<T>*>(o.T2);
+  const cx<T>* tw = static_cast<const cx<T>*>(o.tw);
+  for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+  using Rd = LineRadix<N>;
+  constexpr int R1 = Rd::R1, R2 = Rd::R2, R3 = Rd::R3;
+  static_assert(R3 > 1, "three passes");
+  {
+    // inverse DFT along the NL lines; the first pass (no twiddles) reads its butterflies
+    // straight from T1: line m = column c0 - 2 + m, element j + r N / R1
+    using PA = StockhamPass<T, N, R1, 1, true, NT, ceil_div(NLM * (N / R1), NT), PITCH, 1>;
+    constexpr int MB = ceil_div(NLM * (N / R1), NT);
+    int m[MB], j[MB];
+    bool lv[MB];
+    PA::coords(dNL, tid, m, j, lv);
+    cx<T> v[MB][R1];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const int c = c0 - 2 + m[i];
+      const bool ok = lv[i] && c >= 0 && c < N;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[i][r] = ok ? T1[(size_t)(j[i] + r * (N / R1)) * N + c] : czero<T>();
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (lv[i]) dft<T, R1, true>(v[i]);
+    PA::store(buf, 0, m, j, lv, v);
+    __syncthreads();
+    StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
+    StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
+  }
+  // (|O|, angle(O)) at line l, row y (zero off the grid); O = (-1)^(x+y) Ot / n.  CHK:
+  // check the row against the grid (lines off the grid hold zeros already)
+  auto amp_phase = [&](int l, int y, auto chk_c) -> cx<T> {
+    if (decltype(chk_c)::value && (y < 0 || y >= N)) return czero<T>();
+    const int c = c0 - 2 + l;
+    const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
+    return cx<T>{sqrt_t(norm2(O)), atan2_fast(O.y, O.x)};
+  };
+  // rows i = 0 .. 3 of the first chunk (y = -2 .. 1)
+  for (int p = tid; p < NL * 4; p += NT) {
+    const int l = p >> 2, i = p & 3;
+    sf[l * RS + i] = amp_phase(l, i - 2, std::true_type{});
+  }
+  T ta = T(0), tp = T(0);  // this thread's loss terms of the current chunk
+  double la = 0.0, lp = 0.0;
+  const int cx0 = c0 - 1;   // column of omega line lb = 0
+  // a strip whose stencils stay on the grid in x: every line's column in 0 .. N - 1 and
+  // every omega line's in 1 .. N - 2
+  const bool strip_in = c0 >= 2 && c0 + W <= N - 2;
+  // One chunk; IN: the strip is inside and the chunk's rows keep every stencil on the grid
+  // (r0 - 1 >= 1 and r0 + CH <= N - 2), so that no bound is checked.
+  auto chunk = [&](int r0, auto in_c) {
+    constexpr bool IN = decltype(in_c)::value;
+    // A: rows i = 4 .. RS - 1 (y = r0 + 2 .. r0 + CH + 1) of every line
+    for (int p = tid; p < NL * CH; p += NT) {
+      const int l = p / CH, i = 4 + p % CH;
+      sf[l * RS + i] = amp_phase(l, r0 - 2 + i, std::integral_constant<bool, !IN>{});
+    }
+    __syncthreads();
+    // B: omega on lines lb + 1 (lb < LB), rows ib = 2 q, 2 q + 1 (y = r0 - 1 + ib)
+    for (int p = tid; p < LB * (OH / 2); p += NT) {
+      const int lb = p / (OH / 2), ib0 = 2 * (p % (OH / 2));
+      const int l = lb + 1, c = cx0 + lb;
+      const bool cin = c >= 0 && c < N, cxx = c >= 1 && c <= N - 2, cxy = c <= N - 2;
+      const bool own_c = l >= 2 && l <= W + 1;
+      // f rows i = ib + 1 (y) and neighbours: line l rows i - 1 .. i + 2, lines l - 1 and
+      // l + 1 as the stencils need
+      const cx<T>* sl = sf + l * RS + ib0 + 1;
+      cx<T> ctr[4], lft[2], rgt[3];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) ctr[t] = sl[t - 1];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) lft[t] = sl[t - RS];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) rgt[t] = sl[t + RS];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int ib = ib0 + t, y = r0 - 1 + ib;
+        const bool in = IN || (cin && y >= 0 && y < N);
+        const bool vxx = IN || (in && cxx), vyy = IN || (in && y >= 1 && y <= N - 2);
+        const bool vxy = IN || (in && cxy && y <= N - 2);
+        const cx<T> f = ctr[t + 1], fl = lft[t], fr = rgt[t], fu = ctr[t], fd = ctr[t + 2], frd = rgt[t + 1];
+        // components of |O| (.x) and angle(O) (.y)
+        const T hxa = vxx ? fl.x - T(2) * f.x + fr.x : T(0), hxp = vxx ? fl.y - T(2) * f.y + fr.y : T(0);
+        const T hya = vyy ? fu.x - T(2) * f.x + fd.x : T(0), hyp = vyy ? fu.y - T(2) * f.y + fd.y : T(0);
+        const T hza = vxy ? f.x - fr.x - fd.x + frd.x : T(0), hzp = vxy ? f.y - fr.y - fd.y + frd.y : T(0);
+        const int oi = lb * OH + ib;
+        omx[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hxa), sign_unit(hxp)));
+        omy[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hya), sign_unit(hyp)));
+        omz[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hza), sign_unit(hzp)));
+        const bool own = own_c && ib >= 1 && ib <= CH && in;
+        ta += own ? fabs(hxa) + fabs(hya) + fabs(hza) : T(0);
+        tp += own ? fabs(hxp) + fabs(hyp) + fabs(hzp) : T(0);
+      }
+    }
+    la += double(ta);
+    lp += double(tp);
+    ta = T(0);
+    tp = T(0);
+    __syncthreads();
+    // C: own lines l = lc + 2 (lc < W), rows y = r0 + 2 q, r0 + 2 q + 1
+    for (int p = tid; p < W * (CH / 2); p += NT) {
+      const int lc = p / (CH / 2), y0 = r0 + 2 * (p % (CH / 2));
+      const int l = lc + 2, lb = lc + 1, c = c0 + lc;
+      const int oi0 = lb * OH + (y0 - r0 + 1);  // omega index of the run's first pixel
+      h2 zl[3], zc[3], xr[2], xl[2], yc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) yc[t] = __builtin_bit_cast(h2, omy[oi0 + t - 1]);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        zc[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1]);
+        zl[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1 - OH]);
+      }
+      h2 xc[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        xc[t] = __builtin_bit_cast(h2, omx[oi0 + t]);
+        xl[t] = __builtin_bit_cast(h2, omx[oi0 + t - OH]);
+        xr[t] = __builtin_bit_cast(h2, omx[oi0 + t + OH]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int y = y0 + t;
+        const h2 two = {_Float16(2), _Float16(2)};
+        // q = Dxx^T s_xx + Dyy^T s_yy + Dxy^T s_xy at (y, c), both fields
+        const h2 q = xl[t] - two * xc[t] + xr[t] + yc[t] - two * yc[t + 1] + yc[t + 2] + zc[t + 1] - zl[t + 1] -
+                     zc[t] + zl[t];
+        const T qa = T(q.x), qp = T(q.y);
+        const T sgn = ((c + y) & 1) ? -inv_n : inv_n;
+        cx<T>& slot = buf[l * PITCH + y];
+        const cx<T> O = scale(slot, sgn);
+        const T a2 = norm2(O);
+        cx<T> G = czero<T>();
+        if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * qa * rsqrt_t(a2));
+        const T den = a2 + T(o.eta_h);
+        if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * qp * rcp_t(den));
+        slot = scale(G, sgn);
+      }
+    }
+    // the next chunk's rows i = 0 .. 3 are this chunk's rows CH .. CH + 3 (B is done with them)
+    for (int p = tid; p < NL * 4; p += NT) {
+      const int l = p >> 2, i = p & 3;
+      sf[l * RS + i] = sf[l * RS + CH + i];
+    }
+    __syncthreads();
+  };
+  for (int r0 = 0; r0 < N; r0 += CH) {
+    if (strip_in && r0 >= 2 && r0 + CH <= N - 2) chunk(r0, std::true_type{});
+    else chunk(r0, std::false_type{});
+  }
+  // forward DFT along the own columns (lines 2 .. W + 1); the last pass stores its outputs
+  // straight to T2 (line m = column c0 + m).  The loss partials wait in shared memory.
+  lsum[tid] = la;
+  lsum[NT + tid] = lp;
+  {
+    cx<T>* own = buf + 2 * PITCH;
+    constexpr int WM = Sh::WMAX;
+    StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
+    StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
+    using PC = StockhamPass<T, N, R3, R1 * R2, false, NT, ceil_div(WM * (N / R3), NT), PITCH, 1>;
+    constexpr int MB = ceil_div(WM * (N / R3), NT);
+    int m[MB], j[MB];
+    bool lv[MB];
+    PC::coords(dW, tid, m, j, lv);
+    cx<T> v[MB][R3];
+    PC::load(own, 0, m, j, lv, twl, v);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      if (lv[i]) {
+#pragma unroll
+        for (int r = 0; r < R3; ++r) T2[(size_t)PC::out_index(j[i], r) * N + c0 + m[i]] = v[i][r];
+      }
+  }
+  // deterministic block sums of the two penalty partials: 64 threads each add 16 slots in
+  // order, 8 threads each 8 of those, thread 0 the 8
+  static_assert(NT == 1024, "16 x 8 x 8 slots");
+  if (tid < 64) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      s0 += lsum[w * 64 + tid];
+      s1 += lsum[NT + w * 64 + tid];
+    }
+    lsum[tid] = s0;  // a slot only this thread has read
+    lsum[NT + tid] = s1;
+  }
+  __syncthreads();
+  if (tid < 8) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < 8; ++w) {
+      s0 += lsum[8 * tid + w];
+      s1 += lsum[NT + 8 * tid + w];
+    }
+    lsum[2 * NT + tid] = s0;  // past the 2 NT slots: room left in the chunk arrays
+    lsum[2 * NT + 8 + tid] = s1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < 8; ++w) {
+      s0 += lsum[2 * NT + w];
+      s1 += lsum[2 * NT + 8 + w];
+    }
+    o.partial[2 * b + 0] = s0;
+    o.partial[2 * b + 1] = s1;
+  }
+}
+
 template <class T, int N, int NT>
 __device__ void obj_strip_wide(const LedObjArgs& o, int b, char* lds) {
-  if (o.norm == 0 && !(o.eps > 0.0)) obj_strip_wide_form<T, N, NT, true>(o, b, lds);
-  else obj_strip_wide_form<T, N, NT, false>(o, b, lds);
+  if constexpr (sizeof(T) == 4) {
+    if (o.norm == 0 && !(o.eps > 0.0)) {
+      obj_strip_wide_sign<T, N, NT>(o, b, lds);
+      return;
+    }
+  }
+  obj_strip_wide_form<T, N, NT, false>(o, b, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -110,6 +110,8 @@ def test_batch_equals_tiles_run_alone(branches):
     batch.close()
 
 
+@pytest.mark.skip(reason="elfpie_batch_tune is switched off: one GPU run of this test ended in a host abort "
+                         "(no device fault reported) whose cause reading the code has not found")
 def test_batch_tuning_keeps_states_and_picks_a_count():
     e = E()
     tiles = build_tiles()
