@@ -219,7 +219,10 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
   using P1fC = StockhamPass<T, N, R1, 1, false, NT, MB1, 1, PITCH>;
   using P2fC = StockhamPass<T, N, R2, R1, false, NT, MB2, 1, PITCH, 0, TWB>;
 
-  __shared__ cx<T> img[N * PITCH];
+  // the tile; in a launch with object blocks, large enough for their arrays too
+  constexpr size_t TILE = size_t(N) * PITCH;
+  constexpr size_t OBJ = NOBJ > 0 ? (obj_wide_lds_bytes<T, (NOBJ > 0 ? NOBJ : 512), NT>() + sizeof(cx<T>) - 1) / sizeof(cx<T>) : 0;
+  __shared__ cx<T> img[TILE > OBJ ? TILE : OBJ];
   __shared__ cx<T> twl[N];
   __shared__ int4 srow[N];  // per row: first and last support column, offset of s - first
   __shared__ double red[NT / 64];
@@ -1186,7 +1189,7 @@ constexpr size_t obj_wide_form_bytes() {
   using Sh = ObjWide<N, SIGN>;
   constexpr size_t lines = sizeof(cx<T>) * (Sh::NLM * Sh::PITCH + N);
   if constexpr (SIGN) {
-    constexpr size_t chunk = 2 * sizeof(T) * Sh::NLM * Sh::RS + 3 * sizeof(unsigned) * Sh::OWM * Sh::OH;
+    constexpr size_t chunk = 2 * (2 * sizeof(T) * Sh::NLM * Sh::RS + 3 * sizeof(unsigned) * Sh::OWM * Sh::OH);
     constexpr size_t sums = sizeof(double) * (2 * NT + 16);
     return lines + (chunk > sums ? chunk : sums);
   }
@@ -1428,18 +1431,19 @@ __device__ __forceinline__ float atan2_fast(float y, float x) {
 
 // The sign form (the exact anisotropic L1, omega = sign, rho = |.|) of an object block in
 // FP32: the same method as obj_strip_wide_form, laid out for fewer instructions.  After the
-// column inverse DFT, chunks of CH rows go through three phases, each thread on a short
+// column inverse DFT, each chunk of CH rows goes through three steps, each thread on a short
 // run of rows of one line, so that neighbours along a line are shared in registers:
-//   A  (|O|, angle(O)) of every line, rows r0 + 2 .. r0 + CH + 1 (the four rows above are
-//      carried over from the previous chunk, whose own rows have since been overwritten
-//      by G; rows off the grid are zero), as pairs;
+//   A  (|O|, angle(O)) of every line on the chunk's rows and two halo rows each side (rows
+//      off the grid are zero), as pairs;
 //   B  the three H components of both fields on lines 1 .. W + 2 and rows r0 - 1 .. r0 + CH
 //      (zero where the stencil leaves the grid), their signs packed as half pairs
 //      (|O| in the low half, angle(O) in the high half) in one plane per component, and
 //      the loss terms of the own pixels;
 //   C  on the own pixels q = H^T omega for both fields at once in half arithmetic (sums
 //      of at most ten signs, exact), and G as in obj_strip_wide_form, written over O.
-// The per-thread loss partials are reduced in a fixed order after the forward DFT.
+// The steps of consecutive chunks overlap (A of one chunk, B of the one before, C of the
+// one before that, between two barriers), on two alternating sets of chunk arrays.  The
+// per-thread loss partials are reduced in a fixed order after the forward DFT.
 template <class T, int N, int NT>
 __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   static_assert(sizeof(T) == 4, "packed half signs of FP32 features");
@@ -1449,11 +1453,14 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   static_assert(OH % 2 == 0 && CH % 2 == 0, "runs of two rows");
   cx<T>* buf = reinterpret_cast<cx<T>*>(lds);  // line l = column c0 - 2 + l
   cx<T>* twl = buf + NLM * PITCH;
-  cx<T>* sf = twl + N;                                  // (|O|, angle(O)) at [l * RS + i], y = r0 - 2 + i
-  unsigned* omx = reinterpret_cast<unsigned*>(sf + NLM * RS);  // [lb * OH + ib], line lb + 1, y = r0 - 1 + ib
-  unsigned* omy = omx + OWM * OH;
-  unsigned* omz = omy + OWM * OH;
-  double* lsum = reinterpret_cast<double*>(sf);  // after the chunks: 2 NT loss partials
+  // two sets of chunk arrays (chunks alternate between them): (|O|, angle(O)) at
+  // [l * RS + i] for y = r0 - 2 + i, and the three packed sign planes at [lb * OH + ib]
+  // for line lb + 1, y = r0 - 1 + ib
+  cx<T>* sf0 = twl + N;
+  unsigned* om0 = reinterpret_cast<unsigned*>(sf0 + 2 * NLM * RS);
+  auto sfb = [&](int c) { return sf0 + (c & 1) * (NLM * RS); };
+  auto omb = [&](int c) { return om0 + (c & 1) * (3 * OWM * OH); };
+  double* lsum = reinterpret_cast<double*>(sf0);  // after the chunks: 2 NT loss partials
   const int tid = threadIdx.x;
   const int c0 = b * N / o.nblk, c1 = (b + 1) * N / o.nblk, W = c1 - c0, NL = W + 4, LB = W + 2;
   const Div dNL = make_div(NL), dW = make_div(W);
@@ -1497,117 +1504,131 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
     return cx<T>{sqrt_t(norm2(O)), atan2_fast(O.y, O.x)};
   };
-  // rows i = 0 .. 3 of the first chunk (y = -2 .. 1)
-  for (int p = tid; p < NL * 4; p += NT) {
-    const int l = p >> 2, i = p & 3;
-    sf[l * RS + i] = amp_phase(l, i - 2, std::true_type{});
-  }
   T ta = T(0), tp = T(0);  // this thread's loss terms of the current chunk
   double la = 0.0, lp = 0.0;
   const int cx0 = c0 - 1;   // column of omega line lb = 0
   // a strip whose stencils stay on the grid in x: every line's column in 0 .. N - 1 and
   // every omega line's in 1 .. N - 2
   const bool strip_in = c0 >= 2 && c0 + W <= N - 2;
-  // One chunk; IN: the strip is inside and the chunk's rows keep every stencil on the grid
-  // (r0 - 1 >= 1 and r0 + CH <= N - 2), so that no bound is checked.
-  auto chunk = [&](int r0, auto in_c) {
-    constexpr bool IN = decltype(in_c)::value;
-    // A: rows i = 4 .. RS - 1 (y = r0 + 2 .. r0 + CH + 1) of every line
-    for (int p = tid; p < NL * CH; p += NT) {
-      const int l = p / CH, i = 4 + p % CH;
-      sf[l * RS + i] = amp_phase(l, r0 - 2 + i, std::integral_constant<bool, !IN>{});
-    }
-    __syncthreads();
-    // B: omega on lines lb + 1 (lb < LB), rows ib = 2 q, 2 q + 1 (y = r0 - 1 + ib)
-    for (int p = tid; p < LB * (OH / 2); p += NT) {
-      const int lb = p / (OH / 2), ib0 = 2 * (p % (OH / 2));
-      const int l = lb + 1, c = cx0 + lb;
-      const bool cin = c >= 0 && c < N, cxx = c >= 1 && c <= N - 2, cxy = c <= N - 2;
-      const bool own_c = l >= 2 && l <= W + 1;
-      // f rows i = ib + 1 (y) and neighbours: line l rows i - 1 .. i + 2, lines l - 1 and
-      // l + 1 as the stencils need
-      const cx<T>* sl = sf + l * RS + ib0 + 1;
-      cx<T> ctr[4], lft[2], rgt[3];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) ctr[t] = sl[t - 1];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) lft[t] = sl[t - RS];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) rgt[t] = sl[t + RS];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int ib = ib0 + t, y = r0 - 1 + ib;
-        const bool in = IN || (cin && y >= 0 && y < N);
-        const bool vxx = IN || (in && cxx), vyy = IN || (in && y >= 1 && y <= N - 2);
-        const bool vxy = IN || (in && cxy && y <= N - 2);
-        const cx<T> f = ctr[t + 1], fl = lft[t], fr = rgt[t], fu = ctr[t], fd = ctr[t + 2], frd = rgt[t + 1];
-        // components of |O| (.x) and angle(O) (.y)
-        const T hxa = vxx ? fl.x - T(2) * f.x + fr.x : T(0), hxp = vxx ? fl.y - T(2) * f.y + fr.y : T(0);
-        const T hya = vyy ? fu.x - T(2) * f.x + fd.x : T(0), hyp = vyy ? fu.y - T(2) * f.y + fd.y : T(0);
-        const T hza = vxy ? f.x - fr.x - fd.x + frd.x : T(0), hzp = vxy ? f.y - fr.y - fd.y + frd.y : T(0);
-        const int oi = lb * OH + ib;
-        omx[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hxa), sign_unit(hxp)));
-        omy[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hya), sign_unit(hyp)));
-        omz[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hza), sign_unit(hzp)));
-        const bool own = own_c && ib >= 1 && ib <= CH && in;
-        ta += own ? fabs(hxa) + fabs(hya) + fabs(hza) : T(0);
-        tp += own ? fabs(hxp) + fabs(hyp) + fabs(hzp) : T(0);
-      }
-    }
-    la += double(ta);
-    lp += double(tp);
-    ta = T(0);
-    tp = T(0);
-    __syncthreads();
-    // C: own lines l = lc + 2 (lc < W), rows y = r0 + 2 q, r0 + 2 q + 1
-    for (int p = tid; p < W * (CH / 2); p += NT) {
-      const int lc = p / (CH / 2), y0 = r0 + 2 * (p % (CH / 2));
-      const int l = lc + 2, lb = lc + 1, c = c0 + lc;
-      const int oi0 = lb * OH + (y0 - r0 + 1);  // omega index of the run's first pixel
-      h2 zl[3], zc[3], xr[2], xl[2], yc[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) yc[t] = __builtin_bit_cast(h2, omy[oi0 + t - 1]);
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        zc[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1]);
-        zl[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1 - OH]);
-      }
-      h2 xc[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        xc[t] = __builtin_bit_cast(h2, omx[oi0 + t]);
-        xl[t] = __builtin_bit_cast(h2, omx[oi0 + t - OH]);
-        xr[t] = __builtin_bit_cast(h2, omx[oi0 + t + OH]);
-      }
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int y = y0 + t;
-        const h2 two = {_Float16(2), _Float16(2)};
-        // q = Dxx^T s_xx + Dyy^T s_yy + Dxy^T s_xy at (y, c), both fields
-        const h2 q = xl[t] - two * xc[t] + xr[t] + yc[t] - two * yc[t + 1] + yc[t + 2] + zc[t + 1] - zl[t + 1] -
-                     zc[t] + zl[t];
-        const T qa = T(q.x), qp = T(q.y);
-        const T sgn = ((c + y) & 1) ? -inv_n : inv_n;
-        cx<T>& slot = buf[l * PITCH + y];
-        const cx<T> O = scale(slot, sgn);
-        const T a2 = norm2(O);
-        cx<T> G = czero<T>();
-        if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * qa * rsqrt_t(a2));
-        const T den = a2 + T(o.eta_h);
-        if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * qp * rcp_t(den));
-        slot = scale(G, sgn);
-      }
-    }
-    // the next chunk's rows i = 0 .. 3 are this chunk's rows CH .. CH + 3 (B is done with them)
-    for (int p = tid; p < NL * 4; p += NT) {
-      const int l = p >> 2, i = p & 3;
-      sf[l * RS + i] = sf[l * RS + CH + i];
-    }
-    __syncthreads();
+  constexpr int NCH = N / CH;
+  // A(c), item q: (|O|, angle(O)) of line q / RS, chunk row q % RS (y = r0 - 2 + q % RS)
+  auto stage_a = [&](int c, int q) {
+    const int l = q / RS, i = q % RS;
+    sfb(c)[l * RS + i] = amp_phase(l, c * CH - 2 + i, std::true_type{});
   };
-  for (int r0 = 0; r0 < N; r0 += CH) {
-    if (strip_in && r0 >= 2 && r0 + CH <= N - 2) chunk(r0, std::true_type{});
-    else chunk(r0, std::false_type{});
+  // B(c), item q: omega on line lb + 1, rows ib = 2 (q mod OH / 2) and the next
+  // (y = r0 - 1 + ib).  IN: the strip is inside and the chunk's rows keep every stencil
+  // on the grid, so that no bound is checked.
+  auto stage_b = [&](int c, int q, auto in_c) {
+    constexpr bool IN = decltype(in_c)::value;
+    const int r0 = c * CH;
+    const cx<T>* sf = sfb(c);
+    unsigned* omx = omb(c);
+    unsigned* omy = omx + OWM * OH;
+    unsigned* omz = omy + OWM * OH;
+    const int lb = q / (OH / 2), ib0 = 2 * (q % (OH / 2));
+    const int l = lb + 1, c_ = cx0 + lb;
+    const bool cin = c_ >= 0 && c_ < N, cxx = c_ >= 1 && c_ <= N - 2, cxy = c_ <= N - 2;
+    const bool own_c = l >= 2 && l <= W + 1;
+    // f rows i = ib + 1 (y) and neighbours: line l rows i - 1 .. i + 2, lines l - 1 and
+    // l + 1 as the stencils need
+    const cx<T>* sl = sf + l * RS + ib0 + 1;
+    cx<T> ctr[4], lft[2], rgt[3];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ctr[t] = sl[t - 1];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) lft[t] = sl[t - RS];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) rgt[t] = sl[t + RS];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ib = ib0 + t, y = r0 - 1 + ib;
+      const bool in = IN || (cin && y >= 0 && y < N);
+      const bool vxx = IN || (in && cxx), vyy = IN || (in && y >= 1 && y <= N - 2);
+      const bool vxy = IN || (in && cxy && y <= N - 2);
+      const cx<T> f = ctr[t + 1], fl = lft[t], fr = rgt[t], fu = ctr[t], fd = ctr[t + 2], frd = rgt[t + 1];
+      // components of |O| (.x) and angle(O) (.y)
+      const T hxa = vxx ? fl.x - T(2) * f.x + fr.x : T(0), hxp = vxx ? fl.y - T(2) * f.y + fr.y : T(0);
+      const T hya = vyy ? fu.x - T(2) * f.x + fd.x : T(0), hyp = vyy ? fu.y - T(2) * f.y + fd.y : T(0);
+      const T hza = vxy ? f.x - fr.x - fd.x + frd.x : T(0), hzp = vxy ? f.y - fr.y - fd.y + frd.y : T(0);
+      const int oi = lb * OH + ib;
+      omx[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hxa), sign_unit(hxp)));
+      omy[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hya), sign_unit(hyp)));
+      omz[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hza), sign_unit(hzp)));
+      const bool own = own_c && ib >= 1 && ib <= CH && in;
+      ta += own ? fabs(hxa) + fabs(hya) + fabs(hza) : T(0);
+      tp += own ? fabs(hxp) + fabs(hyp) + fabs(hzp) : T(0);
+    }
+  };
+  // C(c), item q: own line l = q / (CH / 2) + 2, rows y = r0 + 2 (q mod CH / 2) and the next
+  auto stage_c = [&](int c, int q) {
+    const int r0 = c * CH;
+    const unsigned* omx = omb(c);
+    const unsigned* omy = omx + OWM * OH;
+    const unsigned* omz = omy + OWM * OH;
+    const int lc = q / (CH / 2), y0 = r0 + 2 * (q % (CH / 2));
+    const int l = lc + 2, lb = lc + 1, c_ = c0 + lc;
+    const int oi0 = lb * OH + (y0 - r0 + 1);  // omega index of the run's first pixel
+    h2 zl[3], zc[3], xr[2], xl[2], yc[4], xc[2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) yc[t] = __builtin_bit_cast(h2, omy[oi0 + t - 1]);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      zc[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1]);
+      zl[t] = __builtin_bit_cast(h2, omz[oi0 + t - 1 - OH]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      xc[t] = __builtin_bit_cast(h2, omx[oi0 + t]);
+      xl[t] = __builtin_bit_cast(h2, omx[oi0 + t - OH]);
+      xr[t] = __builtin_bit_cast(h2, omx[oi0 + t + OH]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int y = y0 + t;
+      const h2 two = {_Float16(2), _Float16(2)};
+      // q = Dxx^T s_xx + Dyy^T s_yy + Dxy^T s_xy at (y, c), both fields
+      const h2 qq = xl[t] - two * xc[t] + xr[t] + yc[t] - two * yc[t + 1] + yc[t + 2] + zc[t + 1] - zl[t + 1] -
+                    zc[t] + zl[t];
+      const T qa = T(qq.x), qp = T(qq.y);
+      const T sgn = ((c_ + y) & 1) ? -inv_n : inv_n;
+      cx<T>& slot = buf[l * PITCH + y];
+      const cx<T> O = scale(slot, sgn);
+      const T a2 = norm2(O);
+      cx<T> G = czero<T>();
+      if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * qa * rsqrt_t(a2));
+      const T den = a2 + T(o.eta_h);
+      if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * qp * rcp_t(den));
+      slot = scale(G, sgn);
+    }
+  };
+  // Software pipeline over the chunks, one barrier per stage: stage s runs A(s) (the
+  // next chunk's amplitude and phase, into the other array set), B(s - 1) and C(s - 2).
+  // A(s) reads O rows r0(s) - 2 .. r0(s) + 65, which C(s - 2) (own rows r0(s) - 128 ..
+  // r0(s) - 65) does not touch; A(s) and B(s - 1) use different (|O|, angle(O)) sets,
+  // B(s - 1) and C(s - 2) different sign sets.  The items of the three are spread over
+  // the block as one list, so that no wave idles while another finishes a stage.
+  const int nA = NL * RS, nB = LB * (OH / 2), nC = W * (CH / 2);
+  for (int st = 0; st < NCH + 2; ++st) {
+    const int ca = st, cb = st - 1, cc = st - 2;
+    const int na = ca < NCH ? nA : 0, nb = cb >= 0 && cb < NCH ? nB : 0, nc = cc >= 0 ? nC : 0;
+    const bool inb = strip_in && cb >= 1 && cb * CH + CH <= N - 2;
+    for (int q = tid; q < na + nb + nc; q += NT) {
+      if (q < na) stage_a(ca, q);
+      else if (q < na + nb) {
+        if (inb) stage_b(cb, q - na, std::true_type{});
+        else stage_b(cb, q - na, std::false_type{});
+      } else {
+        stage_c(cc, q - na - nb);
+      }
+    }
+    if (nb) {
+      la += double(ta);
+      lp += double(tp);
+      ta = T(0);
+      tp = T(0);
+    }
+    __syncthreads();
   }
   // forward DFT along the own columns (lines 2 .. W + 1); the last pass stores its outputs
   // straight to T2 (line m = column c0 + m).  The loss partials wait in shared memory.
