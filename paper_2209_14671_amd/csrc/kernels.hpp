@@ -1190,7 +1190,7 @@ constexpr size_t obj_wide_form_bytes() {
   constexpr size_t lines = sizeof(cx<T>) * (Sh::NLM * Sh::PITCH + N);
   if constexpr (SIGN) {
     constexpr size_t chunk = 2 * (2 * sizeof(T) * Sh::NLM * Sh::RS + 3 * sizeof(unsigned) * Sh::OWM * Sh::OH);
-    constexpr size_t sums = sizeof(double) * (2 * NT + 16);
+    constexpr size_t sums = sizeof(double) * (4 * NT);
     return lines + (chunk > sums ? chunk : sums);
   }
   return lines + sizeof(T) * 2 * Sh::NLM * Sh::RS + sizeof(T) * 6 * Sh::OWM * Sh::OH + 8 +
@@ -1569,6 +1569,9 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     const int lc = q / (CH / 2), y0 = r0 + 2 * (q % (CH / 2));
     const int l = lc + 2, lb = lc + 1, c_ = c0 + lc;
     const int oi0 = lb * OH + (y0 - r0 + 1);  // omega index of the run's first pixel
+    cx<T> Ot[2];  // the run's two values of Ot, read first (one wait for every read)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) Ot[t] = buf[l * PITCH + y0 + t];
     h2 zl[3], zc[3], xr[2], xl[2], yc[4], xc[2];
 #pragma unroll
     for (int t = 0; t < 4; ++t) yc[t] = __builtin_bit_cast(h2, omy[oi0 + t - 1]);
@@ -1592,14 +1595,13 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
                     zc[t] + zl[t];
       const T qa = T(qq.x), qp = T(qq.y);
       const T sgn = ((c_ + y) & 1) ? -inv_n : inv_n;
-      cx<T>& slot = buf[l * PITCH + y];
-      const cx<T> O = scale(slot, sgn);
+      const cx<T> O = scale(Ot[t], sgn);
       const T a2 = norm2(O);
       cx<T> G = czero<T>();
       if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * qa * rsqrt_t(a2));
       const T den = a2 + T(o.eta_h);
       if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * qp * rcp_t(den));
-      slot = scale(G, sgn);
+      buf[l * PITCH + y] = scale(G, sgn);
     }
   };
   // Software pipeline over the chunks, one barrier per stage: stage s runs A(s) (the
@@ -1634,11 +1636,28 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   // straight to T2 (line m = column c0 + m).  The loss partials wait in shared memory.
   lsum[tid] = la;
   lsum[NT + tid] = lp;
+  // deterministic block sums of the two penalty partials, a level between two passes (the
+  // passes' barriers publish each level): 64 threads each add 16 slots in order, 8 threads
+  // each 8 of those, thread 0 the 8
+  static_assert(NT == 1024, "16 x 8 x 8 slots");
+  auto sum_level = [&](int nthr, int nin, int src, int dst) {
+    if (tid < nthr) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int w = 0; w < nin; ++w) {
+        s0 += lsum[src + (nthr == 64 ? w * 64 + tid : nin * tid + w)];
+        s1 += lsum[src + NT + (nthr == 64 ? w * 64 + tid : nin * tid + w)];
+      }
+      lsum[dst + tid] = s0;
+      lsum[dst + NT + tid] = s1;
+    }
+  };
   {
     cx<T>* own = buf + 2 * PITCH;
     constexpr int WM = Sh::WMAX;
     StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
+    sum_level(64, 16, 0, 2 * NT);  // slots 2 NT .. (the first pass's barriers published lsum)
     StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
+    sum_level(8, 8, 2 * NT, 2 * NT + 64);
     using PC = StockhamPass<T, N, R3, R1 * R2, false, NT, ceil_div(WM * (N / R3), NT), PITCH, 1>;
     constexpr int MB = ceil_div(WM * (N / R3), NT);
     int m[MB], j[MB];
@@ -1653,34 +1672,12 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
         for (int r = 0; r < R3; ++r) T2[(size_t)PC::out_index(j[i], r) * N + c0 + m[i]] = v[i][r];
       }
   }
-  // deterministic block sums of the two penalty partials: 64 threads each add 16 slots in
-  // order, 8 threads each 8 of those, thread 0 the 8
-  static_assert(NT == 1024, "16 x 8 x 8 slots");
-  if (tid < 64) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < 16; ++w) {
-      s0 += lsum[w * 64 + tid];
-      s1 += lsum[NT + w * 64 + tid];
-    }
-    lsum[tid] = s0;  // a slot only this thread has read
-    lsum[NT + tid] = s1;
-  }
-  __syncthreads();
-  if (tid < 8) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < 8; ++w) {
-      s0 += lsum[8 * tid + w];
-      s1 += lsum[NT + 8 * tid + w];
-    }
-    lsum[2 * NT + tid] = s0;  // past the 2 NT slots: room left in the chunk arrays
-    lsum[2 * NT + 8 + tid] = s1;
-  }
-  __syncthreads();
+  __syncthreads();  // the second level
   if (tid == 0) {
     double s0 = 0.0, s1 = 0.0;
     for (int w = 0; w < 8; ++w) {
-      s0 += lsum[2 * NT + w];
-      s1 += lsum[2 * NT + 8 + w];
+      s0 += lsum[2 * NT + 64 + w];
+      s1 += lsum[3 * NT + 64 + w];
     }
     o.partial[2 * b + 0] = s0;
     o.partial[2 * b + 1] = s1;
