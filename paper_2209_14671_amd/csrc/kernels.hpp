@@ -2085,7 +2085,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #define ELFPIE_UPDR_GB 16  // contribution loads in flight per pixel (row form)
 #endif
 #ifndef ELFPIE_UPDR_PF
-#define ELFPIE_UPDR_PF 1  // gather batches issued before the row transform (one pixel per thread)
+#define ELFPIE_UPDR_PF 8  // contribution loads issued before the row transform (one pixel per thread)
 #endif
 #ifndef ELFPIE_UPDROWS_NT
 #define ELFPIE_UPDROWS_NT 512  // threads per block (at most one per pixel of the block's rows)
@@ -2097,10 +2097,15 @@ template <int N> struct UpdRows {
   static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
   static constexpr int NT0 = ELFPIE_UPDROWS_NT < RB * N ? ELFPIE_UPDROWS_NT : RB * N;
   static constexpr int NT = (RB * N) % NT0 == 0 ? NT0 : 256;
+  static constexpr int MINW = N == 512 ? 6 : 1;  // waves per SIMD the registers must allow (512^2)
 };
 
+// For the 512^2 spectrum in FP32, three 512-thread row blocks per compute unit (six waves
+// per SIMD: at most 80 registers), so that a launch's row and pupil blocks are resident
+// together.
 template <class T, int N>
-__global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, PupilArgs pa, FinArgs fa) {
+__global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW : 1) void k_update_rows(
+    UpdArgs a, PupilArgs pa, FinArgs fa) {
   constexpr int RB = UpdRows<N>::RB, NT = UpdRows<N>::NT, PITCH = N + 1;
   constexpr int PPT = RB * N / NT;  // pixels per thread
   static_assert(PPT * NT == RB * N && N % 64 == 0, "whole pixels per thread, whole segments per wave");
@@ -2178,7 +2183,7 @@ __global__ __launch_bounds__(UpdRows<N>::NT) void k_update_rows(UpdArgs a, Pupil
   // transform (the barriers there wait for LDS only), and are added after gH, in the
   // same order as the walk below
   constexpr bool PF = PPT == 1;
-  constexpr int PG = PF ? ELFPIE_UPDR_PF * GB : 1;  // loads issued early
+  constexpr int PG = PF ? ELFPIE_UPDR_PF : 1;  // loads issued early
   static_assert(PG <= 64, "early loads come from the entries held in lanes");
   cx<T> pre[PG];
   if constexpr (PF) {
