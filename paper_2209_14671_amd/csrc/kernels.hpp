@@ -1590,17 +1590,19 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     for (int t = 0; t < 2; ++t) {
       const int y = y0 + t;
       const h2 two = {_Float16(2), _Float16(2)};
-      // q = Dxx^T s_xx + Dyy^T s_yy + Dxy^T s_xy at (y, c), both fields
-      const h2 qq = xl[t] - two * xc[t] + xr[t] + yc[t] - two * yc[t + 1] + yc[t + 2] + zc[t + 1] - zl[t + 1] -
-                    zc[t] + zl[t];
+      // q = Dxx^T s_xx + Dyy^T s_yy + Dxy^T s_xy at (y, c), both fields, as a shallow tree
+      // (sums of at most ten small integers: exact in any order)
+      const h2 qq = ((xl[t] + xr[t]) + (yc[t] + yc[t + 2])) + ((zc[t + 1] + zl[t]) - two * (xc[t] + yc[t + 1])) -
+                    (zl[t + 1] + zc[t]);
       const T qa = T(qq.x), qp = T(qq.y);
       const T sgn = ((c_ + y) & 1) ? -inv_n : inv_n;
       const cx<T> O = scale(Ot[t], sgn);
       const T a2 = norm2(O);
-      cx<T> G = czero<T>();
-      if (a2 > T(0)) G = scale(O, T(0.5) * T(o.alpha) * qa * rsqrt_t(a2));
       const T den = a2 + T(o.eta_h);
-      if (den > T(0)) G = G + scale(mul_i(O), T(0.5) * T(o.beta) * qp * rcp_t(den));
+      // the amplitude term where |O| > 0 and the phase term where |O|^2 + eta > 0, as selects
+      const T fa = a2 > T(0) ? T(0.5) * T(o.alpha) * qa * rsqrt_t(a2) : T(0);
+      const T fp = den > T(0) ? T(0.5) * T(o.beta) * qp * rcp_t(den) : T(0);
+      const cx<T> G = scale(O, fa) + scale(mul_i(O), fp);
       buf[l * PITCH + y] = scale(G, sgn);
     }
   };
@@ -2093,11 +2095,14 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #ifndef ELFPIE_UPDROWS_RB
 #define ELFPIE_UPDROWS_RB 1  // rows per block where 256 threads cover whole rows
 #endif
+#ifndef ELFPIE_UPDR_MINW
+#define ELFPIE_UPDR_MINW 6
+#endif
 template <int N> struct UpdRows {
   static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
   static constexpr int NT0 = ELFPIE_UPDROWS_NT < RB * N ? ELFPIE_UPDROWS_NT : RB * N;
   static constexpr int NT = (RB * N) % NT0 == 0 ? NT0 : 256;
-  static constexpr int MINW = N == 512 ? 6 : 1;  // waves per SIMD the registers must allow (512^2)
+  static constexpr int MINW = N == 512 ? ELFPIE_UPDR_MINW : 1;  // waves per SIMD the registers must allow (512^2)
 };
 
 // For the 512^2 spectrum in FP32, three 512-thread row blocks per compute unit (six waves
