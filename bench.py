@@ -527,16 +527,15 @@ def main():
     # one history buffer for the warm-up and the timed run: the run graphs are keyed on its
     # address, so the warm-up captures them and the timed run only replays
     hist_buf = torch.empty((max(args.warmup, args.steps, 1), 4), dtype=torch.float64, device=dev)
+    # per-kernel timing (HIP events around back-to-back launches on this stream; the state is
+    # read, not changed), then the warm-up iterations right before the timed ones
+    log("per-stage timing")
+    stages = plan.stage_timing(st, meas, args.stage_reps)
     log(f"warmup {args.warmup} iterations")
     if args.warmup:
         plan.run(st, meas, args.warmup, history=hist_buf)
     torch.cuda.synchronize()
     cap0 = plan.stats()["captures"]
-    # per-kernel timing (HIP events around back-to-back launches on this stream; the state is
-    # read, not changed) before the timed run: the warm-up's graph capture leaves the GPU idle
-    # for tens of milliseconds of host work, and these launches bring it back to steady clocks
-    log("per-stage timing")
-    stages = plan.stage_timing(st, meas, args.stage_reps)
 
     log(f"timing {args.steps} iterations")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -222,12 +222,14 @@ elfpie_status elfpie_grad_noalloc(const elfpie_problem *p, const void *psi, cons
 elfpie_status elfpie_step(elfpie_plan *plan, const elfpie_state *state, const void *meas,
                           double *d_loss4, void *stream);
 
-/* n_iter iterations (elfpie_step repeated), replayed from HIP graphs of 32 iterations
- * and then at most one each of 16, 8, 4, 2 and 1, all captured by the first call with
- * these state, stack and history pointers; later calls with the same pointers only
- * replay, so the first call carries the capture cost.  Graphs are captured again after
- * elfpie_plan_set_penalty and when a pointer changes; the old ones are destroyed only
- * after their last replays have finished.  d_loss_hist (optional, device, n_iter x 4
+/* n_iter iterations (elfpie_step repeated).  A plan whose object branch rides in the
+ * per-LED launch (elfpie_stage_timing's [4]: two long launches per iteration) launches
+ * them directly on `stream` and captures nothing.  Other plans replay HIP graphs of 32
+ * iterations and then at most one each of 16, 8, 4, 2 and 1, all captured by the first
+ * call with these state, stack and history pointers; later calls with the same pointers
+ * only replay, so the first call carries the capture cost.  Graphs are captured again
+ * after elfpie_plan_set_penalty and when a pointer changes; the old ones are destroyed
+ * only after their last replays have finished.  d_loss_hist (optional, device, n_iter x 4
  * doubles) receives each iteration's loss terms.  checked = 1 waits for the
  * stream at the end and returns ELFPIE_E_NONFINITE if any loss was NaN / Inf;
  * checked = 0 returns at once. */

@@ -55,6 +55,13 @@ struct TailReq {
   TailArgs a{};
 };
 
+// The loss history slot counter and the non-finite flag of a run, cleared by its
+// opening launch.
+struct Resets {
+  int* ctr;
+  int* flag;
+};
+
 // A tail with nothing to do.
 inline TailReq no_tail() {
   TailReq r;
@@ -606,7 +613,8 @@ struct Ops {
   }
 
   template <int N, bool INV, bool COLS>
-  static void launch_lines(const C* in, C* out, const C* tw, const TailReq* tail, hipStream_t s) {
+  static void launch_lines(const C* in, C* out, const C* tw, const TailReq* tail, const Resets* rs,
+                           hipStream_t s) {
     using Sh = BigShape<N, COLS>;
     TailArgs ta{};
     int extra = 0;
@@ -614,24 +622,32 @@ struct Ops {
       ta = shape_tail(*tail, Sh::NT);
       extra = ta.pupil_blocks + ta.fin_block;
     }
+    if (rs && extra) {  // a riding loss block reads the counter: clear it before the launch
+      k_fill<int><<<1, 64, 0, s>>>(rs->ctr, 0, 1);
+      k_fill<int><<<1, 64, 0, s>>>(rs->flag, 0, 1);
+    } else if (rs) {
+      ta.zero_ctr = rs->ctr;
+      ta.zero_flag = rs->flag;
+    }
     k_fft_lines<T, N, INV, COLS><<<N / Sh::RPB + extra, Sh::NT, 0, s>>>(in, out, tw, ta);
   }
 
-  // Transform of every row or column of an n_hi^2 array; a pending tail rides along.
+  // Transform of every row or column of an n_hi^2 array; a pending tail rides along, and
+  // (rs) the launch clears a run's counters.
   template <bool INV, bool COLS>
   static elfpie_status lines(elfpie_plan* pl, const void* in, void* out, hipStream_t s,
-                             const TailReq* tail = nullptr) {
+                             const TailReq* tail = nullptr, const Resets* rs = nullptr) {
     const Tables& tb = pl->tb;
     const C* tw = pl->at<C>(tb.o_twhi);
     const C* i = static_cast<const C*>(in);
     C* o = static_cast<C*>(out);
     switch (tb.n_hi) {
-      case 128: launch_lines<128, INV, COLS>(i, o, tw, tail, s); break;
-      case 256: launch_lines<256, INV, COLS>(i, o, tw, tail, s); break;
-      case 384: launch_lines<384, INV, COLS>(i, o, tw, tail, s); break;
-      case 512: launch_lines<512, INV, COLS>(i, o, tw, tail, s); break;
-      case 768: launch_lines<768, INV, COLS>(i, o, tw, tail, s); break;
-      case 1024: launch_lines<1024, INV, COLS>(i, o, tw, tail, s); break;
+      case 128: launch_lines<128, INV, COLS>(i, o, tw, tail, rs, s); break;
+      case 256: launch_lines<256, INV, COLS>(i, o, tw, tail, rs, s); break;
+      case 384: launch_lines<384, INV, COLS>(i, o, tw, tail, rs, s); break;
+      case 512: launch_lines<512, INV, COLS>(i, o, tw, tail, rs, s); break;
+      case 768: launch_lines<768, INV, COLS>(i, o, tw, tail, rs, s); break;
+      case 1024: launch_lines<1024, INV, COLS>(i, o, tw, tail, rs, s); break;
       default: return set_err(pl, ELFPIE_E_UNSUPPORTED, "n_hi not supported");
     }
     LAUNCH_CHECK(pl, "k_fft_lines");
@@ -968,10 +984,12 @@ struct Ops {
   // inverse row transforms of the next one ride in the update launch: t1_ready says
   // that T1 already holds the latter (the previous iteration of the same call left it),
   // and par picks the Hessian loss partial buffer, alternating between iterations.
+  // rs: the run's counters, cleared before anything of this iteration reads them.
   static elfpie_status iteration(elfpie_plan* pl, const void* psi, const void* P, const void* meas,
                                  const elfpie_state* st, void* g_psi, void* g_P, double* loss4, double* hist,
                                  hipStream_t s, const TailReq* prev = nullptr, TailReq* defer = nullptr,
-                                 const void* stored_fields = nullptr, bool t1_ready = false, int par = 0) {
+                                 const void* stored_fields = nullptr, bool t1_ready = false, int par = 0,
+                                 const Resets* rs = nullptr) {
     const Tables& tb = pl->tb;
     void* T1 = pl->at<void>(tb.o_T1);
     void* T2 = pl->at<void>(tb.o_T2);
@@ -979,12 +997,17 @@ struct Ops {
     const int mode = stored_fields ? LED_GRAD | LED_STORED : LED_GRAD;
     const bool learn_p = st ? (pl->prob.flags & ELFPIE_LEARN_PUPIL) != 0 : g_P != nullptr;
     const bool pre = learn_p && st && (pl->prob.flags & ELFPIE_PUPIL_FILTER);
+    if (rs && !(tb.fused && !t1_ready)) {  // no row transform opens this iteration
+      k_fill<int><<<1, 64, 0, s>>>(rs->ctr, 0, 1);
+      k_fill<int><<<1, 64, 0, s>>>(rs->flag, 0, 1);
+      rs = nullptr;
+    }
     if (tb.fused) {
       // the inverse row transforms of psi first (unless the previous update left them in
       // T1), with a pending tail riding along; else that tail alone: the per-LED launch
       // reads P, so the previous pupil update finishes before it
       if (!t1_ready) {
-        if ((r = lines<true, false>(pl, psi, T1, s, prev)) != ELFPIE_OK) return r;
+        if ((r = lines<true, false>(pl, psi, T1, s, prev, rs)) != ELFPIE_OK) return r;
       } else if (prev && (r = tail(pl, *prev, s)) != ELFPIE_OK) {
         return r;
       }
@@ -1028,15 +1051,17 @@ struct Ops {
   // With the row form, a sequence of calls can chain: cont says that an earlier call
   // of the same run left T1 ready and its last pupil update pending (it rides in this
   // call's first launch); without close this call leaves the same to the next one.
+  // rs: the run's counters, cleared by the first iteration.
   static elfpie_status iterations(elfpie_plan* pl, const elfpie_state* st, const void* meas, int n_iter,
-                                  double* hist, hipStream_t s, bool cont = false, bool close = true) {
+                                  double* hist, hipStream_t s, bool cont = false, bool close = true,
+                                  const Resets* rs = nullptr) {
     TailReq pend = cont ? pending_pupil(pl, st, hist) : TailReq{};
     elfpie_status r = ELFPIE_OK;
     for (int it = 0; it < n_iter && r == ELFPIE_OK; ++it) {
       TailReq next;
       const bool chained = it > 0 || cont;
       r = iteration(pl, st->psi, st->P, meas, st, nullptr, nullptr, nullptr, hist, s, chained ? &pend : nullptr, &next,
-                    nullptr, chained, it & 1);
+                    nullptr, chained, it & 1, it == 0 ? rs : nullptr);
       pend = next;
     }
     if (r != ELFPIE_OK || (n_iter == 0 && !cont) || !close) return r;
@@ -1128,11 +1153,11 @@ struct Ops {
         C* work = pl->at<C>(tb.o_T1);
         k_init_big_prep<T><<<nb, 256, 0, s>>>(mc, work, tb.n_lo);
         if (tb.n_lo == 192) {
-          launch_lines<192, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
-          launch_lines<192, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+          launch_lines<192, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, nullptr, s);
+          launch_lines<192, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, nullptr, s);
         } else {
-          launch_lines<256, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
-          launch_lines<256, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, s);
+          launch_lines<256, false, false>(work, work, pl->at<C>(tb.o_twlo), nullptr, nullptr, s);
+          launch_lines<256, false, true>(work, work, pl->at<C>(tb.o_twlo), nullptr, nullptr, s);
         }
         k_init_big_place<T><<<nb, 256, 0, s>>>(work, psi, y0, x0, tb.n_hi, tb.n_lo, sc, xlo, xhi);
         LAUNCH_CHECK(pl, "k_init_big");
@@ -1568,6 +1593,19 @@ elfpie_status elfpie_step(elfpie_plan* pl, const elfpie_state* st, const void* m
   });
 }
 
+// The end of a run call: mark the last replay (graph execs are destroyed only after it),
+// and with `checked` wait for the stream and report a non-finite loss.
+static elfpie_status finish_run(elfpie_plan* pl, const int* flag, int32_t checked, hipStream_t s) {
+  HIP_TRY(pl, hipEventRecord(pl->gdone, s));
+  if (checked) {
+    HIP_TRY(pl, hipStreamSynchronize(s));
+    int h = 0;
+    HIP_TRY(pl, hipMemcpy(&h, flag, sizeof h, hipMemcpyDeviceToHost));
+    if (h) return set_err(pl, ELFPIE_E_NONFINITE, "a loss value was NaN or Inf");
+  }
+  return ELFPIE_OK;
+}
+
 elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* meas, int32_t n_iter,
                          double* d_loss_hist, int32_t checked, void* stream) {
   if (!pl) return ELFPIE_E_INVALID;
@@ -1588,6 +1626,17 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
     return ELFPIE_OK;
   }
   const bool chain = tb.rowupd;
+  if (tb.fused) {
+    // a fused plan's iteration is two long launches, which the host submits well ahead of
+    // the GPU: launched directly, a run captures nothing and has no joins between graph
+    // replays, and its opening row transforms clear the counters
+    const Resets rs{ctr, flag};
+    const elfpie_status r = dispatch(pl, [&](auto ops) {
+      return decltype(ops)::iterations(pl, st, meas, n_iter, d_loss_hist, s, false, true, &rs);
+    });
+    if (r != ELFPIE_OK) return r;
+    return finish_run(pl, flag, checked, s);
+  }
   // the graphs bake in every pointer of the iteration: reuse them only for the same ones
   const bool same = pl->gvalid && std::memcmp(&pl->gkey, st, sizeof *st) == 0 && pl->gkey_meas == meas &&
                     pl->gkey_hist == d_loss_hist;
@@ -1650,14 +1699,7 @@ elfpie_status elfpie_run(elfpie_plan* pl, const elfpie_state* st, const void* me
         dispatch(pl, [&](auto ops) { return decltype(ops)::close_run(pl, st, d_loss_hist, s); });
     if (r != ELFPIE_OK) return r;
   }
-  HIP_TRY(pl, hipEventRecord(pl->gdone, s));
-  if (checked) {
-    HIP_TRY(pl, hipStreamSynchronize(s));
-    int h = 0;
-    HIP_TRY(pl, hipMemcpy(&h, flag, sizeof h, hipMemcpyDeviceToHost));
-    if (h) return set_err(pl, ELFPIE_E_NONFINITE, "a loss value was NaN or Inf");
-  }
-  return ELFPIE_OK;
+  return finish_run(pl, flag, checked, s);
 }
 
 elfpie_status elfpie_object_from_spectrum(elfpie_plan* pl, const void* psi, void* obj, void* stream) {

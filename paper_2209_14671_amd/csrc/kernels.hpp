@@ -860,7 +860,8 @@ __device__ __forceinline__ void pupil_finish(const PupilArgs& a, const double* s
 // Unnormalised DFT (inverse when INV) of every row (COLS = false) or every column
 // (COLS = true) of an N x N complex array; in may equal out.  Blocks past the
 // N / RPB line blocks run the previous iteration's tail (pupil update, loss), which
-// touches none of the arrays transformed here.
+// touches none of the arrays transformed here.  As the opening launch of a run (no
+// tail then), block 0 clears the run's loss counters.
 template <class T, int N, bool INV, bool COLS>
 __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<T>* in, cx<T>* out,
                                                                       const cx<T>* tw, TailArgs ta) {
@@ -881,6 +882,10 @@ __global__ __launch_bounds__((BigShape<N, COLS>::NT)) void k_fft_lines(const cx<
     return;
   }
   const int l0 = blockIdx.x * RPB;
+  if (blockIdx.x == 0 && tid == 0) {
+    if (ta.zero_ctr) *ta.zero_ctr = 0;
+    if (ta.zero_flag) *ta.zero_flag = 0;
+  }
   for (int i = tid; i < N; i += NT) twl[i] = tw[i];
   cx<T> ld[EPT];
 #pragma unroll

@@ -157,6 +157,10 @@ struct TailArgs {
   int pupil_blocks;     // blocks of the pupil update (0: none)
   int fin_block;        // 1: one more block reduces the loss
   int pupil_ppb;        // riding in the strip launch: pupil pixels per strip block (0: none)
+  // the opening launch of a run (the row transforms, no tail riding along): its first
+  // block clears the loss history slot counter and the non-finite flag (NULL: neither)
+  int* zero_ctr;
+  int* zero_flag;
 };
 
 

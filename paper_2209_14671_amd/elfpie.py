@@ -97,16 +97,16 @@ class State:
     t: torch.Tensor
 
     def to_c(self):
-        s = _lib.StateC()
-        for f in dataclasses.fields(self):
-            setattr(s, f.name, getattr(self, f.name).data_ptr())
-        return s
+        return _lib.StateC(*(getattr(self, f).data_ptr() for f in _STATE_FIELDS))
 
     def clone(self) -> "State":
         return State(*(getattr(self, f.name).clone() for f in dataclasses.fields(self)))
 
     def state_dict(self):
         return {f.name: getattr(self, f.name) for f in dataclasses.fields(self)}
+
+
+_STATE_FIELDS = tuple(f.name for f in dataclasses.fields(State))
 
 
 class Plan:
@@ -151,14 +151,16 @@ class Plan:
 
     # -- argument checks ------------------------------------------------------------
     def _need(self, t, shape, dtype, name):
+        # one combined test on the common path (a run call checks nine state tensors)
+        if (isinstance(t, torch.Tensor) and t.dtype == dtype and t.shape == shape and t.device == self.device
+                and t.is_contiguous()):
+            return t
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch tensor")
         if t.device != self.device:
             raise ValueError(f"{name} is on {t.device}, plan is on {self.device}")
-        if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
-                             f"got {t.dtype} {tuple(t.shape)}")
-        return t
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
 
     def _check(self, status):
         _lib.check(status, self.handle)

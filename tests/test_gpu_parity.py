@@ -446,10 +446,10 @@ def test_config2_full_size_literal_l1_at_the_librarys_decisions():
 
 
 def test_config2_chained_run_equals_steps_and_tracks_oracle():
-    """The launch sequence the benchmark times, at full size: elfpie_run(41) replays graphs
-    of 32, 8 and 1 iterations that open, continue and close a chain (T1 carried over, the
-    pupil update riding in the strip launch).  In the benchmark's mode (literal L1) it must
-    equal 41 elfpie_step calls bit for bit.  In the smoothed mode three chained iterations
+    """The launch sequence the benchmark times, at full size: elfpie_run(41) launches 41
+    iterations directly (T1 carried over from each update launch to the next per-LED launch,
+    the run's counters cleared by its opening row transforms).  In the benchmark's mode
+    (literal L1) it must equal 41 elfpie_step calls bit for bit.  In the smoothed mode three chained iterations
     (graphs of 2 and 1) must match three oracle iterations to 1e-5."""
     for l1_eps in (0.0, 1e-3):
         pair = _config2_pair(l1_eps)
