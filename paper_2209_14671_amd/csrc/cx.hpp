@@ -32,12 +32,12 @@ template <class T> __host__ __device__ __forceinline__ cx<T> mul_i(cx<T> a) { re
 #ifndef ELFPIE_FAST_SIGN
 #define ELFPIE_FAST_SIGN 1
 #endif
-// sign(d) in {-1, 0, 1}.  FP32: three operations instead of two compares, two selects and
-// a conversion: d * 2^127 * 2^127 keeps the sign, is exact or overflows to +-inf, and is
-// at least 2^105 in magnitude for every nonzero d (denormals included), so the median with
-// -1 and 1 is exactly the sign (zero stays zero).
+// sign(d) in {-1, 0, 1}.  FP32: two operations instead of two compares, two selects and
+// a conversion: d * 2^254 (an exponent shift) keeps the sign, is exact or overflows to
+// +-inf, and is at least 2^105 in magnitude for every nonzero d (denormals included), so
+// the median with -1 and 1 is exactly the sign (zero stays zero).
 __device__ __forceinline__ float sign_unit(float d) {
-  if (ELFPIE_FAST_SIGN) return __builtin_amdgcn_fmed3f(d * 0x1p127f * 0x1p127f, -1.0f, 1.0f);
+  if (ELFPIE_FAST_SIGN) return __builtin_amdgcn_fmed3f(__builtin_ldexpf(d, 254), -1.0f, 1.0f);
   return float((d > 0.0f) - (d < 0.0f));
 }
 __device__ __forceinline__ double sign_unit(double d) { return double((d > 0.0) - (d < 0.0)); }

@@ -1501,37 +1501,36 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
     StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
   }
-  // (|O|, angle(O)) at line l, row y (zero off the grid); O = (-1)^(x+y) Ot / n.  CHK:
-  // check the row against the grid (lines off the grid hold zeros already)
+  // (|O|, angle(O)) at line l, row y (zero off the grid); O = (-1)^(x+y) Ot / n, so |O| =
+  // |Ot| / n and angle(O) = atan2 of Ot negated where x + y is odd (a positive scale leaves
+  // atan2's ratio alone; 1 / n is a power of two, so the scaled parts are exact anyway).
+  // CHK: check the row against the grid (lines off the grid hold zeros already)
+  static_assert((N & (N - 1)) == 0, "1 / n a power of two");
   auto amp_phase = [&](int l, int y, auto chk_c) -> cx<T> {
     if (decltype(chk_c)::value && (y < 0 || y >= N)) return czero<T>();
     const int c = c0 - 2 + l;
-    const cx<T> O = scale(buf[l * PITCH + y], ((c + y) & 1) ? -inv_n : inv_n);
-    return cx<T>{sqrt_t(norm2(O)), atan2_fast(O.y, O.x)};
+    const cx<T> Ot = buf[l * PITCH + y];
+    const bool neg = (c + y) & 1;
+    return cx<T>{inv_n * sqrt_t(norm2(Ot)), atan2_fast(neg ? -Ot.y : Ot.y, neg ? -Ot.x : Ot.x)};
   };
   T ta = T(0), tp = T(0);  // this thread's loss terms of the current chunk
   double la = 0.0, lp = 0.0;
   const int cx0 = c0 - 1;   // column of omega line lb = 0
-  // a strip whose stencils stay on the grid in x: every line's column in 0 .. N - 1 and
-  // every omega line's in 1 .. N - 2
-  const bool strip_in = c0 >= 2 && c0 + W <= N - 2;
   constexpr int NCH = N / CH;
   // A(c), item q: (|O|, angle(O)) of line q / RS, chunk row q % RS (y = r0 - 2 + q % RS)
   auto stage_a = [&](int c, int q) {
     const int l = q / RS, i = q % RS;
     sfb(c)[l * RS + i] = amp_phase(l, c * CH - 2 + i, std::true_type{});
   };
-  // B(c), item q: omega on line lb + 1, rows ib = 2 (q mod OH / 2) and the next
-  // (y = r0 - 1 + ib).  IN: the strip is inside and the chunk's rows keep every stencil
-  // on the grid, so that no bound is checked.
-  auto stage_b = [&](int c, int q, auto in_c) {
+  // B(c) on line lb + 1, rows ib = ib0 and ib0 + 1 (y = r0 - 1 + ib).  IN: every stencil
+  // of the two pixels stays on the grid, so that no bound is checked.
+  auto stage_b = [&](int c, int lb, int ib0, auto in_c) {
     constexpr bool IN = decltype(in_c)::value;
     const int r0 = c * CH;
     const cx<T>* sf = sfb(c);
     unsigned* omx = omb(c);
     unsigned* omy = omx + OWM * OH;
     unsigned* omz = omy + OWM * OH;
-    const int lb = q / (OH / 2), ib0 = 2 * (q % (OH / 2));
     const int l = lb + 1, c_ = cx0 + lb;
     const bool cin = c_ >= 0 && c_ < N, cxx = c_ >= 1 && c_ <= N - 2, cxy = c_ <= N - 2;
     const bool own_c = l >= 2 && l <= W + 1;
@@ -1552,10 +1551,15 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
       const bool vxx = IN || (in && cxx), vyy = IN || (in && y >= 1 && y <= N - 2);
       const bool vxy = IN || (in && cxy && y <= N - 2);
       const cx<T> f = ctr[t + 1], fl = lft[t], fr = rgt[t], fu = ctr[t], fd = ctr[t + 2], frd = rgt[t + 1];
-      // components of |O| (.x) and angle(O) (.y)
-      const T hxa = vxx ? fl.x - T(2) * f.x + fr.x : T(0), hxp = vxx ? fl.y - T(2) * f.y + fr.y : T(0);
-      const T hya = vyy ? fu.x - T(2) * f.x + fd.x : T(0), hyp = vyy ? fu.y - T(2) * f.y + fd.y : T(0);
-      const T hza = vxy ? f.x - fr.x - fd.x + frd.x : T(0), hzp = vxy ? f.y - fr.y - fd.y + frd.y : T(0);
+      // components of |O| (.x) and angle(O) (.y), computed everywhere, then cleared where the
+      // stencil leaves the grid by a bit mask (an arithmetic select: no branch, no load
+      // moved under a condition)
+      auto keep = [](T h, bool v) {
+        return __builtin_bit_cast(T, __builtin_bit_cast(unsigned, h) & (v ? 0xffffffffu : 0u));
+      };
+      const T hxa = keep(fl.x - T(2) * f.x + fr.x, vxx), hxp = keep(fl.y - T(2) * f.y + fr.y, vxx);
+      const T hya = keep(fu.x - T(2) * f.x + fd.x, vyy), hyp = keep(fu.y - T(2) * f.y + fd.y, vyy);
+      const T hza = keep(f.x - fr.x - fd.x + frd.x, vxy), hzp = keep(f.y - fr.y - fd.y + frd.y, vxy);
       const int oi = lb * OH + ib;
       omx[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hxa), sign_unit(hxp)));
       omy[oi] = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(sign_unit(hya), sign_unit(hyp)));
@@ -1565,14 +1569,18 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
       tp += own ? fabs(hxp) + fabs(hyp) + fabs(hzp) : T(0);
     }
   };
-  // C(c), item q: own line l = q / (CH / 2) + 2, rows y = r0 + 2 (q mod CH / 2) and the next
+  // C(c), item q: own line l = q / (CH / 2) + 2, rows y = r0 + 2 (q mod CH / 2) and the next.
+  // With O = s Ot, s = (-1)^(x+y) / n, the value written, s G, is Ot (ka qa / |Ot| + i kp qp /
+  // (|Ot|^2 + eta n^2)) with ka = alpha / (2 n) and kp = beta / 2: the sign s drops out.
+  const T ka = T(0.5) * T(o.alpha) * inv_n, kp = T(0.5) * T(o.beta);
+  const T eta_n2 = T(o.eta_h) / (inv_n * inv_n);
   auto stage_c = [&](int c, int q) {
     const int r0 = c * CH;
     const unsigned* omx = omb(c);
     const unsigned* omy = omx + OWM * OH;
     const unsigned* omz = omy + OWM * OH;
     const int lc = q / (CH / 2), y0 = r0 + 2 * (q % (CH / 2));
-    const int l = lc + 2, lb = lc + 1, c_ = c0 + lc;
+    const int l = lc + 2, lb = lc + 1;
     const int oi0 = lb * OH + (y0 - r0 + 1);  // omega index of the run's first pixel
     cx<T> Ot[2];  // the run's two values of Ot, read first (one wait for every read)
 #pragma unroll
@@ -1600,35 +1608,68 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
       const h2 qq = ((xl[t] + xr[t]) + (yc[t] + yc[t + 2])) + ((zc[t + 1] + zl[t]) - two * (xc[t] + yc[t + 1])) -
                     (zl[t + 1] + zc[t]);
       const T qa = T(qq.x), qp = T(qq.y);
-      const T sgn = ((c_ + y) & 1) ? -inv_n : inv_n;
-      const cx<T> O = scale(Ot[t], sgn);
-      const T a2 = norm2(O);
-      const T den = a2 + T(o.eta_h);
+      const T a2 = norm2(Ot[t]);
+      const T den = a2 + eta_n2;
       // the amplitude term where |O| > 0 and the phase term where |O|^2 + eta > 0, as selects
-      const T fa = a2 > T(0) ? T(0.5) * T(o.alpha) * qa * rsqrt_t(a2) : T(0);
-      const T fp = den > T(0) ? T(0.5) * T(o.beta) * qp * rcp_t(den) : T(0);
-      const cx<T> G = scale(O, fa) + scale(mul_i(O), fp);
-      buf[l * PITCH + y] = scale(G, sgn);
+      const T fa = a2 > T(0) ? ka * qa * rsqrt_t(a2) : T(0);
+      const T fp = den > T(0) ? kp * qp * rcp_t(den) : T(0);
+      buf[l * PITCH + y] = scale(Ot[t], fa) + scale(mul_i(Ot[t]), fp);
     }
   };
   // Software pipeline over the chunks, one barrier per stage: stage s runs A(s) (the
   // next chunk's amplitude and phase, into the other array set), B(s - 1) and C(s - 2).
   // A(s) reads O rows r0(s) - 2 .. r0(s) + 65, which C(s - 2) (own rows r0(s) - 128 ..
   // r0(s) - 65) does not touch; A(s) and B(s - 1) use different (|O|, angle(O)) sets,
-  // B(s - 1) and C(s - 2) different sign sets.  The items of the three are spread over
-  // the block as one list, so that no wave idles while another finishes a stage.
+  // B(s - 1) and C(s - 2) different sign sets.  The items of the three are shared out
+  // over the whole block (below), so that no wave idles while another finishes a stage.
+  // The OH / 2 two-row items of B on a line: the KB = OH / 2 - 1 whose rows keep their
+  // stencils on the grid in every chunk (the first chunk's rows from 1, the last one's up
+  // to N - 2) come first, line after line (at the grid's right edge its last two lines
+  // first, as at the left edge); the one item per line that holds the grid's first or last
+  // row (or the chunk's last two rows elsewhere) comes after all of those.  So the items
+  // that check bounds (these and the two lines at the grid's left or right edge) fill
+  // whole runs of 64, and the others run without a check.
+  constexpr int KB = OH / 2 - 1;
+  static_assert(KB == 32 && CH + 2 == OH, "items 0 .. 31 of a line by a shift");
+  const int lrot = c0 + W >= N - 1 ? LB - 2 : 0;
+  auto b_item = [&](int c, int q) {
+    const int core = LB * KB;
+    int lb, k;
+    if (q < core) {
+      lb = q / KB + lrot;
+      lb = lb >= LB ? lb - LB : lb;
+      k = q % KB + (c == 0 ? 1 : 0);
+    } else {
+      lb = q - core;
+      k = c == 0 ? 0 : KB;
+    }
+    const int c_ = cx0 + lb, y0 = c * CH - 1 + 2 * k;
+    if (c_ >= 1 && c_ <= N - 2 && y0 >= 1 && y0 <= N - 3) stage_b(c, lb, 2 * k, std::true_type{});
+    else stage_b(c, lb, 2 * k, std::false_type{});
+  };
+  // A stage's items go out in runs of 64 (one wave each): the runs of B, then of C, then
+  // of A (dearest first), dealt to the 16 waves in a snake order (0 .. 15, 15 .. 0, ...),
+  // so that every wave runs one kind of item at a time (the kind is uniform across the
+  // wave) and the four waves of each SIMD get about the same work.
+  static_assert(NT == 1024, "16 waves");
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int nA = NL * RS, nB = LB * (OH / 2), nC = W * (CH / 2);
   for (int st = 0; st < NCH + 2; ++st) {
     const int ca = st, cb = st - 1, cc = st - 2;
     const int na = ca < NCH ? nA : 0, nb = cb >= 0 && cb < NCH ? nB : 0, nc = cc >= 0 ? nC : 0;
-    const bool inb = strip_in && cb >= 1 && cb * CH + CH <= N - 2;
-    for (int q = tid; q < na + nb + nc; q += NT) {
-      if (q < na) stage_a(ca, q);
-      else if (q < na + nb) {
-        if (inb) stage_b(cb, q - na, std::true_type{});
-        else stage_b(cb, q - na, std::false_type{});
+    const int rb = (nb + 63) >> 6, rc = (nc + 63) >> 6, nrun = rb + rc + ((na + 63) >> 6);
+    for (int r = 0;; ++r) {
+      const int k = r * 16 + ((r & 1) ? 15 - wv : wv);
+      if (k >= nrun) break;
+      if (k < rb) {
+        const int q = k * 64 + lane;
+        if (q < nb) b_item(cb, q);
+      } else if (k < rb + rc) {
+        const int q = (k - rb) * 64 + lane;
+        if (q < nc) stage_c(cc, q);
       } else {
-        stage_c(cc, q - na - nb);
+        const int q = (k - rb - rc) * 64 + lane;
+        if (q < na) stage_a(ca, q);
       }
     }
     if (nb) {
