@@ -1644,7 +1644,9 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
       k = c == 0 ? 0 : KB;
     }
     const int c_ = cx0 + lb, y0 = c * CH - 1 + 2 * k;
-    if (c_ >= 1 && c_ <= N - 2 && y0 >= 1 && y0 <= N - 3) stage_b(c, lb, 2 * k, std::true_type{});
+    // one form for the whole wave (the checked one is right for every item): no wave runs both
+    const bool fast = c_ >= 1 && c_ <= N - 2 && y0 >= 1 && y0 <= N - 3;
+    if (__builtin_amdgcn_ballot_w64(!fast) == 0) stage_b(c, lb, 2 * k, std::true_type{});
     else stage_b(c, lb, 2 * k, std::false_type{});
   };
   // A stage's items go out in runs of 64 (one wave each): the runs of B, then of C, then
