@@ -1501,15 +1501,11 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     StockhamPass<T, N, R2, R1, true, NT, ceil_div(NLM * (N / R2), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
     StockhamPass<T, N, R3, R1 * R2, true, NT, ceil_div(NLM * (N / R3), NT), PITCH, 1>::run(buf, 0, dNL, twl, tid);
   }
-  // (|O|, angle(O)) at line l, row y (zero off the grid); O = (-1)^(x+y) Ot / n, so |O| =
-  // |Ot| / n and angle(O) = atan2 of Ot negated where x + y is odd (a positive scale leaves
-  // atan2's ratio alone; 1 / n is a power of two, so the scaled parts are exact anyway).
-  // CHK: check the row against the grid (lines off the grid hold zeros already)
+  // (|O|, angle(O)) of Ot at column c, row y; O = (-1)^(x+y) Ot / n, so |O| = |Ot| / n and
+  // angle(O) = atan2 of Ot negated where x + y is odd (a positive scale leaves atan2's ratio
+  // alone; 1 / n is a power of two, so the scaled parts are exact anyway)
   static_assert((N & (N - 1)) == 0, "1 / n a power of two");
-  auto amp_phase = [&](int l, int y, auto chk_c) -> cx<T> {
-    if (decltype(chk_c)::value && (y < 0 || y >= N)) return czero<T>();
-    const int c = c0 - 2 + l;
-    const cx<T> Ot = buf[l * PITCH + y];
+  auto amp_phase = [&](cx<T> Ot, int c, int y) -> cx<T> {
     const bool neg = (c + y) & 1;
     return cx<T>{inv_n * sqrt_t(norm2(Ot)), atan2_fast(neg ? -Ot.y : Ot.y, neg ? -Ot.x : Ot.x)};
   };
@@ -1517,10 +1513,20 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   double la = 0.0, lp = 0.0;
   const int cx0 = c0 - 1;   // column of omega line lb = 0
   constexpr int NCH = N / CH;
-  // A(c), item q: (|O|, angle(O)) of line q / RS, chunk row q % RS (y = r0 - 2 + q % RS)
+  // A(c), item q: (|O|, angle(O)) of line l = q / (RS / 2), chunk rows i = q mod RS / 2 and
+  // i + RS / 2 (y = r0 - 2 + i), zero off the grid (lines off it hold zeros already; rows off
+  // it read a clamped row and are cleared by a select): two independent chains per thread,
+  // neighbouring lanes on neighbouring rows
+  static_assert(RS % 2 == 0, "two halves of the chunk rows");
+  constexpr int RH = RS / 2;
   auto stage_a = [&](int c, int q) {
-    const int l = q / RS, i = q % RS;
-    sfb(c)[l * RS + i] = amp_phase(l, c * CH - 2 + i, std::true_type{});
+    const int l = q / RH, i = q % RH;
+    const int y = c * CH - 2 + i, cl = c0 - 2 + l;
+    const cx<T> o0 = buf[l * PITCH + max(y, 0)], o1 = buf[l * PITCH + min(y + RH, N - 1)];
+    const cx<T> v0 = amp_phase(o0, cl, y), v1 = amp_phase(o1, cl, y + RH);
+    cx<T>* dst = sfb(c) + l * RS + i;
+    dst[0] = y >= 0 ? v0 : czero<T>();
+    dst[RH] = y + RH < N ? v1 : czero<T>();
   };
   // B(c) on line lb + 1, rows ib = ib0 and ib0 + 1 (y = r0 - 1 + ib).  IN: every stencil
   // of the two pixels stays on the grid, so that no bound is checked.
@@ -1655,7 +1661,7 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   // wave) and the four waves of each SIMD get about the same work.
   static_assert(NT == 1024, "16 waves");
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int nA = NL * RS, nB = LB * (OH / 2), nC = W * (CH / 2);
+  const int nA = NL * (RS / 2), nB = LB * (OH / 2), nC = W * (CH / 2);
   for (int st = 0; st < NCH + 2; ++st) {
     const int ca = st, cb = st - 1, cc = st - 2;
     const int na = ca < NCH ? nA : 0, nb = cb >= 0 && cb < NCH ? nB : 0, nc = cc >= 0 ? nC : 0;
