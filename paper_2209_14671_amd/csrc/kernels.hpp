@@ -1196,7 +1196,7 @@ constexpr size_t obj_wide_form_bytes() {
   if constexpr (SIGN) {
     constexpr size_t chunk = 2 * (2 * sizeof(T) * Sh::NLM * Sh::RS + 3 * sizeof(unsigned) * Sh::OWM * Sh::OH);
     constexpr size_t sums = sizeof(double) * (4 * NT);
-    return lines + (chunk > sums ? chunk : sums);
+    return lines + sizeof(cx<T>) + (chunk > sums ? chunk : sums);  // + the 16-byte alignment
   }
   return lines + sizeof(T) * 2 * Sh::NLM * Sh::RS + sizeof(T) * 6 * Sh::OWM * Sh::OH + 8 +
          sizeof(double) * 2 * (NT / 64);
@@ -1461,7 +1461,9 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
   // two sets of chunk arrays (chunks alternate between them): (|O|, angle(O)) at
   // [l * RS + i] for y = r0 - 2 + i, and the three packed sign planes at [lb * OH + ib]
   // for line lb + 1, y = r0 - 1 + ib
-  cx<T>* sf0 = twl + N;
+  // the chunk arrays start 16-byte aligned (the B step reads pairs of rows as 16 bytes)
+  static_assert(sizeof(cx<T>) == 8 && RS % 2 == 0, "16-byte pairs of rows");
+  cx<T>* sf0 = twl + N + ((NLM * PITCH + N) & 1);
   unsigned* om0 = reinterpret_cast<unsigned*>(sf0 + 2 * NLM * RS);
   auto sfb = [&](int c) { return sf0 + (c & 1) * (NLM * RS); };
   auto omb = [&](int c) { return om0 + (c & 1) * (3 * OWM * OH); };
@@ -1541,15 +1543,23 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     const bool cin = c_ >= 0 && c_ < N, cxx = c_ >= 1 && c_ <= N - 2, cxy = c_ <= N - 2;
     const bool own_c = l >= 2 && l <= W + 1;
     // f rows i = ib + 1 (y) and neighbours: line l rows i - 1 .. i + 2, lines l - 1 and
-    // l + 1 as the stencils need
-    const cx<T>* sl = sf + l * RS + ib0 + 1;
-    cx<T> ctr[4], lft[2], rgt[3];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) ctr[t] = sl[t - 1];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) lft[t] = sl[t - RS];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) rgt[t] = sl[t + RS];
+    // l + 1 as the stencils need, read as aligned 16-byte pairs of rows ib0 .. ib0 + 3 (ib0
+    // even), so that neighbouring lanes read neighbouring 16 bytes
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    auto pair = [](const cx<T>* p, cx<T>& a, cx<T>& b) {
+      const f4 v = *reinterpret_cast<const f4*>(p);
+      a = cx<T>{v.x, v.y};
+      b = cx<T>{v.z, v.w};
+    };
+    const cx<T>* sc = sf + l * RS + ib0;
+    cx<T> ctr[4], lq[4], rq[4];
+    pair(sc, ctr[0], ctr[1]);
+    pair(sc + 2, ctr[2], ctr[3]);
+    pair(sc - RS, lq[0], lq[1]);
+    pair(sc - RS + 2, lq[2], lq[3]);
+    pair(sc + RS, rq[0], rq[1]);
+    pair(sc + RS + 2, rq[2], rq[3]);
+    const cx<T> lft[2] = {lq[1], lq[2]}, rgt[3] = {rq[1], rq[2], rq[3]};
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int ib = ib0 + t, y = r0 - 1 + ib;
