@@ -1723,7 +1723,26 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
     StockhamPass<T, N, R1, 1, false, NT, ceil_div(WM * (N / R1), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
     sum_level(64, 16, 0, 2 * NT);  // slots 2 NT .. (the first pass's barriers published lsum)
     StockhamPass<T, N, R2, R1, false, NT, ceil_div(WM * (N / R2), NT), PITCH, 1>::run(own, 0, dW, twl, tid);
-    sum_level(8, 8, 2 * NT, 2 * NT + 64);
+    // the last two levels in wave 0, in registers (no barrier): threads 0 .. 7 each add 8
+    // level-1 slots in order, and thread 0 adds their eight sums in order, read across lanes
+    if (tid < 64) {
+      double s0 = 0.0, s1 = 0.0;
+      if (tid < 8)
+        for (int w = 0; w < 8; ++w) {
+          s0 += lsum[2 * NT + 8 * tid + w];
+          s1 += lsum[3 * NT + 8 * tid + w];
+        }
+      double f0 = s0, f1 = s1;
+#pragma unroll
+      for (int i = 1; i < 8; ++i) {
+        f0 += __shfl(s0, i, 64);
+        f1 += __shfl(s1, i, 64);
+      }
+      if (tid == 0) {
+        o.partial[2 * b + 0] = f0;
+        o.partial[2 * b + 1] = f1;
+      }
+    }
     using PC = StockhamPass<T, N, R3, R1 * R2, false, NT, ceil_div(WM * (N / R3), NT), PITCH, 1>;
     constexpr int MB = ceil_div(WM * (N / R3), NT);
     int m[MB], j[MB];
@@ -1737,16 +1756,6 @@ __device__ void obj_strip_wide_sign(const LedObjArgs& o, int b, char* lds) {
 #pragma unroll
         for (int r = 0; r < R3; ++r) T2[(size_t)PC::out_index(j[i], r) * N + c0 + m[i]] = v[i][r];
       }
-  }
-  __syncthreads();  // the second level
-  if (tid == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < 8; ++w) {
-      s0 += lsum[2 * NT + 64 + w];
-      s1 += lsum[3 * NT + 64 + w];
-    }
-    o.partial[2 * b + 0] = s0;
-    o.partial[2 * b + 1] = s1;
   }
 }
 
