@@ -74,27 +74,40 @@ struct StockhamPass {
     }
   }
 
-  // Read and transform this thread's butterflies.
-  __device__ static __forceinline__ void load(const cx<T>* buf, int m0, const int (&m)[MAXB], const int (&j)[MAXB],
-                                              const bool (&live)[MAXB], const cx<T>* tw, cx<T> (&v)[MAXB][R]) {
+  // Butterfly i of this thread: read, twiddle, transform.
+  __device__ static __forceinline__ void load_one(const cx<T>* buf, int m0, int m, int j, const cx<T>* tw,
+                                                  cx<T> (&v)[R]) {
+    const cx<T>* base = buf + (m0 + m) * TS + j * ES;
+    const int jm = j % NS;
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
-      if (live[i]) {
-        const cx<T>* base = buf + (m0 + m[i]) * TS + j[i] * ES;
-        const int jm = j[i] % NS;
+    for (int r = 0; r < R; ++r) v[r] = base[r * BPT * ES];
+    if (NS > 1) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i][r] = base[r * BPT * ES];
-        if (NS > 1) {
-#pragma unroll
-          for (int r = 1; r < R; ++r) {
-            cx<T> w = TWB ? tw[jm * R + r] : tw[r * jm * (N / (NS * R))];
-            if (INV) w.y = -w.y;
-            v[i][r] = v[i][r] * w;
-          }
-        }
-        dft<T, R, INV>(v[i]);
+      for (int r = 1; r < R; ++r) {
+        cx<T> w = TWB ? tw[jm * R + r] : tw[r * jm * (N / (NS * R))];
+        if (INV) w.y = -w.y;
+        v[r] = v[r] * w;
       }
     }
+    dft<T, R, INV>(v);
+  }
+
+  // Read and transform this thread's butterflies.  With two per thread, a wave whose
+  // lanes hold any second butterfly runs both as one straight sequence (the reads of both
+  // first; a lane without one reads butterfly 0 of transform 0 and drops it at the store),
+  // so that the second does not wait behind the first.
+  __device__ static __forceinline__ void load(const cx<T>* buf, int m0, const int (&m)[MAXB], const int (&j)[MAXB],
+                                              const bool (&live)[MAXB], const cx<T>* tw, cx<T> (&v)[MAXB][R]) {
+    if constexpr (MAXB == 2) {
+      if (__builtin_amdgcn_ballot_w64(live[1]) != 0) {
+        load_one(buf, m0, live[0] ? m[0] : 0, live[0] ? j[0] : 0, tw, v[0]);
+        load_one(buf, m0, live[1] ? m[1] : 0, live[1] ? j[1] : 0, tw, v[1]);
+        return;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i)
+      if (live[i]) load_one(buf, m0, m[i], j[i], tw, v[i]);
   }
 
   __device__ static __forceinline__ void store(cx<T>* buf, int m0, const int (&m)[MAXB], const int (&j)[MAXB],
