@@ -29,6 +29,8 @@ def build(verbose: bool = False) -> str:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
         SRC, "-o", tmp,
+        # roctx ranges over the entry points (a profiler's marker trace)
+        "-L", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"), "-lrocprofiler-sdk-roctx",
     ]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
