@@ -3,8 +3,8 @@
 ELFPIE_F32_MFMA_BF16X3 (split-BF16 DFT-matrix row transforms) from the oracle's initial
 state on the oracle's stack, against 100 FP64 oracle iterations: relative L2 error of the
 object O = F_A Psi and of the pupil P.  The oracle takes about two minutes on one core, so
-the study runs on request (ELFPIE_PRECISION_STUDY=1); it writes its numbers to
-gpurun_out/precision_study.json when that folder exists."""
+the study runs on request (ELFPIE_PRECISION_STUDY=1); it writes its numbers as JSON to the
+file that ELFPIE_PRECISION_STUDY_OUT names, if set."""
 import json
 import os
 
@@ -48,8 +48,8 @@ def test_precision_forms_after_100_iterations():
         print(f"{name}: O {eO:.3e} P {eP:.3e} final loss {eL:.3e}")
         plan.close()
     print(json.dumps(out))
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", "precision_study.json"), "w") as fh:
+    if os.environ.get("ELFPIE_PRECISION_STUDY_OUT"):
+        with open(os.environ["ELFPIE_PRECISION_STUDY_OUT"], "w") as fh:
             json.dump(out, fh, indent=1)
     # both forms follow the FP64 trajectory; the matrix-core form within ten times the plain
     # form's error or 1e-3, whichever is larger
