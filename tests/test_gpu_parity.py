@@ -509,6 +509,31 @@ def test_checked_run_reports_nonfinite_loss():
     plan.run(st, meas, 2, checked=True)  # the flag is cleared by the next run
 
 
+def test_checked_run_of_the_fused_plan():
+    """The same at the benchmark's size, where elfpie_run launches directly and its opening
+    row transforms clear the counters: a NaN in one image gives ELFPIE_E_NONFINITE, the next
+    clean run returns OK, and its history starts at row 0."""
+    e = E()
+    pair = _config2_pair(0.0)
+    plan = make_plan(pair, True)
+    assert plan.stats()["captures"] == 0
+    meas = dev(pair.meas, True)
+    bad = meas.clone()
+    bad[100, 64, 64] = float("nan")
+    st = gpu_state(plan, pair, True)
+    with pytest.raises(e.ElfpieError) as ei:
+        plan.run(st, bad, 2, checked=True)
+    assert ei.value.status == 6  # ELFPIE_E_NONFINITE
+    st = gpu_state(plan, pair, True)
+    h = plan.run(st, meas, 3, checked=True)
+    torch.cuda.synchronize()
+    assert torch.isfinite(h).all()
+    ref = plan.run(gpu_state(plan, pair, True), meas, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(h, ref)
+    assert plan.stats()["captures"] == 0  # direct launches: nothing captured
+
+
 @pytest.mark.parametrize("n_lo,up", [(64, 8), (32, 16)])
 def test_fp64_large_spectrum_matches_oracle(n_lo, up):
     """FP64 plans with n_hi above 256 take the tile-form object branch (line transforms,
