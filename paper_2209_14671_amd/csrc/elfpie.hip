@@ -110,12 +110,12 @@ struct Tables {
   int nobj = 0;
   int nhp = 0;                     // Hessian loss partial pairs written per evaluation
   size_t hess_pairs = 0;           // pairs per Hessian partial buffer (two, by iteration parity)
-  int nseg = 0;                    // 64-column segments per spectrum row
+  int nseg = 0;                    // kUpdSegW-column segments per spectrum row
   int nch = 0, chunk = kPupilChunk;  // pupil reduction chunks
   std::vector<int> win;            // K x 2 (y0, x0)
   std::vector<int> xlo, xhi, rowoff;
   std::vector<int> tile_ptr, tile_led;
-  std::vector<int> seg_ptr, seg_ent;  // (row, segment) -> LED runs, 4 ints per entry
+  std::vector<int> seg_ptr, seg_ent;  // (row, segment) -> LED runs, 2 ints per entry
   size_t elem = 0;                 // bytes of one real in the plan precision
   // workspace offsets
   size_t o_win = 0, o_xlo = 0, o_xhi = 0, o_roff = 0, o_tptr = 0, o_tled = 0, o_twlo = 0, o_twhi = 0;
@@ -278,12 +278,13 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
   tb->nhp = tb->strip ? tb->n_hi / ELFPIE_STRIP_W : ntiles;
   tb->hess_pairs = (size_t)std::max(tb->nhp, ntiles);
 
-  // row-form update lists: per spectrum row and 64-column segment, the runs of the
+  // row-form update lists: per spectrum row and kUpdSegW-column segment, the runs of the
   // LED supports that meet it, in ascending LED order, with the contribution index
   // of each pixel as base + column
   tb->rowupd = kRowUpdate && tb->strip && (long long)tb->K * S < (1LL << 30);
   if (tb->rowupd) {
-    tb->nseg = tb->n_hi / 64;
+    constexpr int W = kUpdSegW;
+    tb->nseg = tb->n_hi / W;
     const int nreg = tb->n_hi * tb->nseg;
     std::vector<std::vector<int>> seg(nreg);
     for (int k = 0; k < tb->K; ++k) {
@@ -292,23 +293,21 @@ elfpie_status build_tables(const elfpie_problem* p, Tables* tb, std::string* err
         if (tb->xlo[dy] > tb->xhi[dy]) continue;
         const int uy = y0 + dy, xa = x0 + tb->xlo[dy], xb = x0 + tb->xhi[dy];
         const int base = k * S + tb->rowoff[dy] - xa;
-        for (int g = xa / 64; g <= xb / 64; ++g) {
+        for (int g = xa / W; g <= xb / W; ++g) {
           std::vector<int>& e = seg[uy * tb->nseg + g];
           e.push_back(base);
-          e.push_back(std::max(xa, g * 64));
-          e.push_back(std::min(xb, g * 64 + 63));
-          e.push_back(k);
+          e.push_back(std::max(xa, g * W) | (std::min(xb, g * W + W - 1) << 16));
         }
       }
     }
     tb->seg_ptr.assign(nreg + 1, 0);
     tb->seg_ent.clear();
     for (int r = 0; r < nreg; ++r) {
-      tb->seg_ptr[r] = (int)(tb->seg_ent.size() / 4);
+      tb->seg_ptr[r] = (int)(tb->seg_ent.size() / 2);
       tb->seg_ent.insert(tb->seg_ent.end(), seg[r].begin(), seg[r].end());
     }
-    tb->seg_ptr[nreg] = (int)(tb->seg_ent.size() / 4);
-    if (tb->seg_ent.empty()) tb->seg_ent.assign(4, 0);
+    tb->seg_ptr[nreg] = (int)(tb->seg_ent.size() / 2);
+    if (tb->seg_ent.empty()) tb->seg_ent.assign(2, 0);
   }
 
   // workspace layout

@@ -2148,8 +2148,8 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 //   the rows of T2 (the Hessian-term gradient after its column transforms) get their
 //   forward row DFT in LDS, which completes gH;
 //   g = gH + the LED contributions covering each pixel, summed in ascending LED order
-//   (the same terms in the same order as k_update) from per-(row, 64-column segment)
-//   lists; a wave's 64 pixels share one segment, so its list reads are scalar;
+//   (the same terms in the same order as k_update) from per-(row, 16-column segment)
+//   lists; a wave's 64 pixels span four segments, one per 16-lane quarter;
 //   step mode applies the plan's rule (Eq. 19) and writes the state, gradient mode
 //   writes g;
 //   with inv, the rows of psi as they leave this launch get their inverse row DFT
@@ -2160,7 +2160,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #define ELFPIE_UPDR_GB 16  // contribution loads in flight per pixel (row form)
 #endif
 #ifndef ELFPIE_UPDR_PF
-#define ELFPIE_UPDR_PF 8  // contribution loads issued before the row transform (one pixel per thread)
+#define ELFPIE_UPDR_PF 10  // contribution loads issued before the row transform (one pixel per thread)
 #endif
 #ifndef ELFPIE_UPDROWS_NT
 #define ELFPIE_UPDROWS_NT 512  // threads per block (at most one per pixel of the block's rows)
@@ -2188,7 +2188,6 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
   constexpr int PPT = RB * N / NT;  // pixels per thread
   static_assert(PPT * NT == RB * N && N % 64 == 0, "whole pixels per thread, whole segments per wave");
   constexpr int GB = ELFPIE_UPDR_GB;
-  using cint = const __attribute__((address_space(4))) int;  // wave-uniform reads go scalar
   __shared__ cx<T> buf[RB * PITCH];
   __shared__ cx<T> twl[N];
   __shared__ double sbc[6];
@@ -2239,39 +2238,57 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
     }
   }
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
-  cint* sp = (cint*)a.seg_ptr;
-  cint* se = (cint*)a.seg_ent;
-  // Each pixel's segment list: lane j of the wave holds entry j (up to 64), fetched with
-  // one vector load per field; the walk reads them back with readlane, so that only the
-  // list bounds are scalar loads on the way to the contribution loads.
+  const int2* se = static_cast<const int2*>(static_cast<const void*>(a.seg_ent));
+  // Each pixel's list is that of its 16-column segment, which is also its 16-lane quarter
+  // of the wave.  Lane j holds entries j & 15 and 16 + (j & 15) of its quarter's list
+  // (one 8-byte load each: contribution base, and the first and last column packed), and
+  // the walk hands entry l of each quarter to the quarter's lanes with ds_bpermute, so the
+  // wave walks the longest of its four lists rather than the union of them.  Entries past
+  // 32 (long lists only) are read by each lane itself.
+  static_assert(kUpdSegW == 16, "one list per 16-lane quarter");
   const int lane = tid & 63;
-  int b0[PPT], nl[PPT], lb[PPT], lxs[PPT], lxe[PPT];
+  const int qaddr = (lane & 48) << 2;  // ds_bpermute byte address of the quarter's lane 0
+  constexpr int kNone = 0xffff;        // packed columns of a missing entry: first 65535, last 0
+  int nw[PPT], lbA[PPT], pkA[PPT], lbB[PPT], pkB[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int p = tid + i * NT;
-    const int seg = __builtin_amdgcn_readfirstlane((r0 + p / N) * a.nseg + (p % N) / 64);
-    b0[i] = sp[seg];
-    nl[i] = sp[seg + 1] - b0[i];
-    const int li = lane < nl[i] ? b0[i] + lane : 0;  // entry 0 exists, also for an empty list
-    lb[i] = a.seg_ent[4 * li];
-    lxs[i] = a.seg_ent[4 * li + 1];
-    lxe[i] = a.seg_ent[4 * li + 2];
+    const int seg = (r0 + p / N) * a.nseg + (p % N) / kUpdSegW;
+    const int b0 = a.seg_ptr[seg], nl = a.seg_ptr[seg + 1] - b0;
+    const int q = lane & 15;
+    const int2 ea = se[q < nl ? b0 + q : 0];  // entry 0 exists, also for an empty list
+    const int2 eb = se[q + 16 < nl ? b0 + q + 16 : 0];
+    lbA[i] = ea.x;
+    pkA[i] = q < nl ? ea.y : kNone;  // a missing entry covers no column
+    lbB[i] = eb.x;
+    pkB[i] = q + 16 < nl ? eb.y : kNone;
+    const int m01 = max(__builtin_amdgcn_readlane(nl, 0), __builtin_amdgcn_readlane(nl, 16));
+    const int m23 = max(__builtin_amdgcn_readlane(nl, 32), __builtin_amdgcn_readlane(nl, 48));
+    nw[i] = __builtin_amdgcn_readfirstlane(max(m01, m23));  // the wave's longest list
   }
+  // entry l (wave-uniform, below 32) of this lane's quarter list: C index base and columns
+  auto held = [&](int i, int l, int& base, int& xs, int& xe) {
+    const int addr = qaddr | ((l & 15) << 2);
+    base = __builtin_amdgcn_ds_bpermute(addr, l < 16 ? lbA[i] : lbB[i]);
+    const int pk = __builtin_amdgcn_ds_bpermute(addr, l < 16 ? pkA[i] : pkB[i]);
+    xs = pk & 0xffff;
+    xe = pk >> 16;
+  };
   // with one pixel per thread, the first PG contribution loads go out before the row
   // transform (the barriers there wait for LDS only), and are added after gH, in the
   // same order as the walk below
   constexpr bool PF = PPT == 1;
   constexpr int PG = PF ? ELFPIE_UPDR_PF : 1;  // loads issued early
-  static_assert(PG <= 64, "early loads come from the entries held in lanes");
+  static_assert(PG <= 16, "early loads come from the first entries held in lanes");
   cx<T> pre[PG];
   if constexpr (PF) {
     const int ux = tid % N;
 #pragma unroll
     for (int j = 0; j < PG; ++j) {
-      const int lu = min(j, max(nl[0] - 1, 0));  // wave-uniform
-      const int xs = __builtin_amdgcn_readlane(lxs[0], lu), xe = __builtin_amdgcn_readlane(lxe[0], lu);
-      const bool ok = j < nl[0] && ux >= xs && ux <= xe;
-      pre[j] = ok ? C[__builtin_amdgcn_readlane(lb[0], lu) + ux] : czero<T>();
+      int base, xs, xe;
+      held(0, j, base, xs, xe);
+      const bool ok = ux >= xs && ux <= xe;
+      pre[j] = ok ? C[base + ux] : czero<T>();
     }
   }
   __syncthreads();
@@ -2283,45 +2300,53 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
     const int ux = p % N;
     cx<T>& slot = buf[(p / N) * PITCH + ux];
     cx<T> g = slot;
-    int lstart = 0;
     if constexpr (PF) {
 #pragma unroll
       for (int j = 0; j < PG; ++j) g = g + pre[j];
-      lstart = PG;
     }
-    const int nh = min(nl[i], 64);  // entries held in lanes
-    for (int l0 = lstart; l0 < nh; l0 += GB) {
+    // the held entries in rounds of GB loads whose entry numbers are compile-time
+    // constants (so the hand-over needs no address arithmetic); a missing entry covers
+    // no column, and the rounds past the wave's longest list are skipped
+    constexpr int LS = PF ? PG : 0;
+#pragma unroll
+    for (int l0 = LS; l0 < 32; l0 += GB) {
+      if (nw[i] <= l0) break;  // wave-uniform
       int idx[GB];
       bool ok[GB];
 #pragma unroll
       for (int j = 0; j < GB; ++j) {
-        const int lu = min(l0 + j, nh - 1);  // wave-uniform
-        const int xs = __builtin_amdgcn_readlane(lxs[i], lu), xe = __builtin_amdgcn_readlane(lxe[i], lu);
-        ok[j] = l0 + j < nh && ux >= xs && ux <= xe;
-        idx[j] = __builtin_amdgcn_readlane(lb[i], lu) + ux;
+        if (l0 + j >= 32) break;
+        int base, xs, xe;
+        held(i, l0 + j, base, xs, xe);
+        ok[j] = ux >= xs && ux <= xe;
+        idx[j] = base + ux;
       }
       cx<T> cv[GB];
 #pragma unroll
-      for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
+      for (int j = 0; j < GB; ++j) cv[j] = l0 + j < 32 && ok[j] ? C[idx[j]] : czero<T>();
 #pragma unroll
       for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
     }
-    // entries past the 64 held in lanes (long lists only), through scalar loads
-    const int b1 = b0[i] + nl[i];
-    for (int l0 = b0[i] + 64; l0 < b1; l0 += GB) {
-      int idx[GB];
-      bool ok[GB];
+    // entries past the 32 held in lanes (long lists only), read by each lane
+    if (nw[i] > 32) {
+      const int seg = (r0 + p / N) * a.nseg + ux / kUpdSegW;
+      const int b0 = a.seg_ptr[seg], nl = a.seg_ptr[seg + 1] - b0;
+      for (int l0 = 32; l0 < nw[i]; l0 += GB) {
+        int idx[GB];
+        bool ok[GB];
 #pragma unroll
-      for (int j = 0; j < GB; ++j) {
-        const int l = min(l0 + j, b1 - 1);  // wave-uniform list entry
-        ok[j] = l0 + j < b1 && ux >= se[4 * l + 1] && ux <= se[4 * l + 2];
-        idx[j] = se[4 * l] + ux;
+        for (int j = 0; j < GB; ++j) {
+          const int l = l0 + j;
+          const int2 e = se[l < nl ? b0 + l : 0];
+          ok[j] = l < nl && ux >= (e.y & 0xffff) && ux <= (e.y >> 16);
+          idx[j] = e.x + ux;
+        }
+        cx<T> cv[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
+#pragma unroll
+        for (int j = 0; j < GB; ++j) g = g + cv[j];
       }
-      cx<T> cv[GB];
-#pragma unroll
-      for (int j = 0; j < GB; ++j) cv[j] = ok[j] ? C[idx[j]] : czero<T>();
-#pragma unroll
-      for (int j = 0; j < GB; ++j) g = g + cv[j];
     }
     const size_t u = (size_t)r0 * N + p;
     if (step) {

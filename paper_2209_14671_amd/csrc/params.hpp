@@ -5,6 +5,10 @@
 
 namespace elfpie {
 
+// Width of the column segments of the row-form update's contribution lists: a wave's 64
+// pixels of one row span four of them, one per 16-lane quarter.
+constexpr int kUpdSegW = 16;
+
 enum LedMode : int {
   LED_GRAD = 1,     // residual, W and the back-projected contributions C, D
   LED_FIELDS = 2,   // write the complex low-resolution fields
@@ -98,10 +102,11 @@ struct UpdArgs {
   // the row form (k_update_rows): whole rows per block, row transforms folded in
   const void* tw;       // n_hi forward twiddles
   void* T1;             // out (inv): unnormalised inverse row DFT of psi after this call
-  const int* seg_ptr;   // CSR over (row, 64-column segment) of the spectrum
-  const int* seg_ent;   // entries of 4 ints: C index base (index = base + column), first
-                        // column, last column, unused; ascending LED order per segment
-  int nseg;             // segments per row (n_hi / 64)
+  const int* seg_ptr;   // CSR over (row, kUpdSegW-column segment) of the spectrum
+  const int* seg_ent;   // entries of 2 ints (8-byte aligned): C index base (index = base +
+                        // column), first column | last column << 16; ascending LED order per
+                        // segment
+  int nseg;             // segments per row (n_hi / kUpdSegW)
   int inv;              // 1: write T1
 };
 
