@@ -2219,24 +2219,30 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
   if (step && tid == 0) bias_corrections(a.lg1, a.lg2, double(*a.t), sbc);
   const cx<T>* Hc = static_cast<const cx<T>*>(a.gH) + (size_t)r0 * N;
-  cx<T> x[PPT], mu[PPT];
-  double v[PPT];
-  T d[PPT];
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
     const int p = tid + i * NT;
     buf[(p / N) * PITCH + p % N] = Hc[p];
-    const size_t u = (size_t)r0 * N + p;
-    x[i] = keep_x ? static_cast<const cx<T>*>(a.x)[u] : czero<T>();
-    mu[i] = czero<T>();
-    v[i] = 0.0;
-    d[i] = T(0);
-    if (step) {
-      mu[i] = static_cast<const cx<T>*>(a.mu)[u];
-      v[i] = a.v[u];
-      d[i] = static_cast<const T*>(a.delta)[u];
-    }
   }
+  cx<T> x[PPT], mu[PPT];
+  double v[PPT];
+  T d[PPT];
+  // the parameter and optimiser state of this thread's pixels, needed only at Eq. 19
+  auto load_state = [&]() {
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const size_t u = (size_t)r0 * N + tid + i * NT;
+      x[i] = keep_x ? static_cast<const cx<T>*>(a.x)[u] : czero<T>();
+      mu[i] = czero<T>();
+      v[i] = 0.0;
+      d[i] = T(0);
+      if (step) {
+        mu[i] = static_cast<const cx<T>*>(a.mu)[u];
+        v[i] = a.v[u];
+        d[i] = static_cast<const T*>(a.delta)[u];
+      }
+    }
+  };
   const cx<T>* C = static_cast<const cx<T>*>(a.C);
   const int2* se = static_cast<const int2*>(static_cast<const void*>(a.seg_ent));
   // Each pixel's list is that of its 16-column segment, which is also its 16-lane quarter
@@ -2283,14 +2289,24 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
   cx<T> pre[PG];
   if constexpr (PF) {
     const int ux = tid % N;
+    // all hand-overs first, then all loads (one wait on the LDS counter between them)
+    int pidx[PG];
+    bool pok[PG];
 #pragma unroll
     for (int j = 0; j < PG; ++j) {
       int base, xs, xe;
       held(0, j, base, xs, xe);
-      const bool ok = ux >= xs && ux <= xe;
-      pre[j] = ok ? C[base + ux] : czero<T>();
+      pok[j] = ux >= xs && ux <= xe;
+      pidx[j] = base + ux;
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < PG; ++j) pre[j] = pok[j] ? C[pidx[j]] : czero<T>();
   }
+  // Loads return in issue order, so state loads issued before the list entries would hold
+  // up the early contribution loads; issued here, they are in flight during the row DFT.
+  __builtin_amdgcn_sched_barrier(0);
+  load_state();
   __syncthreads();
   fft_lines_inplace<T, N, false, NT, RB>(buf, twl, tid);  // gH; ends with a barrier
 
@@ -2300,14 +2316,14 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
     const int ux = p % N;
     cx<T>& slot = buf[(p / N) * PITCH + ux];
     cx<T> g = slot;
-    if constexpr (PF) {
-#pragma unroll
-      for (int j = 0; j < PG; ++j) g = g + pre[j];
-    }
     // the held entries in rounds of GB loads whose entry numbers are compile-time
     // constants (so the hand-over needs no address arithmetic); a missing entry covers
     // no column, and the rounds past the wave's longest list are skipped
     constexpr int LS = PF ? PG : 0;
+    if constexpr (PF) {
+#pragma unroll
+      for (int j = 0; j < PG; ++j) g = g + pre[j];
+    }
 #pragma unroll
     for (int l0 = LS; l0 < 32; l0 += GB) {
       if (nw[i] <= l0) break;  // wave-uniform
