@@ -2171,6 +2171,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #ifndef ELFPIE_UPDR_MINW
 #define ELFPIE_UPDR_MINW 6
 #endif
+
 template <int N> struct UpdRows {
   static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
   static constexpr int NT0 = ELFPIE_UPDROWS_NT < RB * N ? ELFPIE_UPDROWS_NT : RB * N;
@@ -2303,10 +2304,12 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
 #pragma unroll
     for (int j = 0; j < PG; ++j) pre[j] = pok[j] ? C[pidx[j]] : czero<T>();
   }
-  // Loads return in issue order, so state loads issued before the list entries would hold
-  // up the early contribution loads; issued here, they are in flight during the row DFT.
+  // Loads return in issue order: state loads issued before the list entries would hold up
+  // the early contribution loads, and issued before the row DFT they would hold up the walk
+  // after it.  In step mode they go out with the walk's first round (or after the row DFT
+  // where there is none); in gradient mode (psi alone, for T1) before the row DFT.
   __builtin_amdgcn_sched_barrier(0);
-  load_state();
+  if (!step) load_state();
   __syncthreads();
   fft_lines_inplace<T, N, false, NT, RB>(buf, twl, tid);  // gH; ends with a barrier
 
@@ -2340,9 +2343,14 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
       cx<T> cv[GB];
 #pragma unroll
       for (int j = 0; j < GB; ++j) cv[j] = l0 + j < 32 && ok[j] ? C[idx[j]] : czero<T>();
+      if (step && i == 0 && l0 == LS) {
+        __builtin_amdgcn_sched_barrier(0);
+        load_state();
+      }
 #pragma unroll
       for (int j = 0; j < GB; ++j) g = g + cv[j];  // adding zero leaves g unchanged
     }
+    if (step && i == 0 && nw[0] <= LS) load_state();
     // entries past the 32 held in lanes (long lists only), read by each lane
     if (nw[i] > 32) {
       const int seg = (r0 + p / N) * a.nseg + ux / kUpdSegW;
