@@ -2171,6 +2171,9 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #ifndef ELFPIE_UPDR_MINW
 #define ELFPIE_UPDR_MINW 6
 #endif
+#ifndef ELFPIE_PUP_RUN
+#define ELFPIE_PUP_RUN 8  // neighbouring pupil support groups per XCD run
+#endif
 
 template <int N> struct UpdRows {
   static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
@@ -2203,7 +2206,13 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
   const int pfirst = pa.final_in_launch ? a.pupil_blocks : 0;
   if (pa.final_in_launch && (int)blockIdx.x < pfirst) {
     static_assert(RB * PITCH >= NT, "the group sums fit the row buffer");
-    pupil_block_final<T, NT>(pa, blockIdx.x, tid, sbc, buf);
+    // runs of R neighbouring support groups per XCD: a group's D reads (32 pixels of every
+    // LED) share their first and last cache lines with its neighbours', and within an XCD
+    // those lines are fetched once; the runs are dealt to the XCDs in turn
+    constexpr int R = ELFPIE_PUP_RUN;
+    int vb = blockIdx.x;
+    if (R > 1 && pfirst % (8 * R) == 0) vb = (vb / (8 * R)) * 8 * R + (vb % 8) * R + (vb / 8) % R;
+    pupil_block_final<T, NT>(pa, vb, tid, sbc, buf);
     return;
   }
   if (!pa.final_in_launch && (int)blockIdx.x >= N / RB) {
