@@ -173,7 +173,7 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #define ELFPIE_STRIP_XCD 1
 #endif
 #ifndef ELFPIE_UPD_PAIR
-#define ELFPIE_UPD_PAIR 2  // neighbouring update rows per XCD run
+#define ELFPIE_UPD_PAIR 16  // neighbouring update rows per XCD run (at most)
 #endif
 // Workgroup b of a launch of n runs on XCD b mod 8.  Renumbering b so that each XCD takes
 // a run of consecutive LEDs (neighbours in the LED grid, whose spectrum windows overlap)
@@ -2175,6 +2175,13 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs a, PupilArgs pa) {
 #define ELFPIE_PUP_RUN 8  // neighbouring pupil support groups per XCD run
 #endif
 
+// the longest run of neighbouring row blocks per XCD, up to g (a power of two), that deals
+// the nr row blocks to the 8 XCDs in whole runs (1: plain round-robin)
+constexpr int upd_row_run(int nr, int g) {
+  while (g > 1 && nr % (8 * g) != 0) g /= 2;
+  return g;
+}
+
 template <int N> struct UpdRows {
   static constexpr int RB = (N == 128 || N == 384) ? 2 : ELFPIE_UPDROWS_RB;
   static constexpr int NT0 = ELFPIE_UPDROWS_NT < RB * N ? ELFPIE_UPDROWS_NT : RB * N;
@@ -2220,10 +2227,11 @@ __global__ __launch_bounds__(UpdRows<N>::NT, sizeof(T) == 4 ? UpdRows<N>::MINW :
     return;
   }
   // runs of G neighbouring rows per XCD (their contribution segments meet in cache lines
-  // of C), the runs still spread over the XCDs in turn
-  constexpr int G = ELFPIE_UPD_PAIR;
+  // of C), the runs still spread over the XCDs in turn; G is the longest run up to
+  // ELFPIE_UPD_PAIR that divides the rows evenly
+  constexpr int G = upd_row_run(N / RB, ELFPIE_UPD_PAIR);
   int rb = blockIdx.x - pfirst;
-  if (G > 1 && (N / RB) % (8 * G) == 0) rb = (rb / (8 * G)) * 8 * G + (rb % 8) * G + (rb / 8) % G;
+  if (G > 1) rb = (rb / (8 * G)) * 8 * G + (rb % 8) * G + (rb / 8) % G;
   const int r0 = rb * RB;
   const bool step = a.step != 0, keep_x = step || a.inv;
   for (int i = tid; i < N; i += NT) twl[i] = static_cast<const cx<T>*>(a.tw)[i];
