@@ -169,6 +169,9 @@ __device__ __forceinline__ void led_bump_step(const LedArgs& a, int k, int tid) 
 #ifndef ELFPIE_STRIP_TSUM
 #define ELFPIE_STRIP_TSUM 1
 #endif
+#ifndef ELFPIE_OBJ_XCD
+#define ELFPIE_OBJ_XCD 1  // object blocks of the per-LED launch: neighbouring strips per XCD
+#endif
 #ifndef ELFPIE_STRIP_XCD
 #define ELFPIE_STRIP_XCD 1
 #endif
@@ -236,7 +239,11 @@ __global__ __launch_bounds__(LedShape<N>::NT) void k_led(LedArgs a) {
     static_assert(obj_wide_lds_bytes<T, NOBJ, NT>() <= sizeof(img), "object blocks fit the tile's LDS");
     nled -= a.obj.nblk;
     if ((int)blockIdx.x >= nled) {  // block-uniform: an object block
-      obj_strip_wide<T, NOBJ, NT>(a.obj, blockIdx.x - nled, reinterpret_cast<char*>(img));
+      // runs of neighbouring strips per XCD: they share the halo columns of T1 and the
+      // cache lines of T2 at their edges, which each XCD then fetches and writes back once
+      const int bo = blockIdx.x - nled;
+      const int sb = ELFPIE_OBJ_XCD ? xcd_order(bo, a.obj.nblk) : bo;
+      obj_strip_wide<T, NOBJ, NT>(a.obj, sb, reinterpret_cast<char*>(img));
       return;
     }
   }
